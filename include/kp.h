@@ -1,0 +1,150 @@
+/*
+ * kp.h -- C ABI of the MI355X (gfx950) filtered K-means library (libkp.so).
+ *
+ * The library runs the K-means iteration of KPynq (Wang et al., "KPynq: A
+ * Work-Efficient Triangle-Inequality based K-means on FPGA"): a point-level
+ * filter, then a group-level filter, then a distance calculator for the
+ * (point, centroid group) pairs that survive, then the centroid update
+ * (Section 1 names the filters and the distance calculator; the Abstract
+ * states that the result is that of standard K-means).  Every stage is a HIP
+ * kernel for gfx950; the host code here only plans memory, groups the
+ * centroids once at kp_init and launches work on a stream.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named *_dev are device pointers (HBM of the ctx's GPU).  Host
+ *    pointers are named *_host.  No call keeps a host pointer.
+ *  - The caller owns every buffer: the points, the workspace and all
+ *    outputs.  The library never allocates device memory; all of its state
+ *    lives in the caller's workspace (kp_workspace_bytes).  It allocates
+ *    small host-side bookkeeping only in kp_init.
+ *  - Matrices are row-major FP32 with no padding: point i of problem p is
+ *    points_dev[i*d .. i*d+d-1].
+ *  - Centroid indices at the boundary are the caller's original indices
+ *    0..k-1; ties between equally near centroids go to the lowest index.
+ *  - Every call returns a kp_status.  KP_ERR_INVALID (bad argument) leaves
+ *    the ctx unchanged.  KP_ERR_HIP (a HIP runtime failure) poisons the ctx:
+ *    every later call except kp_destroy returns KP_ERR_STATE.
+ *    kp_last_error() gives a detail string for the calling thread.
+ *  - A ctx is bound to one device and one stream and is not thread-safe.
+ *    Work is ordered after everything already queued on that stream and
+ *    everything later queued on it runs after it.
+ */
+#ifndef KP_H
+#define KP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kp_ctx kp_ctx;   /* opaque */
+
+typedef enum {
+    KP_OK = 0,
+    KP_ERR_INVALID = 1,      /* bad size, NULL, short or misaligned workspace */
+    KP_ERR_NOMEM = 2,        /* host allocation failed */
+    KP_ERR_HIP = 3,          /* HIP runtime error; the ctx is poisoned */
+    KP_ERR_STATE = 4,        /* call on a poisoned ctx, or out of order */
+    KP_ERR_UNSUPPORTED = 5   /* valid request outside what this build supports */
+} kp_status;
+
+typedef enum {
+    /* Distances in FP32, direct form sum (x_i - c_i)^2 on the vector ALUs. */
+    KP_PREC_FP32 = 0,
+    /* Distances as ||x||^2 - 2 x.c + ||c||^2 with x and c rounded to BF16 on
+     * MFMA (FP32 accumulation); every point whose decision is not certain
+     * under the derived error bound is re-checked in FP32 direct form.
+     * Centroid sums, means and drifts are FP64 in both modes. */
+    KP_PREC_BF16_RECHECK = 1
+} kp_precision;
+
+/* One K-means problem. */
+typedef struct {
+    int64_t n;                     /* points, 1 <= k <= n < 2^31 */
+    int32_t d;                     /* dimensions, 1 <= d <= 1024 (FP32 mode: d <= 128) */
+    int32_t k;                     /* centroids, 1 <= k <= 65536 */
+    int32_t g;                     /* centroid groups, 1 <= g <= k */
+    int32_t precision;             /* kp_precision */
+    const float *points_dev;       /* n*d FP32; BORROWED: must stay valid and
+                                      unchanged until kp_destroy */
+    const float *init_centroids_dev; /* k*d FP32; copied during kp_init */
+    uint64_t seed;                 /* seeds the grouping of the centroids */
+} kp_problem;
+
+/* Launch tuning.  Pass NULL for the built-in defaults.  A zero field means
+ * "default" for that field. */
+typedef struct {
+    int32_t waves_per_block;       /* 1..4 waves of 64 lanes per workgroup */
+    int32_t blocks_per_cu;         /* grid = 256 CUs * this (grid-stride loops) */
+    int32_t age_limit;             /* iterations a point may go without a
+                                      refresh of its bounds: 2..32 (default 32) */
+    int32_t use_graph;             /* 1 (default): replay iterations from a
+                                      captured hipGraph; -1: plain launches */
+} kp_tuning;
+
+/* Per-iteration counters of one problem (kp_stats). */
+typedef struct {
+    int32_t iter;                  /* 1-based iteration number */
+    int32_t dense;                 /* 1 if this iteration computed all distances */
+    int64_t point_filter_fail;     /* points whose upper bound reached the point-level lower bound */
+    int64_t pairs;                 /* (point, group) pairs that survived the group-level filter */
+    int64_t distances;             /* point-centroid distances computed (padding excluded) */
+    int64_t rechecks;              /* points re-decided in FP32 direct form */
+    int64_t moved;                 /* points whose assignment changed */
+} kp_iter_stats;
+
+/* Bytes of device workspace kp_init needs for these problems; 0 if the
+ * description is invalid (kp_last_error says why). */
+size_t kp_workspace_bytes(const kp_problem *problems_host, int32_t count, const kp_tuning *tuning_host);
+
+/* Validate the problems, carve the workspace, group each problem's
+ * centroids (host, once) and queue the per-point preparation on `stream`
+ * (a hipStream_t; NULL = the default stream).  Synchronises the stream.
+ * workspace_dev must be 256-byte aligned and hold kp_workspace_bytes().
+ * On success *out receives a new ctx. */
+kp_status kp_init(kp_ctx **out, const kp_problem *problems_host, int32_t count,
+                  void *workspace_dev, size_t workspace_bytes, void *stream,
+                  const kp_tuning *tuning_host);
+
+/* Queue `iters` K-means iterations (assignment step + centroid update) of
+ * every problem on the ctx stream; returns without waiting.  The first
+ * iteration of a ctx computes every distance; later ones are filtered.
+ * iters must be >= 1. */
+kp_status kp_iterate(kp_ctx *ctx, int32_t iters);
+
+/* Queue a copy of problem `problem`'s current assignment (n int32, original
+ * centroid indices) to labels_dev.  KP_ERR_STATE before the first iteration. */
+kp_status kp_assign(kp_ctx *ctx, int32_t problem, int32_t *labels_dev);
+
+/* Queue a copy of problem `problem`'s current centroids (k*d, original order)
+ * as FP32 (the values distances use) and/or FP64 (the exact means); either
+ * pointer may be NULL. */
+kp_status kp_centroids(kp_ctx *ctx, int32_t problem, float *c32_dev, double *c64_dev);
+
+/* Synchronise the ctx stream and copy up to `cap` per-iteration records of
+ * problem `problem` (oldest first) to stats_host; *n_host receives the count
+ * written.  At most the last 1024 iterations are kept. */
+kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *stats_host, int32_t cap, int32_t *n_host);
+
+/* Number of iterations completed on the ctx (host-side count of queued
+ * iterations).  Returns -1 for NULL. */
+int32_t kp_iterations(const kp_ctx *ctx);
+
+/* Synchronise and release the ctx's host resources, stream and graph.  The
+ * workspace and points are the caller's to free afterwards.  NULL is a
+ * no-op. */
+kp_status kp_destroy(kp_ctx *ctx);
+
+/* Static description of a status code. */
+const char *kp_strerror(kp_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *kp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KP_H */

@@ -1,0 +1,151 @@
+// Grouping of the initial centroids (host, once per kp_init).
+//
+// The group-level filter keeps one lower bound per (point, group of
+// centroids) (paper, Section 1: "Group-level Filter").  The paper does not
+// say how groups are formed; here they are the clusters of a small FP64
+// K-means over the k initial centroids: k-means++ seeding from the problem's
+// seed, five Lloyd iterations, and every empty group filled with the member
+// of the largest group that lies farthest from that group's center.  The
+// grouping only changes how much work the filter saves, never the result.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <limits>
+#include <vector>
+
+#include "grouping.h"
+
+namespace kp {
+
+namespace {
+
+struct SplitMix {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }
+};
+
+double sq(const float *a, const double *b, int d)
+{
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double t = (double)a[i] - b[i];
+        s += t * t;
+    }
+    return s;
+}
+
+}  // namespace
+
+Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed)
+{
+    std::vector<int> lab(k, 0);
+    if (g >= k) {
+        for (int j = 0; j < k; ++j) lab[j] = j;
+        g = k;
+    } else if (g > 1) {
+        SplitMix rng{seed ^ 0x6B70796E71ull};
+        std::vector<double> ctr((size_t)g * d);
+        std::vector<double> best(k, std::numeric_limits<double>::infinity());
+        int first = (int)(rng.next() % (uint64_t)k);
+        for (int i = 0; i < d; ++i) ctr[i] = C[(size_t)first * d + i];
+        for (int q = 1; q < g; ++q) {
+            double tot = 0.0;
+            for (int j = 0; j < k; ++j) {
+                best[j] = std::min(best[j], sq(C + (size_t)j * d, &ctr[(size_t)(q - 1) * d], d));
+                tot += best[j];
+            }
+            int pick = (int)(rng.next() % (uint64_t)k);
+            if (tot > 0.0) {
+                double u = rng.uniform() * tot, acc = 0.0;
+                for (int j = 0; j < k; ++j) {
+                    acc += best[j];
+                    if (acc > u) {
+                        pick = j;
+                        break;
+                    }
+                }
+            }
+            for (int i = 0; i < d; ++i) ctr[(size_t)q * d + i] = C[(size_t)pick * d + i];
+        }
+        std::vector<int> cnt(g);
+        for (int it = 0; it < 5; ++it) {
+            for (int j = 0; j < k; ++j) {
+                double bv = std::numeric_limits<double>::infinity();
+                int bq = 0;
+                for (int q = 0; q < g; ++q) {
+                    double v = sq(C + (size_t)j * d, &ctr[(size_t)q * d], d);
+                    if (v < bv) {
+                        bv = v;
+                        bq = q;
+                    }
+                }
+                lab[j] = bq;
+            }
+            std::fill(ctr.begin(), ctr.end(), 0.0);
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int j = 0; j < k; ++j) {
+                cnt[lab[j]]++;
+                for (int i = 0; i < d; ++i) ctr[(size_t)lab[j] * d + i] += C[(size_t)j * d + i];
+            }
+            for (int q = 0; q < g; ++q)
+                if (cnt[q])
+                    for (int i = 0; i < d; ++i) ctr[(size_t)q * d + i] /= cnt[q];
+        }
+        // fill empty groups
+        for (;;) {
+            int empty = -1, big = 0;
+            for (int q = 0; q < g; ++q) {
+                if (cnt[q] == 0 && empty < 0) empty = q;
+                if (cnt[q] > cnt[big]) big = q;
+            }
+            if (empty < 0) break;
+            int far = -1;
+            double fv = -1.0;
+            for (int j = 0; j < k; ++j) {
+                if (lab[j] != big) continue;
+                double v = sq(C + (size_t)j * d, &ctr[(size_t)big * d], d);
+                if (v > fv) {
+                    fv = v;
+                    far = j;
+                }
+            }
+            lab[far] = empty;
+            cnt[big]--;
+            cnt[empty] = 1;
+            for (int i = 0; i < d; ++i) ctr[(size_t)empty * d + i] = C[(size_t)far * d + i];
+        }
+    }
+    Grouping out;
+    out.g = g;
+    out.gsize.assign(g, 0);
+    for (int j = 0; j < k; ++j) out.gsize[lab[j]]++;
+    out.gstart.assign(g + 1, 0);
+    int run = 0;
+    out.maxgs = 0;
+    for (int q = 0; q < g; ++q) {
+        out.gstart[q] = run;
+        run += (out.gsize[q] + CHUNK_SLOTS - 1) / CHUNK_SLOTS * CHUNK_SLOTS;
+        out.maxgs = std::max(out.maxgs, out.gsize[q]);
+    }
+    out.gstart[g] = run;
+    out.kg = run;
+    out.perm.assign(run, -1);
+    out.slot_group.assign(run, -1);
+    std::vector<int> fill(g, 0);
+    for (int j = 0; j < k; ++j) {   // ascending original index within a group
+        int q = lab[j];
+        int s = out.gstart[q] + fill[q]++;
+        out.perm[s] = j;
+        out.slot_group[s] = q;
+    }
+    return out;
+}
+
+}  // namespace kp

@@ -1,0 +1,500 @@
+// C ABI of libkp (declared in include/kp.h): argument checks, workspace
+// planning, the one-time grouping of centroids, and the ordering of the
+// per-iteration kernels on a stream (optionally replayed from a hipGraph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kp.h"
+#include "grouping.h"
+#include "kp_device.h"
+#include "kp_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Byte offsets of one problem's arrays inside the workspace.
+struct Plan {
+    size_t Xb, xn, xr, st, lb, c32, cb, cn, cr, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
+    size_t Sc, Sg, Sd, L1, L3, mvp, mvo, mvn, srtp, srtk, hist, cursor, ctr, stats, iter, scal;
+    size_t bytes;
+    int kgmax, ldc, ldb, gs;
+};
+
+Plan plan_problem(const kp_problem &p, int W)
+{
+    Plan o;
+    const size_t n = (size_t)p.n;
+    const int d = p.d, g = p.g;
+    const bool bf = p.precision == KP_PREC_BF16_RECHECK;
+    o.kgmax = p.k + (kp::CHUNK_SLOTS - 1) * g;
+    o.ldc = (d + 3) / 4 * 4;
+    o.ldb = (d + 31) / 32 * 32;
+    o.gs = (g + 3) / 4 * 4;
+    const size_t kgm = (size_t)o.kgmax;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = off;
+        off += up(bytes ? bytes : 1, ALIGN);
+        return r;
+    };
+    o.Xb = take(bf ? n * o.ldb * 2 : 0);
+    o.xn = take(bf ? n * 4 : 0);
+    o.xr = take(bf ? n * 4 : 0);
+    o.st = take(n * sizeof(kp::PointState));
+    o.lb = take(n * (size_t)o.gs * 4);
+    o.c32 = take(kgm * o.ldc * 4);
+    o.cb = take(bf ? kgm * o.ldb * 2 : 0);
+    o.cn = take(kgm * 4);
+    o.cr = take(kgm * 4);
+    o.c64 = take(kgm * d * 8);
+    o.sums = take(kgm * d * 8);
+    o.delta = take(kgm * 8);
+    o.cnt = take(kgm * 4);
+    o.perm = take(kgm * 4);
+    o.sgrp = take(kgm * 4);
+    o.gstart = take((size_t)(g + 1) * 4);
+    o.gsize = take((size_t)g * 4);
+    o.Sc = take((size_t)W * kgm * 8);
+    o.Sg = take((size_t)W * g * 8);
+    o.Sd = take((size_t)W * 8);
+    o.L1 = take(n * 4);
+    o.L3 = take(bf ? n * 16 : 0);
+    o.mvp = take(n * 4);
+    o.mvo = take(n * 4);
+    o.mvn = take(n * 4);
+    o.srtp = take(2 * n * 4);
+    o.srtk = take(2 * n * 4);
+    o.hist = take((kgm + 1) * 4);
+    o.cursor = take((kgm + 1) * 4);
+    o.ctr = take(kp::NCTR * 8);
+    o.stats = take((size_t)kp::STATS_CAP * 8 * 8);
+    o.iter = take(4);
+    o.scal = take(16);
+    o.bytes = off;
+    return o;
+}
+
+int tuning_W(const kp_tuning *t) { return (t && t->age_limit) ? t->age_limit : 32; }
+
+bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
+{
+    if (!ps) {
+        set_error("problems is NULL");
+        return false;
+    }
+    if (count < 1 || count > 4096) {
+        set_error("count=%d outside 1..4096", count);
+        return false;
+    }
+    if (t) {
+        if (t->waves_per_block < 0 || t->waves_per_block > 4) {
+            set_error("waves_per_block=%d outside 0..4", t->waves_per_block);
+            return false;
+        }
+        if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) {
+            set_error("blocks_per_cu=%d outside 0..64", t->blocks_per_cu);
+            return false;
+        }
+        if (t->age_limit != 0 && (t->age_limit < 2 || t->age_limit > 32)) {
+            set_error("age_limit=%d outside 2..32", t->age_limit);
+            return false;
+        }
+        if (t->use_graph < -1 || t->use_graph > 1) {
+            set_error("use_graph=%d outside -1..1", t->use_graph);
+            return false;
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        const kp_problem &p = ps[i];
+        if (p.n < 1 || p.n > 0x7FFFFFFFll) {
+            set_error("problem %d: n=%lld outside 1..2^31-1", i, (long long)p.n);
+            return false;
+        }
+        if (p.d < 1 || p.d > 1024) {
+            set_error("problem %d: d=%d outside 1..1024", i, p.d);
+            return false;
+        }
+        if (p.k < 1 || p.k > 65536 || (int64_t)p.k > p.n) {
+            set_error("problem %d: k=%d must satisfy 1 <= k <= min(n, 65536)", i, p.k);
+            return false;
+        }
+        if (p.g < 1 || p.g > p.k) {
+            set_error("problem %d: g=%d must satisfy 1 <= g <= k", i, p.g);
+            return false;
+        }
+        if (p.precision != KP_PREC_FP32 && p.precision != KP_PREC_BF16_RECHECK) {
+            set_error("problem %d: unknown precision %d", i, p.precision);
+            return false;
+        }
+        if (!p.points_dev || !p.init_centroids_dev) {
+            set_error("problem %d: NULL points or initial centroids", i);
+            return false;
+        }
+        if (((uintptr_t)p.points_dev & 15u) != 0) {
+            set_error("problem %d: points_dev must be 16-byte aligned", i);
+            return false;
+        }
+    }
+    return true;
+}
+
+bool supported(const kp_problem *ps, int32_t count)
+{
+    for (int i = 0; i < count; ++i) {
+        const kp_problem &p = ps[i];
+        if (p.precision == KP_PREC_FP32 && p.d > 128) {
+            set_error("problem %d: FP32 mode supports d <= 128 (got %d); use BF16_RECHECK", i, p.d);
+            return false;
+        }
+        if (p.precision == KP_PREC_BF16_RECHECK && p.d > 256) {
+            set_error("problem %d: BF16 mode supports d <= 256 (got %d)", i, p.d);
+            return false;
+        }
+        if (p.precision == KP_PREC_BF16_RECHECK && p.g > 1024) {
+            set_error("problem %d: BF16 mode supports g <= 1024 (got %d)", i, p.g);
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+struct kp_ctx;
+static void release_ctx(kp_ctx *ctx);
+
+struct kp_ctx {
+    int count = 0;
+    int device = 0;
+    hipStream_t user = nullptr, own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<kp::ProbDev> P;
+    kp::LaunchCfg cfg{4, 2048};
+    int use_graph = 1;
+    int iters = 0;
+    bool poisoned = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+// Frees the ctx's host resources, stream, events and graph without touching
+// the caller-visible error string.
+static void release_ctx(kp_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->own) (void)hipStreamSynchronize(ctx->own);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    delete ctx;
+}
+
+#define KP_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                  \
+            if (ctx) ctx->poisoned = true;                                             \
+            return KP_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+extern "C" {
+
+size_t kp_workspace_bytes(const kp_problem *problems, int32_t count, const kp_tuning *tuning)
+{
+    if (!validate(problems, count, tuning)) return 0;
+    const int W = tuning_W(tuning);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) total += plan_problem(problems[i], W).bytes;
+    return total;
+}
+
+kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void *workspace, size_t ws_bytes,
+                  void *stream, const kp_tuning *tuning)
+{
+    kp_ctx *ctx = nullptr;
+    if (!out) {
+        set_error("out is NULL");
+        return KP_ERR_INVALID;
+    }
+    if (!validate(problems, count, tuning)) return KP_ERR_INVALID;
+    if (!supported(problems, count)) return KP_ERR_UNSUPPORTED;
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) {
+        set_error("workspace must be non-NULL and %zu-byte aligned", ALIGN);
+        return KP_ERR_INVALID;
+    }
+    const int W = tuning_W(tuning);
+    std::vector<Plan> plans;
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        plans.push_back(plan_problem(problems[i], W));
+        need += plans.back().bytes;
+    }
+    if (ws_bytes < need) {
+        set_error("workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return KP_ERR_INVALID;
+    }
+    ctx = new (std::nothrow) kp_ctx;
+    if (!ctx) {
+        set_error("host allocation failed");
+        return KP_ERR_NOMEM;
+    }
+    std::unique_ptr<kp_ctx, void (*)(kp_ctx *)> guard(ctx, release_ctx);   // freed on any early return
+    ctx->count = count;
+    ctx->user = (hipStream_t)stream;
+    if (tuning) {
+        if (tuning->waves_per_block) ctx->cfg.waves = tuning->waves_per_block;
+        if (tuning->blocks_per_cu) ctx->cfg.grid_cap = 256 * tuning->blocks_per_cu;
+        if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
+    }
+    KP_HIP(hipGetDevice(&ctx->device));
+    KP_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
+    KP_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    KP_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    KP_HIP(hipMemsetAsync(workspace, 0, need, ctx->user));
+
+    char *base = (char *)workspace;
+    std::vector<float> hc;
+    for (int i = 0; i < count; ++i) {
+        const kp_problem &p = problems[i];
+        const Plan &o = plans[i];
+        hc.resize((size_t)p.k * p.d);
+        KP_HIP(hipMemcpyAsync(hc.data(), p.init_centroids_dev, hc.size() * 4, hipMemcpyDeviceToHost, ctx->user));
+        KP_HIP(hipStreamSynchronize(ctx->user));
+        kp::Grouping G = kp::make_groups(hc.data(), p.k, p.d, p.g, p.seed);
+        kp::ProbDev P;
+        std::memset(&P, 0, sizeof P);
+        P.n = p.n;
+        P.d = p.d;
+        P.k = p.k;
+        P.g = G.g;
+        P.kg = G.kg;
+        P.ldc = o.ldc;
+        P.ldb = o.ldb;
+        P.gs = o.gs;
+        P.prec = p.precision;
+        P.W = W;
+        P.maxgs = G.maxgs;
+        P.X = p.points_dev;
+        P.Xb = (uint16_t *)(base + o.Xb);
+        P.xn = (float *)(base + o.xn);
+        P.xr = (float *)(base + o.xr);
+        P.st = (kp::PointState *)(base + o.st);
+        P.lb = (float *)(base + o.lb);
+        P.c32 = (float *)(base + o.c32);
+        P.cb = (uint16_t *)(base + o.cb);
+        P.cn = (float *)(base + o.cn);
+        P.cr = (float *)(base + o.cr);
+        P.c64 = (double *)(base + o.c64);
+        P.sums = (double *)(base + o.sums);
+        P.delta = (double *)(base + o.delta);
+        P.cnt = (int *)(base + o.cnt);
+        P.perm = (const int *)(base + o.perm);
+        P.slot_group = (const int *)(base + o.sgrp);
+        P.gstart = (const int *)(base + o.gstart);
+        P.gsize = (const int *)(base + o.gsize);
+        P.Sc = (double *)(base + o.Sc);
+        P.Sg = (double *)(base + o.Sg);
+        P.Sd = (double *)(base + o.Sd);
+        P.L1 = (int *)(base + o.L1);
+        P.L3 = (int4 *)(base + o.L3);
+        P.mv_pt = (int *)(base + o.mvp);
+        P.mv_old = (int *)(base + o.mvo);
+        P.mv_new = (int *)(base + o.mvn);
+        P.srt_pt = (int *)(base + o.srtp);
+        P.srt_key = (int *)(base + o.srtk);
+        P.hist = (int *)(base + o.hist);
+        P.cursor = (int *)(base + o.cursor);
+        P.ctr = (unsigned long long *)(base + o.ctr);
+        P.stats = (long long *)(base + o.stats);
+        P.iter = (int *)(base + o.iter);
+        P.scal = (float *)(base + o.scal);
+        KP_HIP(hipMemcpyAsync((void *)P.perm, G.perm.data(), G.perm.size() * 4, hipMemcpyHostToDevice, ctx->user));
+        KP_HIP(hipMemcpyAsync((void *)P.slot_group, G.slot_group.data(), G.slot_group.size() * 4,
+                              hipMemcpyHostToDevice, ctx->user));
+        KP_HIP(hipMemcpyAsync((void *)P.gstart, G.gstart.data(), G.gstart.size() * 4, hipMemcpyHostToDevice,
+                              ctx->user));
+        KP_HIP(hipMemcpyAsync((void *)P.gsize, G.gsize.data(), G.gsize.size() * 4, hipMemcpyHostToDevice,
+                              ctx->user));
+        KP_HIP(kp::launch_prep(P, ctx->user, p.init_centroids_dev));
+        KP_HIP(hipStreamSynchronize(ctx->user));   // host vectors above are reused
+        ctx->P.push_back(P);
+        base += o.bytes;
+    }
+    *out = guard.release();
+    g_last_error.clear();
+    return KP_OK;
+}
+
+static kp_status check_ctx(kp_ctx *ctx)
+{
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return KP_ERR_INVALID;
+    }
+    if (ctx->poisoned) {
+        set_error("ctx is poisoned by an earlier HIP failure");
+        return KP_ERR_STATE;
+    }
+    return KP_OK;
+}
+
+kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (iters < 1) {
+        set_error("iters=%d must be >= 1", iters);
+        return KP_ERR_INVALID;
+    }
+    KP_HIP(hipEventRecord(ctx->ev_in, ctx->user));
+    KP_HIP(hipStreamWaitEvent(ctx->own, ctx->ev_in, 0));
+    int todo = iters;
+    if (ctx->iters == 0) {
+        for (auto &P : ctx->P) KP_HIP(kp::launch_iteration(P, ctx->own, true, ctx->cfg));
+        ctx->iters = 1;
+        --todo;
+    }
+    if (todo > 0) {
+        if (ctx->use_graph) {
+            if (!ctx->gexec) {
+                KP_HIP(hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal));
+                for (auto &P : ctx->P) {
+                    hipError_t e = kp::launch_iteration(P, ctx->own, false, ctx->cfg);
+                    if (e != hipSuccess) {
+                        hipGraph_t junk = nullptr;
+                        (void)hipStreamEndCapture(ctx->own, &junk);
+                        if (junk) (void)hipGraphDestroy(junk);
+                        KP_HIP(e);
+                    }
+                }
+                KP_HIP(hipStreamEndCapture(ctx->own, &ctx->graph));
+                KP_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+            }
+            for (int i = 0; i < todo; ++i) KP_HIP(hipGraphLaunch(ctx->gexec, ctx->own));
+        } else {
+            for (int i = 0; i < todo; ++i)
+                for (auto &P : ctx->P) KP_HIP(kp::launch_iteration(P, ctx->own, false, ctx->cfg));
+        }
+        ctx->iters += todo;
+    }
+    KP_HIP(hipEventRecord(ctx->ev_out, ctx->own));
+    KP_HIP(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+    return KP_OK;
+}
+
+kp_status kp_assign(kp_ctx *ctx, int32_t problem, int32_t *labels)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count || !labels) {
+        set_error("bad problem index %d or NULL labels", problem);
+        return KP_ERR_INVALID;
+    }
+    if (ctx->iters == 0) {
+        set_error("no iteration has run yet");
+        return KP_ERR_STATE;
+    }
+    KP_HIP(kp::launch_labels(ctx->P[problem], ctx->user, labels));
+    return KP_OK;
+}
+
+kp_status kp_centroids(kp_ctx *ctx, int32_t problem, float *c32, double *c64)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count) {
+        set_error("bad problem index %d", problem);
+        return KP_ERR_INVALID;
+    }
+    if (!c32 && !c64) return KP_OK;
+    KP_HIP(kp::launch_centroids_out(ctx->P[problem], ctx->user, c32, c64));
+    return KP_OK;
+}
+
+kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *out, int32_t cap, int32_t *n_out)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count || !n_out || (cap > 0 && !out) || cap < 0) {
+        set_error("bad problem index %d, cap %d or NULL output", problem, cap);
+        return KP_ERR_INVALID;
+    }
+    KP_HIP(hipStreamSynchronize(ctx->user));
+    const kp::ProbDev &P = ctx->P[problem];
+    int done = 0;
+    KP_HIP(hipMemcpy(&done, P.iter, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<long long> rec((size_t)kp::STATS_CAP * 8);
+    KP_HIP(hipMemcpy(rec.data(), P.stats, rec.size() * sizeof(long long), hipMemcpyDeviceToHost));
+    const int first = std::max(1, done - kp::STATS_CAP + 1);
+    int w = 0;
+    for (int it = first; it <= done && w < cap; ++it, ++w) {
+        const long long *r = &rec[(size_t)((it - 1) % kp::STATS_CAP) * 8];
+        out[w].iter = (int32_t)r[0];
+        out[w].dense = (int32_t)r[1];
+        out[w].point_filter_fail = r[2];
+        out[w].pairs = r[3];
+        out[w].distances = r[4];
+        out[w].rechecks = r[5];
+        out[w].moved = r[6];
+    }
+    *n_out = w;
+    return KP_OK;
+}
+
+int32_t kp_iterations(const kp_ctx *ctx) { return ctx ? ctx->iters : -1; }
+
+kp_status kp_destroy(kp_ctx *ctx)
+{
+    if (!ctx) return KP_OK;
+    kp_status st = KP_OK;
+    if (ctx->user || ctx->own) {
+        if (hipStreamSynchronize(ctx->user) != hipSuccess) st = KP_ERR_HIP;
+        if (ctx->own && hipStreamSynchronize(ctx->own) != hipSuccess) st = KP_ERR_HIP;
+    }
+    release_ctx(ctx);
+    if (st != KP_OK) set_error("stream synchronisation failed during kp_destroy");
+    return st;
+}
+
+const char *kp_strerror(kp_status s)
+{
+    switch (s) {
+    case KP_OK: return "success";
+    case KP_ERR_INVALID: return "invalid argument";
+    case KP_ERR_NOMEM: return "out of host memory";
+    case KP_ERR_HIP: return "HIP runtime error";
+    case KP_ERR_STATE: return "invalid state";
+    case KP_ERR_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char *kp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

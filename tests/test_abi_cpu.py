@@ -1,0 +1,96 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects invalid requests before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_09345_amd import kp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "kp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(kp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = kp.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(kp.kp_problem) == 48
+    assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
+    assert ctypes.sizeof(kp.kp_tuning) == 16
+    assert ctypes.sizeof(kp.kp_iter_stats) == 48 and kp.kp_iter_stats.point_filter_fail.offset == 8
+
+
+def _prob(**kw):
+    base = dict(n=1000, d=32, k=16, g=4, precision=0, points_dev=4096, init_centroids_dev=8192, seed=0)
+    base.update(kw)
+    return kp.kp_problem(**base)
+
+
+def test_workspace_bytes_valid_and_monotone():
+    a = kp.kp_workspace_bytes([_prob()])
+    b = kp.kp_workspace_bytes([_prob(n=2000)])
+    c = kp.kp_workspace_bytes([_prob(precision=1)])
+    assert 0 < a < b and a < c
+    assert kp.kp_workspace_bytes([_prob(), _prob(n=2000)]) == a + b
+
+
+@pytest.mark.parametrize("bad", [dict(n=0), dict(k=0), dict(k=2000), dict(g=0), dict(g=17), dict(d=0),
+                                 dict(d=2000), dict(precision=7), dict(points_dev=0),
+                                 dict(init_centroids_dev=0), dict(points_dev=4100)])
+def test_invalid_problem_rejected(bad):
+    assert kp.kp_workspace_bytes([_prob(**bad)]) == 0
+    assert kp.kp_last_error() != ""
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_init([_prob(**bad)], 1 << 20, 1 << 30)
+    assert e.value.status == kp.KP_ERR_INVALID
+
+
+def test_invalid_tuning_rejected():
+    t = kp.kp_tuning(age_limit=99)
+    assert kp.kp_workspace_bytes([_prob()], t) == 0
+
+
+def test_init_argument_errors_before_device_use():
+    need = kp.kp_workspace_bytes([_prob()])
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_init([_prob()], 256, need - 1)          # short workspace
+    assert e.value.status == kp.KP_ERR_INVALID
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_init([_prob()], 257, need)              # misaligned workspace
+    assert e.value.status == kp.KP_ERR_INVALID
+    with pytest.raises(kp.KPError) as e:
+        kp.kp_init([_prob(d=300)], 256, 1 << 40)      # FP32 mode limit
+    assert e.value.status == kp.KP_ERR_UNSUPPORTED
+    L = kp.lib()
+    assert L.kp_init(None, None, 0, None, 0, None, None) == kp.KP_ERR_INVALID
+
+
+def test_null_ctx_calls():
+    L = kp.lib()
+    assert L.kp_iterate(None, 1) == kp.KP_ERR_INVALID
+    assert L.kp_assign(None, 0, None) == kp.KP_ERR_INVALID
+    assert L.kp_centroids(None, 0, None, None) == kp.KP_ERR_INVALID
+    n = ctypes.c_int32(0)
+    assert L.kp_stats(None, 0, None, 0, ctypes.byref(n)) == kp.KP_ERR_INVALID
+    assert L.kp_destroy(None) == kp.KP_OK
+    assert L.kp_iterations(None) == -1
+
+
+def test_strerror():
+    for s in range(6):
+        assert kp.kp_strerror(s)
+    assert kp.kp_strerror(99) == "unknown status"

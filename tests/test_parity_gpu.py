@@ -1,0 +1,115 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Sizes are chosen so that the oracle finishes in seconds while the GPU runs
+several tiles and a ragged tail; the full-size workloads are checked on
+sampled points (test_fullsize_gpu.py).
+"""
+import numpy as np
+import pytest
+
+import datagen
+from parity import run_steplocked
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(name, **kw):
+    print("CASE", name, kw, flush=True)
+
+
+def test_c1_full_fp32():
+    P = datagen.make_config(1)
+    _print_case("c1", n=P.n)
+    r = run_steplocked(P.X, P.C0, P.g, "fp32", P.iters)
+    st = r["stats"]
+    assert st[0]["dense"] == 1 and len(st) == P.iters
+    assert st[-1]["point_filter_fail"] < P.n // 2     # the point-level filter prunes
+
+
+def test_c2_reduced_fp32():
+    P = datagen.make_config(2, n=60_007)
+    _print_case("c2-reduced", n=P.n)
+    r = run_steplocked(P.X, P.C0, P.g, "fp32", 12)
+    st = r["stats"]
+    assert st[-1]["distances"] < 0.5 * P.n * P.k
+
+
+def test_c3_shape_bf16():
+    P = datagen.make_config(3, n=30_011)
+    _print_case("c3-reduced", n=P.n)
+    r = run_steplocked(P.X, P.C0, P.g, "bf16", 6)
+    st = r["stats"]
+    assert st[0]["dense"] == 1
+    assert sum(s["rechecks"] for s in st) >= 0
+
+
+@pytest.mark.parametrize("d", [16, 32, 64])
+def test_bf16_small_dims(d):
+    rng = np.random.default_rng(d)
+    X = datagen.gaussian_mixture(rng, 9_001, d, 64)
+    C0 = datagen.kmeanspp(rng, X, 64, sample=2000)
+    _print_case("bf16-d", d=d)
+    run_steplocked(X, C0, 7, "bf16", 8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [5, 13, 37])
+def test_ragged_dims(prec, d):
+    rng = np.random.default_rng(100 + d)
+    X = datagen.gaussian_mixture(rng, 3_333, d, 20)
+    C0 = X[:20].copy()
+    _print_case("ragged", d=d, prec=prec)
+    run_steplocked(X, C0, 4, prec, 6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("g", [1, 2, 30])
+def test_group_extremes(prec, g):
+    """G=1 (one group), G=K (every centroid alone) and in between."""
+    rng = np.random.default_rng(7)
+    X = datagen.gaussian_mixture(rng, 5_000, 24, 30)
+    C0 = datagen.kmeanspp(rng, X, 30)
+    _print_case("groups", g=g, prec=prec)
+    run_steplocked(X, C0, g, prec, 8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_k1(prec):
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(777, 9)).astype(np.float32)
+    _print_case("k1", prec=prec)
+    r = run_steplocked(X, X[:1].copy(), 1, prec, 3)
+    np.testing.assert_allclose(r["c64"][0], X.astype(np.float64).mean(axis=0), rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ties_duplicates_and_empty_clusters(prec):
+    """Exact ties (points on a grid, centroids at symmetric positions), duplicated
+    centroids and a centroid that never receives a point."""
+    g = np.arange(-4, 5, dtype=np.float32)
+    X = np.stack(np.meshgrid(g, g, g), axis=-1).reshape(-1, 3)
+    X = np.concatenate([X] * 3).astype(np.float32)           # 2187 points with many exact ties
+    C0 = np.array([[0.5, 0, 0], [-0.5, 0, 0], [0, 0.5, 0], [0, -0.5, 0],
+                   [2, 2, 2], [2, 2, 2],                      # duplicate centroid
+                   [100, 100, 100],                           # never used
+                   [-3, -3, 3]], np.float32)
+    _print_case("ties", prec=prec)
+    r = run_steplocked(X, C0, 3, prec, 5)
+    assert r["c64"][6].tolist() == [100.0, 100.0, 100.0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_age_refresh(prec):
+    """Age limit 2 forces every kept point through a full bound refresh each iteration."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    P = datagen.make_config(2, n=8_191)
+    _print_case("age", prec=prec)
+    run_steplocked(P.X, P.C0, P.g, prec, 7, tuning=kp_tuning(age_limit=2))
+
+
+@pytest.mark.parametrize("use_graph", [1, -1])
+def test_graph_and_plain_launches(use_graph):
+    from paper_1905_09345_amd.kp import kp_tuning
+    P = datagen.make_config(1, n=4_097)
+    _print_case("graph", use_graph=use_graph)
+    run_steplocked(P.X, P.C0, P.g, "fp32", 6, tuning=kp_tuning(use_graph=use_graph))
