@@ -1,0 +1,217 @@
+"""Benchmark: point-iterations/sec of the filtered K-means path on one MI355X.
+
+One step = one complete K-means run of the workload's T iterations (the
+dense first iteration, then T-1 filtered iterations with centroid updates)
+from the initial centroids, on inputs already resident in HBM.  Each step
+uses its own context, created (with its per-point BF16 shadow) before the
+timed region, so every step starts from iteration 1.
+
+value = N * T * steps / seconds.  Printed beside it, on the same JSON line:
+  plain_fp32_lloyd  dense FP32 Lloyd on the same GPU (torch FP32 GEMM with
+                    TF32 off, argmin, full centroid recompute)
+  roofline          the dominant kernel's achieved rate against the MI355X
+                    peak, from HIP events the library records around it
+  cpu_baseline      the FP64 oracle on the host cores, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "point-iterations/sec, filtered BF16+recheck vs plain FP32 Lloyd, same GPU"
+HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
+    ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP32 Lloyd comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--stats", action="store_true", help="print per-iteration filter statistics")
+    return ap.parse_args()
+
+
+def plain_fp32_lloyd(torch, Xd, C0d, iters, warmup=1, chunk=1 << 19):
+    """Dense FP32 Lloyd with torch on the same GPU; returns seconds per iteration."""
+    torch.backends.cuda.matmul.allow_tf32 = False
+    torch.set_float32_matmul_precision("highest")
+    n, d = Xd.shape
+    k = C0d.shape[0]
+    xn = (Xd * Xd).sum(1)
+    C = C0d.clone()
+    lab = torch.empty(n, dtype=torch.int64, device=Xd.device)
+
+    def one():
+        nonlocal C
+        cn = (C * C).sum(1)
+        for s in range(0, n, chunk):
+            e = min(n, s + chunk)
+            D = torch.addmm(cn.unsqueeze(0), Xd[s:e], C.t(), beta=1.0, alpha=-2.0)
+            D.add_(xn[s:e].unsqueeze(1))
+            lab[s:e] = D.argmin(1)
+        sums = torch.zeros((k, d), dtype=torch.float32, device=Xd.device).index_add_(0, lab, Xd)
+        cnt = torch.bincount(lab, minlength=k).to(torch.float32)
+        C = torch.where(cnt.unsqueeze(1) > 0, sums / cnt.clamp(min=1).unsqueeze(1), C)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        one()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / iters
+
+
+def cpu_baseline(P, target_s):
+    """The FP64 oracle (one Lloyd iteration) on a bounded sample of the workload."""
+    import oracle
+    threads = oracle.threads()
+    C = P.C0.astype(np.float64)
+    probe = min(P.n, 2000)
+    t0 = time.perf_counter()
+    lab, _ = oracle.assign(P.X[:probe], C)
+    oracle.update(P.X[:probe], lab, C)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    m = int(min(P.n, max(probe, probe * target_s / dt)))
+    t0 = time.perf_counter()
+    lab, _ = oracle.assign(P.X[:m], C)
+    oracle.update(P.X[:m], lab, C)
+    el = time.perf_counter() - t0
+    return dict(value=m / el, unit="point-iterations/s", cores=threads, kind="oracle",
+                sample="one FP64 Lloyd iteration (assign + update) over the first %d of %d points, all %d "
+                       "centroids, %.1f s" % (m, P.n, P.k, el))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import datagen
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning
+
+    t0 = time.perf_counter()
+    P = datagen.make_config(args.config, n=args.n)
+    log("data: %s n=%d d=%d k=%d g=%d T=%d (%.1f s)" % (P.meta["name"], P.n, P.d, P.k, P.g, P.iters,
+                                                           time.perf_counter() - t0))
+    prec = "bf16" if P.precision == "bf16" else "fp32"
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(P.X).to(dev)
+    C0d = torch.from_numpy(P.C0).to(dev)
+    tun = kp_tuning(timing=1)
+    runs = []
+    for i in range(args.warmup + args.steps):
+        runs.append(KMeans([(Xd, C0d, P.g, prec, P.seed)], tuning=tun))
+    torch.cuda.synchronize()
+    log("contexts ready: %d" % len(runs))
+    for km in runs[:args.warmup]:
+        km.iterate(P.iters)
+    torch.cuda.synchronize()
+    log("warmup done")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    for km in runs[args.warmup:]:
+        km.iterate(P.iters)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    el = max(wall, gpu_s)
+    value = P.n * P.iters * args.steps / el
+    log("timed: %d steps, %.3f ms/step (events %.3f ms/step)" % (args.steps, el / args.steps * 1e3,
+                                                                   gpu_s / args.steps * 1e3))
+
+    # per-stage GPU time (HIP events the library recorded on its stream)
+    stages = [km.stage_times() for km in runs[args.warmup:]]
+    names = stages[0].keys()
+    agg = {nm: dict(ms=sum(s[nm]["ms"] for s in stages) / args.steps,
+                    launches=sum(s[nm]["launches"] for s in stages) / args.steps) for nm in names}
+    st = runs[-1].stats()
+    if args.stats:
+        for s in st:
+            log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
+                "rechecks=%(rechecks)d moved=%(moved)d" % s)
+    for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
+        log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
+    dom = max(agg, key=lambda nm: agg[nm]["ms"])
+    roofline = roofline_of(dom, agg[dom], P, st)
+    del runs
+    torch.cuda.empty_cache()
+
+    baseline = None
+    if not args.no_baseline:
+        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=3)
+        baseline = dict(value=P.n / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
+                        impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration")
+        log("plain FP32 Lloyd: %.3f ms/iteration" % (sec * 1e3))
+    cpu = None if args.no_cpu else cpu_baseline(P, args.cpu_seconds)
+    out = {
+        "metric": METRIC, "value": value, "unit": "point-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if prec == "bf16" else "f32",
+        "data": "synthetic (seeded mixture, see datagen)",
+        "config": {"workload": P.meta["name"], "n": P.n, "d": P.d, "k": P.k, "g": P.g, "iterations": P.iters,
+                   "precision": "bf16 MFMA + fp32 recheck + fp64 centroids" if prec == "bf16"
+                   else "fp32 direct + fp64 centroids"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_fp32_lloyd": baseline,
+        "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
+        "stage_ms_per_step": {nm: round(a["ms"], 4) for nm, a in agg.items()},
+        "filter": {"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"]]
+                   for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def roofline_of(stage, a, P, st):
+    """Achieved rate of the dominant stage from its algorithmic work per launch."""
+    ms_per_launch = a["ms"] / max(a["launches"], 1e-9)
+    if stage == "assign_dense":
+        flops = 2.0 * P.n * P.k * P.d
+        ach = flops / (ms_per_launch * 1e-3) / 1e12
+        if P.precision == "bf16":
+            return dict(kernel="k_assign_bf16 (dense, iteration 1)", bound="mfma", achieved=ach,
+                        peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / MFMA_BF16_PEAK_TFLOPS,
+                        traffic=None, work_per_launch="2*N*K*D = %.4g flop" % flops,
+                        ms_per_launch=ms_per_launch)
+        peak = 78.6   # FP32 vector FMA without packed instructions (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+        return dict(kernel="k_assign_f32 (dense, iteration 1)", bound="alu", achieved=ach, peak=peak,
+                    unit="TFLOP/s", frac=ach / peak, traffic=None,
+                    work_per_launch="2*N*K*D = %.4g flop" % flops, ms_per_launch=ms_per_launch)
+    if stage == "bound_filter":
+        byts = 16.0 * P.n
+        ach = byts / (ms_per_launch * 1e-3) / 1e9
+        return dict(kernel="k_bound_filter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=None, work_per_launch="16 B/point x N = %.4g B" % byts,
+                    ms_per_launch=ms_per_launch)
+    return dict(kernel=stage, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                ms_per_launch=ms_per_launch)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,10 @@ typedef struct {
                                       refresh of its bounds: 2..32 (default 32) */
     int32_t use_graph;             /* 1 (default): replay iterations from a
                                       captured hipGraph; -1: plain launches */
+    int32_t timing;                /* 1: record HIP events on the ctx's stream
+                                      around every stage launched outside a
+                                      graph, and around every graph replay
+                                      (kp_stage_times); 0: none */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */
@@ -94,6 +98,14 @@ typedef struct {
     int64_t rechecks;              /* points re-decided in FP32 direct form */
     int64_t moved;                 /* points whose assignment changed */
 } kp_iter_stats;
+
+/* Accumulated GPU time of one stage (kp_stage_times). */
+typedef struct {
+    char name[24];                 /* "assign_dense", "bound_filter", "assign", "recheck",
+                                      "update", "centroids", "begin", "filtered_iter" */
+    double ms;                     /* total milliseconds between the stage's events */
+    int64_t launches;              /* number of timed launches */
+} kp_stage_time;
 
 /* Bytes of device workspace kp_init needs for these problems; 0 if the
  * description is invalid (kp_last_error says why). */
@@ -127,6 +139,14 @@ kp_status kp_centroids(kp_ctx *ctx, int32_t problem, float *c32_dev, double *c64
  * problem `problem` (oldest first) to stats_host; *n_host receives the count
  * written.  At most the last 1024 iterations are kept. */
 kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *stats_host, int32_t cap, int32_t *n_host);
+
+/* With kp_tuning.timing = 1: synchronise the ctx stream and return, per
+ * stage, the GPU time measured by HIP events recorded on the ctx's internal
+ * stream immediately before and after the stage's kernels, summed over all
+ * iterations queued so far.  Stages replayed inside a hipGraph are timed as
+ * one "filtered_iter" entry per replay.  Writes up to `cap` entries to
+ * out_host and their count to *n_host.  KP_ERR_STATE when timing is off. */
+kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out_host, int32_t cap, int32_t *n_host);
 
 /* Number of iterations completed on the ctx (host-side count of queued
  * iterations).  Returns -1 for NULL. */

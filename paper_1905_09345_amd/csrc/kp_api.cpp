@@ -125,6 +125,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
             set_error("use_graph=%d outside -1..1", t->use_graph);
             return false;
         }
+        if (t->timing < 0 || t->timing > 1) {
+            set_error("timing=%d outside 0..1", t->timing);
+            return false;
+        }
     }
     for (int i = 0; i < count; ++i) {
         const kp_problem &p = ps[i];
@@ -185,8 +189,74 @@ bool supported(const kp_problem *ps, int32_t count)
 struct kp_ctx;
 static void release_ctx(kp_ctx *ctx);
 
+// HIP event pairs recorded around stage launches on the ctx's own stream.
+struct StageTimer {
+    static constexpr int NSTAGE = kp::ST_COUNT + 1;   // + one entry per graph replay
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<Rec> pending;
+    double ms[NSTAGE] = {};
+    long long launches[NSTAGE] = {};
+    static const char *name(int st) { return st == kp::ST_COUNT ? "filtered_iter" : kp::stage_name((kp::Stage)st); }
+    hipError_t begin(int stage, hipStream_t s, Rec &r)
+    {
+        r.stage = stage;
+        if (pool.empty()) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return e;
+            }
+            pool.push_back({a, b});
+        }
+        r.a = pool.back().first;
+        r.b = pool.back().second;
+        pool.pop_back();
+        return hipEventRecord(r.a, s);
+    }
+    hipError_t end(hipStream_t s, Rec &r)
+    {
+        hipError_t e = hipEventRecord(r.b, s);
+        pending.push_back(r);
+        return e;
+    }
+    hipError_t harvest()
+    {
+        for (auto &r : pending) {
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e != hipSuccess) return e;
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, r.a, r.b);
+            if (e != hipSuccess) return e;
+            ms[r.stage] += t;
+            launches[r.stage] += 1;
+            pool.push_back({r.a, r.b});
+        }
+        pending.clear();
+        return hipSuccess;
+    }
+    void destroy()
+    {
+        for (auto &r : pending) pool.push_back({r.a, r.b});
+        pending.clear();
+        for (auto &p : pool) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        pool.clear();
+    }
+};
+
 struct kp_ctx {
     int count = 0;
+    int timing = 0;
+    StageTimer timer;
     int device = 0;
     hipStream_t user = nullptr, own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -205,6 +275,7 @@ static void release_ctx(kp_ctx *ctx)
 {
     if (!ctx) return;
     if (ctx->own) (void)hipStreamSynchronize(ctx->own);
+    ctx->timer.destroy();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -271,6 +342,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         if (tuning->waves_per_block) ctx->cfg.waves = tuning->waves_per_block;
         if (tuning->blocks_per_cu) ctx->cfg.grid_cap = 256 * tuning->blocks_per_cu;
         if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
+        ctx->timing = tuning->timing;
     }
     KP_HIP(hipGetDevice(&ctx->device));
     KP_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
@@ -364,6 +436,24 @@ static kp_status check_ctx(kp_ctx *ctx)
     return KP_OK;
 }
 
+// One iteration of every problem as plain launches, each stage bracketed by
+// timing events when timing is on.
+static hipError_t launch_all(kp_ctx *ctx, bool dense)
+{
+    for (auto &P : ctx->P) {
+        kp::Stage sts[kp::ST_COUNT];
+        const int n = kp::iteration_stages(P, dense, sts);
+        for (int i = 0; i < n; ++i) {
+            StageTimer::Rec r;
+            hipError_t e;
+            if (ctx->timing && (e = ctx->timer.begin(sts[i], ctx->own, r)) != hipSuccess) return e;
+            if ((e = kp::launch_stage(P, ctx->own, sts[i], dense, ctx->cfg)) != hipSuccess) return e;
+            if (ctx->timing && (e = ctx->timer.end(ctx->own, r)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
 {
     kp_status st = check_ctx(ctx);
@@ -376,7 +466,7 @@ kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
     KP_HIP(hipStreamWaitEvent(ctx->own, ctx->ev_in, 0));
     int todo = iters;
     if (ctx->iters == 0) {
-        for (auto &P : ctx->P) KP_HIP(kp::launch_iteration(P, ctx->own, true, ctx->cfg));
+        KP_HIP(launch_all(ctx, true));
         ctx->iters = 1;
         --todo;
     }
@@ -396,10 +486,14 @@ kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
                 KP_HIP(hipStreamEndCapture(ctx->own, &ctx->graph));
                 KP_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
             }
-            for (int i = 0; i < todo; ++i) KP_HIP(hipGraphLaunch(ctx->gexec, ctx->own));
+            for (int i = 0; i < todo; ++i) {
+                StageTimer::Rec r;
+                if (ctx->timing) KP_HIP(ctx->timer.begin(kp::ST_COUNT, ctx->own, r));
+                KP_HIP(hipGraphLaunch(ctx->gexec, ctx->own));
+                if (ctx->timing) KP_HIP(ctx->timer.end(ctx->own, r));
+            }
         } else {
-            for (int i = 0; i < todo; ++i)
-                for (auto &P : ctx->P) KP_HIP(kp::launch_iteration(P, ctx->own, false, ctx->cfg));
+            for (int i = 0; i < todo; ++i) KP_HIP(launch_all(ctx, false));
         }
         ctx->iters += todo;
     }
@@ -462,6 +556,33 @@ kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *out, int32_t cap
         out[w].distances = r[4];
         out[w].rechecks = r[5];
         out[w].moved = r[6];
+    }
+    *n_out = w;
+    return KP_OK;
+}
+
+kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out, int32_t cap, int32_t *n_out)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (!n_out || cap < 0 || (cap > 0 && !out)) {
+        set_error("bad cap %d or NULL output", cap);
+        return KP_ERR_INVALID;
+    }
+    if (!ctx->timing) {
+        set_error("timing is off for this ctx (kp_tuning.timing = 0)");
+        return KP_ERR_STATE;
+    }
+    KP_HIP(hipStreamSynchronize(ctx->own));
+    KP_HIP(ctx->timer.harvest());
+    int w = 0;
+    for (int sidx = 0; sidx < StageTimer::NSTAGE && w < cap; ++sidx) {
+        if (!ctx->timer.launches[sidx]) continue;
+        std::memset(out[w].name, 0, sizeof out[w].name);
+        std::strncpy(out[w].name, StageTimer::name(sidx), sizeof out[w].name - 1);
+        out[w].ms = ctx->timer.ms[sidx];
+        out[w].launches = ctx->timer.launches[sidx];
+        ++w;
     }
     *n_out = w;
     return KP_OK;

@@ -1036,26 +1036,68 @@ static void launch_update(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
         hipLaunchKernelGGL(k_segsum<8>, dim3(segblocks), dim3(256), 0, s, P); break;
     default: hipLaunchKernelGGL(k_segsum<16>, dim3(segblocks), dim3(256), 0, s, P); break;
     }
+}
+
+static void launch_centroid_rows(const ProbDev &P, hipStream_t s)
+{
     hipLaunchKernelGGL(k_centroids<false>, dim3(cap_grid((P.kg + 3) / 4, 4096)), dim3(256), 0, s, P,
                        (const float *)nullptr);
     hipLaunchKernelGGL(k_drift, dim3(1), dim3(1024), 0, s, P, 0);
 }
 
+const char *stage_name(Stage st)
+{
+    static const char *names[ST_COUNT] = {"begin", "bound_filter", "assign_dense", "assign", "recheck",
+                                          "update", "centroids"};
+    return (st >= 0 && st < ST_COUNT) ? names[st] : "?";
+}
+
+int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT])
+{
+    int n = 0;
+    out[n++] = ST_BEGIN;
+    if (dense) {
+        out[n++] = ST_ASSIGN_DENSE;
+    } else {
+        out[n++] = ST_FILTER;
+        out[n++] = ST_ASSIGN;
+    }
+    if (P.prec) out[n++] = ST_RECHECK;
+    out[n++] = ST_UPDATE;
+    out[n++] = ST_CENTROIDS;
+    return n;
+}
+
+hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, const LaunchCfg &cfg)
+{
+    switch (st) {
+    case ST_BEGIN:
+        hipLaunchKernelGGL(k_begin, dim3(cap_grid((P.kg + 256) / 256, 64)), dim3(256), 0, s, P, dense ? 1 : 0);
+        break;
+    case ST_FILTER:
+        hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 255) / 256, cfg.grid_cap)), dim3(256), 0, s, P);
+        break;
+    case ST_ASSIGN_DENSE: launch_assign<true>(P, s, cfg); break;
+    case ST_ASSIGN: launch_assign<false>(P, s, cfg); break;
+    case ST_RECHECK:
+        hipLaunchKernelGGL(k_recheck, dim3(cap_grid((P.n + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
+        break;
+    case ST_UPDATE: launch_update(P, s, cfg); break;
+    case ST_CENTROIDS: launch_centroid_rows(P, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const LaunchCfg &cfg)
 {
-    hipLaunchKernelGGL(k_begin, dim3(cap_grid((P.kg + 256) / 256, 64)), dim3(256), 0, s, P, dense ? 1 : 0);
-    if (dense) {
-        launch_assign<true>(P, s, cfg);
-    } else {
-        hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 255) / 256, cfg.grid_cap)), dim3(256), 0, s, P);
-        launch_assign<false>(P, s, cfg);
+    Stage sts[ST_COUNT];
+    const int n = iteration_stages(P, dense, sts);
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = launch_stage(P, s, sts[i], dense, cfg);
+        if (e != hipSuccess) return e;
     }
-    if (P.prec) {
-        const int rblocks = cap_grid((P.n + 3) / 4, cfg.grid_cap);
-        hipLaunchKernelGGL(k_recheck, dim3(rblocks), dim3(256), 0, s, P);
-    }
-    launch_update(P, s, cfg);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out)

@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
-           "kp_iterations", "kp_destroy", "kp_strerror", "kp_last_error")
+           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_strerror", "kp_last_error")
 
 
 class kp_problem(ctypes.Structure):
@@ -30,13 +30,17 @@ class kp_problem(ctypes.Structure):
 
 class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("age_limit", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("age_limit", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class kp_iter_stats(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("dense", ctypes.c_int32), ("point_filter_fail", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("distances", ctypes.c_int64), ("rechecks", ctypes.c_int64),
                 ("moved", ctypes.c_int64)]
+
+
+class kp_stage_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_double), ("launches", ctypes.c_int64)]
 
 
 class KPError(RuntimeError):
@@ -68,6 +72,8 @@ def lib():
         L.kp_centroids.restype = ctypes.c_int
         L.kp_stats.argtypes = [vp, ctypes.c_int32, P(kp_iter_stats), ctypes.c_int32, P(ctypes.c_int32)]
         L.kp_stats.restype = ctypes.c_int
+        L.kp_stage_times.argtypes = [vp, P(kp_stage_time), ctypes.c_int32, P(ctypes.c_int32)]
+        L.kp_stage_times.restype = ctypes.c_int
         L.kp_iterations.argtypes = [vp]
         L.kp_iterations.restype = ctypes.c_int32
         L.kp_destroy.argtypes = [vp]
@@ -122,6 +128,13 @@ def kp_stats(ctx, problem, cap=1024):
     _check(lib().kp_stats(ctypes.c_void_p(ctx), int(problem), buf, int(cap), ctypes.byref(n)), "kp_stats")
     return [dict(iter=s.iter, dense=s.dense, point_filter_fail=s.point_filter_fail, pairs=s.pairs,
                  distances=s.distances, rechecks=s.rechecks, moved=s.moved) for s in buf[:n.value]]
+
+
+def kp_stage_times(ctx, cap=16):
+    buf = (kp_stage_time * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib().kp_stage_times(ctypes.c_void_p(ctx), buf, int(cap), ctypes.byref(n)), "kp_stage_times")
+    return {s.name.decode(): dict(ms=s.ms, launches=s.launches) for s in buf[:n.value]}
 
 
 def kp_iterations(ctx):
@@ -205,6 +218,9 @@ class KMeans:
 
     def stats(self, problem=0):
         return kp_stats(self.ctx, problem)
+
+    def stage_times(self):
+        return kp_stage_times(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

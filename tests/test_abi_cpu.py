@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 16
+    assert ctypes.sizeof(kp.kp_tuning) == 20
+    assert ctypes.sizeof(kp.kp_stage_time) == 40
     assert ctypes.sizeof(kp.kp_iter_stats) == 48 and kp.kp_iter_stats.point_filter_fail.offset == 8
 
 
@@ -86,6 +87,7 @@ def test_null_ctx_calls():
     assert L.kp_centroids(None, 0, None, None) == kp.KP_ERR_INVALID
     n = ctypes.c_int32(0)
     assert L.kp_stats(None, 0, None, 0, ctypes.byref(n)) == kp.KP_ERR_INVALID
+    assert L.kp_stage_times(None, None, 0, ctypes.byref(n)) == kp.KP_ERR_INVALID
     assert L.kp_destroy(None) == kp.KP_OK
     assert L.kp_iterations(None) == -1
 
