@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--stats", action="store_true", help="print per-iteration filter statistics")
+    ap.add_argument("--plain", action="store_true",
+                    help="plain launches instead of graph replays (per-stage timing of every iteration)")
     return ap.parse_args()
 
 
@@ -121,7 +123,7 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(P.X).to(dev)
     C0d = torch.from_numpy(P.C0).to(dev)
-    tun = kp_tuning(timing=1)
+    tun = kp_tuning(timing=1, use_graph=-1 if args.plain else 1)
     runs = []
     for i in range(args.warmup + args.steps):
         runs.append(KMeans([(Xd, C0d, P.g, prec, P.seed)], tuning=tun))
@@ -154,7 +156,7 @@ def main():
     if args.stats:
         for s in st:
             log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
-                "rechecks=%(rechecks)d moved=%(moved)d" % s)
+                "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
     dom = max(agg, key=lambda nm: agg[nm]["ms"])

@@ -78,8 +78,6 @@ typedef struct {
 typedef struct {
     int32_t waves_per_block;       /* 1..4 waves of 64 lanes per workgroup */
     int32_t blocks_per_cu;         /* grid = 256 CUs * this (grid-stride loops) */
-    int32_t age_limit;             /* iterations a point may go without a
-                                      refresh of its bounds: 2..32 (default 32) */
     int32_t use_graph;             /* 1 (default): replay iterations from a
                                       captured hipGraph; -1: plain launches */
     int32_t timing;                /* 1: record HIP events on the ctx's stream
@@ -97,12 +95,15 @@ typedef struct {
     int64_t distances;             /* point-centroid distances computed (padding excluded) */
     int64_t rechecks;              /* points re-decided in FP32 direct form */
     int64_t moved;                 /* points whose assignment changed */
+    double max_drift;              /* largest centroid move of this iteration's update */
+    int64_t tile_groups;           /* (64-point tile, open group) pairs visited by the distance kernel */
 } kp_iter_stats;
 
 /* Accumulated GPU time of one stage (kp_stage_times). */
 typedef struct {
-    char name[24];                 /* "assign_dense", "bound_filter", "assign", "recheck",
-                                      "update", "centroids", "begin", "filtered_iter" */
+    char name[24];                 /* "assign_dense", "bound_filter", "l1_sort", "assign",
+                                      "recheck", "update", "centroids", "begin",
+                                      "filtered_iter" */
     double ms;                     /* total milliseconds between the stage's events */
     int64_t launches;              /* number of timed launches */
 } kp_stage_time;

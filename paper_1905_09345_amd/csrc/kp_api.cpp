@@ -37,12 +37,13 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t Xb, xn, xr, st, lb, c32, cb, cn, cr, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, L1, L3, mvp, mvo, mvn, srtp, srtk, hist, cursor, ctr, stats, iter, scal;
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+        cursor1, ctr, stats, iter, scal;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
 };
 
-Plan plan_problem(const kp_problem &p, int W)
+Plan plan_problem(const kp_problem &p)
 {
     Plan o;
     const size_t n = (size_t)p.n;
@@ -76,11 +77,21 @@ Plan plan_problem(const kp_problem &p, int W)
     o.sgrp = take(kgm * 4);
     o.gstart = take((size_t)(g + 1) * 4);
     o.gsize = take((size_t)g * 4);
-    o.Sc = take((size_t)W * kgm * 8);
-    o.Sg = take((size_t)W * g * 8);
-    o.Sd = take((size_t)W * 8);
+    o.Sc = take(kgm * 8);
+    o.Sg = take((size_t)g * 8);
+    o.Sd = take(8);
+    o.Scu = take(kgm * 4);
+    o.Scd = take(kgm * 4);
+    o.Sgu = take((size_t)g * 4);
+    o.Sgd = take((size_t)g * 4);
+    o.Sdud = take(8);
     o.L1 = take(n * 4);
-    o.L3 = take(bf ? n * 16 : 0);
+    o.L1s = take(n * 4);
+    const size_t ntiles = (n + 63) / 64;
+    o.tlist = take(ntiles * (size_t)g * 16);
+    o.tcnt = take(ntiles * 4);
+    o.ps4 = take(n * 16);
+    o.psf = take(n * 4);
     o.mvp = take(n * 4);
     o.mvo = take(n * 4);
     o.mvn = take(n * 4);
@@ -88,15 +99,15 @@ Plan plan_problem(const kp_problem &p, int W)
     o.srtk = take(2 * n * 4);
     o.hist = take((kgm + 1) * 4);
     o.cursor = take((kgm + 1) * 4);
+    o.hist1 = take((kgm + 1) * 4);
+    o.cursor1 = take((kgm + 1) * 4);
     o.ctr = take(kp::NCTR * 8);
-    o.stats = take((size_t)kp::STATS_CAP * 8 * 8);
+    o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
     o.scal = take(16);
     o.bytes = off;
     return o;
 }
-
-int tuning_W(const kp_tuning *t) { return (t && t->age_limit) ? t->age_limit : 32; }
 
 bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
 {
@@ -115,10 +126,6 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
         }
         if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) {
             set_error("blocks_per_cu=%d outside 0..64", t->blocks_per_cu);
-            return false;
-        }
-        if (t->age_limit != 0 && (t->age_limit < 2 || t->age_limit > 32)) {
-            set_error("age_limit=%d outside 2..32", t->age_limit);
             return false;
         }
         if (t->use_graph < -1 || t->use_graph > 1) {
@@ -299,9 +306,8 @@ extern "C" {
 size_t kp_workspace_bytes(const kp_problem *problems, int32_t count, const kp_tuning *tuning)
 {
     if (!validate(problems, count, tuning)) return 0;
-    const int W = tuning_W(tuning);
     size_t total = 0;
-    for (int i = 0; i < count; ++i) total += plan_problem(problems[i], W).bytes;
+    for (int i = 0; i < count; ++i) total += plan_problem(problems[i]).bytes;
     return total;
 }
 
@@ -319,11 +325,10 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         set_error("workspace must be non-NULL and %zu-byte aligned", ALIGN);
         return KP_ERR_INVALID;
     }
-    const int W = tuning_W(tuning);
     std::vector<Plan> plans;
     size_t need = 0;
     for (int i = 0; i < count; ++i) {
-        plans.push_back(plan_problem(problems[i], W));
+        plans.push_back(plan_problem(problems[i]));
         need += plans.back().bytes;
     }
     if (ws_bytes < need) {
@@ -370,7 +375,6 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.ldb = o.ldb;
         P.gs = o.gs;
         P.prec = p.precision;
-        P.W = W;
         P.maxgs = G.maxgs;
         P.X = p.points_dev;
         P.Xb = (uint16_t *)(base + o.Xb);
@@ -393,8 +397,17 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Sc = (double *)(base + o.Sc);
         P.Sg = (double *)(base + o.Sg);
         P.Sd = (double *)(base + o.Sd);
+        P.Scu = (float *)(base + o.Scu);
+        P.Scd = (float *)(base + o.Scd);
+        P.Sgu = (float *)(base + o.Sgu);
+        P.Sgd = (float *)(base + o.Sgd);
+        P.Sdud = (float *)(base + o.Sdud);
         P.L1 = (int *)(base + o.L1);
-        P.L3 = (int4 *)(base + o.L3);
+        P.L1s = (int *)(base + o.L1s);
+        P.tlist = (int4 *)(base + o.tlist);
+        P.tcnt = (int *)(base + o.tcnt);
+        P.ps4 = (float4 *)(base + o.ps4);
+        P.psf = (int *)(base + o.psf);
         P.mv_pt = (int *)(base + o.mvp);
         P.mv_old = (int *)(base + o.mvo);
         P.mv_new = (int *)(base + o.mvn);
@@ -402,6 +415,8 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.srt_key = (int *)(base + o.srtk);
         P.hist = (int *)(base + o.hist);
         P.cursor = (int *)(base + o.cursor);
+        P.hist1 = (int *)(base + o.hist1);
+        P.cursor1 = (int *)(base + o.cursor1);
         P.ctr = (unsigned long long *)(base + o.ctr);
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
@@ -543,12 +558,12 @@ kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *out, int32_t cap
     const kp::ProbDev &P = ctx->P[problem];
     int done = 0;
     KP_HIP(hipMemcpy(&done, P.iter, sizeof(int), hipMemcpyDeviceToHost));
-    std::vector<long long> rec((size_t)kp::STATS_CAP * 8);
+    std::vector<long long> rec((size_t)kp::STATS_CAP * 16);
     KP_HIP(hipMemcpy(rec.data(), P.stats, rec.size() * sizeof(long long), hipMemcpyDeviceToHost));
     const int first = std::max(1, done - kp::STATS_CAP + 1);
     int w = 0;
     for (int it = first; it <= done && w < cap; ++it, ++w) {
-        const long long *r = &rec[(size_t)((it - 1) % kp::STATS_CAP) * 8];
+        const long long *r = &rec[(size_t)((it - 1) % kp::STATS_CAP) * 16];
         out[w].iter = (int32_t)r[0];
         out[w].dense = (int32_t)r[1];
         out[w].point_filter_fail = r[2];
@@ -556,6 +571,10 @@ kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *out, int32_t cap
         out[w].distances = r[4];
         out[w].rechecks = r[5];
         out[w].moved = r[6];
+        double md;
+        std::memcpy(&md, &r[7], sizeof md);
+        out[w].max_drift = md;
+        out[w].tile_groups = r[8];
     }
     *n_out = w;
     return KP_OK;

@@ -6,19 +6,25 @@
 //                        ldb = roundup(d, 32) (BF16 mode only)
 //   xn     n       FP32  ||Xb_i||^2 (BF16 mode)
 //   xr     n       FP32  ||X_i - Xb_i|| rounded up (BF16 mode)
-//   st     n       16 B  PointState: assignment slot, upper bound, point-level
-//                        lower bound, stamp of the last refresh
+//   st     n       16 B  PointState: assigned slot and two bounds
 //   lb     n x gs  FP32  group-level lower bounds, gs = roundup(g, 4)
 //   centroids in "slot" order: the members of group q occupy slots
 //   gstart[q] .. gstart[q] + gsize[q] - 1 in ascending original index, and the
 //   group is padded with empty slots to a multiple of 16 so that every
 //   16-slot chunk of a MFMA tile belongs to one group.
 //
-// Bounds are stored "lazily": the drift of the centroids is accumulated in
-// FP64 ring buffers (per slot, per group and its maximum) and a point's
-// stored bounds are brought to the current iteration only when the point is
-// looked at.  Exact arithmetic gives the same bounds as updating every point
-// in every iteration; the rounding directions below keep them valid.
+// Bounds are stored in offset form against the cumulative drift of the
+// centroids (FP64 sums, updated once per iteration):
+//   Sc[j] = sum over updates of ||c_j(new) - c_j(old)||        (per slot)
+//   Sg[q] = sum over updates of max_{j in q} drift              (per group)
+//   Sd    = sum over updates of max_j drift                     (global)
+// A point stores u = ub - Sc[a], p = lbp + Sd and v_q = lb_q + Sg[q] at the
+// time the bound was computed; at any later iteration ub + (drift of c_a
+// since then) = u + Sc[a], and similarly for the lower bounds.  This is the
+// triangle inequality |d(x, c') - d(x, c)| <= ||c' - c|| accumulated over the
+// iterations since the bound was last computed, without touching the point
+// in between.  FP32 copies of the sums rounded up (evaluation) and down
+// (storage) keep every bound valid under rounding.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,15 +35,16 @@ constexpr int WAVE = 64;
 constexpr int CHUNK = 16;             // centroid slots per MFMA tile / group padding
 constexpr int STATS_CAP = 1024;       // per-iteration stats ring
 constexpr int NCTR = 8;               // per-iteration counters
+constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
 
 // counters (unsigned long long) per problem
-enum { CTR_L1 = 0, CTR_L3 = 1, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5 };
+enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6 };
 
 struct __attribute__((aligned(16))) PointState {
     int a;        // slot of the assigned centroid
-    float ub;     // upper bound on d(x, c_a), valid at stamp tx (see ub_eff)
-    float lbp;    // lower bound on min_{j != a} d(x, c_j) at stamp tx
-    int tx;       // iteration whose assignment step last refreshed the bounds
+    float u;      // ub - Sc[a] (rounded up)
+    float p;      // lbp + Sd (rounded down): lbp bounds min_{j != a} d(x, c_j)
+    int pad;
 };
 
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
@@ -48,9 +55,7 @@ struct ProbDev {
     int d, k, g, kg;          // kg = number of slots (with padding)
     int ldc, ldb, gs;         // leading dims: c32 (roundup 4), bf16 (roundup 32), lb row
     int prec;                 // 0 fp32 direct, 1 bf16 + recheck
-    int W;                    // ring length (age limit)
     int maxgs;                // largest group size (real members)
-    int pad0;
     const float *X;
     uint16_t *Xb;
     float *xn, *xr;
@@ -64,14 +69,22 @@ struct ProbDev {
     const int *perm;          // slot -> original index, -1 for padding
     const int *slot_group;    // slot -> group, -1 for padding
     const int *gstart, *gsize;
-    double *Sc, *Sg, *Sd;     // rings: W x kg, W x g, W
-    int *L1;                  // point ids failing the point-level filter
-    int4 *L3;                 // (point, old slot, bits of U*, flags) for the FP32 recheck
-    int *mv_pt, *mv_old, *mv_new;   // moved points
-    int *srt_pt, *srt_key;    // entries sorted by centroid slot (sign in bit 31 of srt_pt)
-    int *hist, *cursor;       // kg + 1
+    double *Sc, *Sg, *Sd;     // cumulative drifts (kg, g, 1), FP64
+    float *Scu, *Scd;         // FP32 copies of Sc rounded up / down
+    float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
+    float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
+    int *L1;                  // point ids failing the point-level filter (filter order)
+    int *L1s;                 // the same ids sorted by assigned slot
+    int4 *tlist;              // per tile of sorted L1: (group, point mask lo, hi, 0), g entries per tile
+    int *tcnt;                // entries used per tile
+    float4 *ps4;              // per position: ub, min closed-group bound, U* of an uncertain point
+    int *psf;                 // per position: bit 0 open (filter to distance kernel), bit 2 uncertain
+    int *mv_pt, *mv_old, *mv_new;   // per position: point, old slot, new slot (-1: did not move)
+    int *srt_pt, *srt_key;    // update entries sorted by centroid slot (sign in bit 31 of srt_pt)
+    int *hist, *cursor;       // kg + 1: centroid update sort
+    int *hist1, *cursor1;     // kg + 1: L1 sort
     unsigned long long *ctr;  // NCTR counters of the running iteration
-    long long *stats;         // STATS_CAP x 8
+    long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
     float *scal;              // [0] max ||c_hat||, [1] max ||c - c_hat||
 };
@@ -112,41 +125,61 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((unsigned)h) << 16); }
 
+// ------------------------------------------------------- offset-form bounds
+// (each FP32 operation rounds to nearest; the f_up / f_dn step covers it)
+__device__ __forceinline__ float ub_now(float u, float scu) { return f_up(u + scu); }
+__device__ __forceinline__ float lb_now(float v, float sgu) { return f_dn(v - sgu); }
+__device__ __forceinline__ float store_u(float ub, float scd) { return f_up(ub - scd); }
+__device__ __forceinline__ float store_lb(float lb, float sgd) { return f_dn(lb + sgd); }
+// Group q may hold the nearest centroid unless ub < lb_q now, i.e. unless
+// ub + Sg[q] < v_q; s + one ulp bounds the exact sum from above (s >= 0).
+__device__ __forceinline__ bool group_open(float ub, float sgu, float v)
+{
+    const float s = ub + sgu;
+    return !(__uint_as_float(__float_as_uint(s) + 1u) < v);
+}
+
 // ------------------------------------------------------- error bounds
 // FP32 direct-form squared distance: four accumulators (coordinate i goes to
 // accumulator i mod 4, fused multiply-add in coordinate order), combined as
 // (a0 + a1) + (a2 + a3).  With m = ceil(d / 4) terms per accumulator the
 // relative error of the result is below (m + 4) u, u = 2^-24 (rounded
-// difference squared: 2u; m fused adds; two combining adds).  EPS2 doubles
-// the margin.
+// difference squared: 2u; m fused adds; two combining adds).  The bound used
+// doubles the margin.  The same constant covers the 16-lane tree of the
+// recheck (d/16 sequential terms and four combining levels).
 __host__ __device__ __forceinline__ double eps2_direct(int d)
 {
     return (double)((d + 3) / 4 + 8) * 5.9604644775390625e-08;   // * 2^-24
 }
-// Upper / lower bound on the true distance from a direct-form FP32 d^2.
-__device__ __forceinline__ float dist_hi(float d2, double eps2)
+// Upper / lower bound on the true distance from a direct-form FP32 d^2 with
+// relative error eps2, widened by rho (rho = 0 for FP32 inputs; the BF16
+// rounding residuals of both vectors otherwise).
+__device__ __forceinline__ float dist_hi(float d2, double eps2, double rho = 0.0)
 {
-    return d2f_up(sqrt((double)d2 * (1.0 + eps2)) * (1.0 + 0x1p-46));
+    return d2f_up((sqrt((double)d2 * (1.0 + eps2)) + rho) * (1.0 + 0x1p-46));
 }
-__device__ __forceinline__ float dist_lo(float d2, double eps2)
+__device__ __forceinline__ float dist_lo(float d2, double eps2, double rho = 0.0)
 {
-    double v = (double)d2 * (1.0 - eps2);
-    return v > 0.0 ? d2f_dn(sqrt(v) * (1.0 - 0x1p-46)) : 0.f;
+    if (!(d2 < __builtin_huge_valf())) return d2;
+    const double v = (double)d2 * (1.0 - eps2);
+    const double r = (v > 0.0 ? sqrt(v) * (1.0 - 0x1p-46) : 0.0) - rho;
+    return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
 // BF16 MFMA estimate v = ||xb||^2 + ||cb||^2 - 2 xb.cb of ||xb - cb||^2:
 //   | v - ||xb - cb||^2 | <= eta,  | ||xb - cb|| - ||x - c|| | <= rho,
 // so the true distance lies in [sqrt(max(v - eta, 0)) - rho, sqrt(v + eta) + rho].
 __device__ __forceinline__ float mfma_hi(float v, double eta, double rho)
 {
-    double t = (double)v + eta;
+    if (!(v < __builtin_huge_valf())) return v;
+    const double t = (double)v + eta;
     return d2f_up((sqrt(t > 0.0 ? t : 0.0) + rho) * (1.0 + 0x1p-46));
 }
 __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 {
     if (!(v < __builtin_huge_valf())) return v;
-    double t = (double)v - eta;
-    double s = t > 0.0 ? sqrt(t) * (1.0 - 0x1p-46) : 0.0;
-    double r = s - rho;
+    const double t = (double)v - eta;
+    const double s = t > 0.0 ? sqrt(t) * (1.0 - 0x1p-46) : 0.0;
+    const double r = s - rho;
     return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
 // eta of one point: the products of BF16 values are exact in FP32, so the
@@ -156,7 +189,7 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 // undocumented internal accumulation order of the matrix cores.
 __device__ __forceinline__ double mfma_eta(float xn, float bmax, int ldb)
 {
-    double a = sqrt((double)xn) + (double)bmax;
+    const double a = sqrt((double)xn) + (double)bmax;
     return 2.0 * (double)(ldb + 4) * 5.9604644775390625e-08 * a * a * (1.0 + 0x1p-20);
 }
 
@@ -170,7 +203,7 @@ __device__ __forceinline__ Best3 merge3(Best3 a, Best3 b)
 {
     // b wins on a smaller value, or an equal value at a lower slot (within one
     // group slots are in ascending original index, so this is the tie rule).
-    bool nb = (b.m1 < a.m1) || (b.m1 == a.m1 && b.s1 < a.s1);
+    const bool nb = (b.m1 < a.m1) || (b.m1 == a.m1 && b.s1 < a.s1);
     Best3 r;
     r.m2 = nb ? fminf(a.m1, b.m2) : fminf(a.m2, b.m1);
     r.m1 = nb ? b.m1 : a.m1;
@@ -193,14 +226,14 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)
 // lane of the wave must call it.  Returns the slot of the calling lane, or -1.
 __device__ __forceinline__ long long wave_append(unsigned long long *ctr, bool pred)
 {
-    unsigned long long m = __ballot(pred);
+    const unsigned long long m = __ballot(pred);
     if (m == 0ull) return -1;
-    int lane = lane_id();
-    int leader = __ffsll((long long)m) - 1;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
     unsigned long long base = 0;
     if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
-    unsigned lo = __shfl((unsigned)(base & 0xFFFFFFFFull), leader);
-    unsigned hi = __shfl((unsigned)(base >> 32), leader);
+    const unsigned lo = __shfl((unsigned)(base & 0xFFFFFFFFull), leader);
+    const unsigned hi = __shfl((unsigned)(base >> 32), leader);
     base = ((unsigned long long)hi << 32) | lo;
     if (!pred) return -1;
     return (long long)(base + __popcll(m & ((1ull << lane) - 1ull)));
@@ -211,46 +244,10 @@ __device__ __forceinline__ float wave_min(float v)
     for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
     return v;
 }
-__device__ __forceinline__ float wave_max(float v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
-}
 __device__ __forceinline__ double wave_sum_d(double v)
 {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
-}
-
-// Lazily accumulated drift between stamp tx and iteration t: the bounds stored
-// at tx were valid for the centroids used by iteration tx; the ring holds the
-// cumulative drift S(tau) after update tau at index tau mod W.  The result
-// is rounded up (every FP64 rounding error is below 2^-52 of the larger sum).
-__device__ __forceinline__ double drift_between(const double *ring, int stride, int idx, int t, int tx, int W)
-{
-    double now = ring[(size_t)((t - 1) % W) * stride + idx];
-    double then = ring[(size_t)((tx - 1) % W) * stride + idx];
-    return (now - then) + now * 0x1p-44;
-}
-// The same difference rounded down (never below zero).
-__device__ __forceinline__ double drift_between_dn(const double *ring, int stride, int idx, int t, int tx, int W)
-{
-    double now = ring[(size_t)((t - 1) % W) * stride + idx];
-    double then = ring[(size_t)((tx - 1) % W) * stride + idx];
-    double v = (now - then) - now * 0x1p-44;
-    return v > 0.0 ? v : 0.0;
-}
-// An upper bound stored at tx, moved to iteration t (FP64, rounded up).
-__device__ __forceinline__ double up_eff(float stored, double drift)
-{
-    double v = (double)stored + drift;
-    return v + fabs(v) * 0x1p-50;
-}
-// A lower bound stored at tx, moved to iteration t (FP64, rounded down).
-__device__ __forceinline__ double lo_eff(float stored, double drift)
-{
-    double v = (double)stored - drift;
-    return v - fabs(v) * 0x1p-50;
 }
 
 }  // namespace kp

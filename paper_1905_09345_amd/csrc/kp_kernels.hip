@@ -1,27 +1,29 @@
 // HIP kernels (gfx950) of the filtered K-means iteration.
 //
 // One iteration t >= 2 of a problem runs, in stream order:
-//   k_begin         clear the iteration's counters
-//   k_bound_filter  point-level filter: bring each point's upper bound and
-//                   point-level lower bound to iteration t and keep the points
-//                   where ub < lbp fails (list L1)              [point-level filter]
-//   k_assign_*      for the points of L1: tighten ub to the exact distance to
-//                   the assigned centroid, retest, then test every group's
-//                   lower bound against ub and compute the distances of the
+//   k_begin         clear the iteration's counters and histograms
+//   k_bound_filter  point-level filter: each point's upper bound and
+//                   point-level lower bound brought to this iteration; the
+//                   points where ub < lbp fails form list L1  [point-level filter]
+//   k_key_hist, k_scan, k_l1_scatter
+//                   L1 sorted by assigned centroid, so that a 64-point tile
+//                   shares its surviving groups
+//   k_assign_*      for the points of L1: tighten ub to the distance to the
+//                   assigned centroid, retest, then test every group's lower
+//                   bound against ub and compute the distances of the
 //                   surviving (point, group) pairs; new assignment and bounds
-//                                                  [group-level filter + distance calculator]
+//                                          [group-level filter + distance calculator]
 //   k_recheck       (BF16 mode) re-decide in FP32 direct form the points whose
 //                   BF16 decision is not certain under the error bound
 //   k_hist, k_scan, k_scatter, k_segsum
-//                   sort the moved points by centroid and add/subtract their
-//                   coordinates into FP64 centroid sums       [centroid update]
+//                   sort the moved points by centroid and add / subtract
+//                   their coordinates into FP64 centroid sums    [centroid update]
 //   k_centroids     new means (FP64), their FP32 / BF16 copies, drifts
-//   k_drift         per-group and global maximum drift into the FP64 rings
-// Iteration 1 replaces the two filter kernels by the dense form of k_assign_*
-// (every distance).  The filters follow the paper's two-level design
-// (Section 1: point-level and group-level filter ahead of the distance
-// calculator); the bound bookkeeping is the triangle inequality
-// |d(x, c') - d(x, c)| <= ||c' - c|| applied to each centroid's drift.
+//   k_drift         per-group and global maximum drift, cumulative sums
+// Iteration 1 replaces the filter, the sort and the survivor form of
+// k_assign_* by the dense form (every distance).  The two filters and the
+// distance calculator are the three parts the paper names (Section 1); the
+// result is that of standard K-means (Abstract).
 #include "kp_device.h"
 #include "kp_launch.h"
 #include <climits>
@@ -29,6 +31,25 @@
 namespace kp {
 
 #define KP_INF __builtin_huge_valf()
+
+// Indices read back from memory are clamped to their arrays, so that a
+// corrupted entry can only give a wrong result, never an access out of bounds.
+__device__ __forceinline__ int clamp_slot(const ProbDev &P, int s) { return min(max(s, 0), P.kg - 1); }
+__device__ __forceinline__ int clamp_pid(const ProbDev &P, int i) { return min(max(i, 0), (int)P.n - 1); }
+// Positions of the running iteration: every point in the dense iteration,
+// every entry of the sorted L1 otherwise.  Each position writes its own
+// moved entry (new slot or -1) and its recheck flag, so no list is appended.
+__device__ __forceinline__ long long positions(const ProbDev &P);
+// A list length kept in a counter (at most one entry per point).
+__device__ __forceinline__ long long list_len(const ProbDev &P, int c)
+{
+    const unsigned long long v = P.ctr[c];
+    return v < (unsigned long long)P.n ? (long long)v : (long long)P.n;
+}
+__device__ __forceinline__ long long positions(const ProbDev &P)
+{
+    return P.ctr[CTR_DENSE] ? P.n : list_len(P, CTR_L1);
+}
 
 // ===================================================================== prep
 // BF16 shadow of the points, ||xb||^2 and the rounding residual ||x - xb||.
@@ -40,13 +61,13 @@ __global__ __launch_bounds__(256) void k_prep(ProbDev P)
         uint16_t *xb = P.Xb + i * P.ldb;
         double s = 0.0, r = 0.0;
         for (int j = 0; j < P.ldb; j += 2) {
-            float v0 = j < P.d ? x[j] : 0.f;
-            float v1 = j + 1 < P.d ? x[j + 1] : 0.f;
-            uint16_t h0 = f2bf(v0), h1 = f2bf(v1);
-            float b0 = bf2f(h0), b1 = bf2f(h1);
+            const float v0 = j < P.d ? x[j] : 0.f;
+            const float v1 = j + 1 < P.d ? x[j + 1] : 0.f;
+            const uint16_t h0 = f2bf(v0), h1 = f2bf(v1);
+            const float b0 = bf2f(h0), b1 = bf2f(h1);
             *(uint32_t *)(xb + j) = (uint32_t)h0 | ((uint32_t)h1 << 16);
             s += (double)b0 * b0 + (double)b1 * b1;
-            double e0 = (double)v0 - b0, e1 = (double)v1 - b1;
+            const double e0 = (double)v0 - b0, e1 = (double)v1 - b1;
             r += e0 * e0 + e1 * e1;
         }
         P.xn[i] = (float)s;
@@ -120,27 +141,32 @@ __global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
 
 // ================================================================== drifts
 // Single workgroup.  After the update of iteration t: per-group maximum
-// drift, global maximum, the cumulative FP64 rings at index t mod W, the
-// error-bound scalars and the iteration's statistics.  first=1 at init (t=0).
+// drift, the global maximum, the cumulative sums (FP64, each increment
+// rounded up) and their FP32 copies, the error-bound scalars and the
+// iteration's statistics.  first = 1 at init.
 __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
 {
     __shared__ double red[1024];
     __shared__ float redf[2][1024];
     const int tid = threadIdx.x;
-    const int t = first ? 0 : (*P.iter + 1);
-    const int W = P.W;
-    const int cur = t % W, prv = (t + W - 1) % W;
+    const double up = 1.0 + 0x1p-50;
     double gmax = 0.0;
     for (int g = tid; g < P.g; g += blockDim.x) {
         double m = 0.0;
         const int s0 = P.gstart[g], ns = P.gsize[g];
         for (int r = 0; r < ns; ++r) m = fmax(m, P.delta[s0 + r]);
-        P.Sg[(size_t)cur * P.g + g] = (t == 0 ? 0.0 : P.Sg[(size_t)prv * P.g + g]) + m;
+        const double sg = first ? 0.0 : (P.Sg[g] + m) * up;
+        P.Sg[g] = sg;
+        P.Sgu[g] = d2f_up(sg);
+        P.Sgd[g] = d2f_dn(sg);
         gmax = fmax(gmax, m);
     }
     float bmax = 0.f, rmax = 0.f;
     for (int s = tid; s < P.kg; s += blockDim.x) {
-        P.Sc[(size_t)cur * P.kg + s] = (t == 0 ? 0.0 : P.Sc[(size_t)prv * P.kg + s]) + P.delta[s];
+        const double sc = first ? 0.0 : (P.Sc[s] + P.delta[s]) * up;
+        P.Sc[s] = sc;
+        P.Scu[s] = d2f_up(sc);
+        P.Scd[s] = d2f_dn(sc);
         if (P.perm[s] >= 0) {
             bmax = fmaxf(bmax, P.cn[s]);
             rmax = fmaxf(rmax, P.cr[s]);
@@ -159,19 +185,24 @@ __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
         __syncthreads();
     }
     if (tid == 0) {
-        P.Sd[cur] = (t == 0 ? 0.0 : P.Sd[prv]) + red[0];
+        const double sd = first ? 0.0 : (P.Sd[0] + red[0]) * up;
+        P.Sd[0] = sd;
+        P.Sdud[0] = d2f_up(sd);
+        P.Sdud[1] = d2f_dn(sd);
         P.scal[0] = d2f_up(sqrt((double)redf[0][0]) * (1.0 + 0x1p-46));
         P.scal[1] = redf[1][0];
         if (!first) {
-            long long *rec = P.stats + (size_t)((t - 1) % STATS_CAP) * 8;
+            const int t = *P.iter + 1;
+            long long *rec = P.stats + (size_t)((t - 1) % STATS_CAP) * 16;
             rec[0] = t;
             rec[1] = (long long)P.ctr[CTR_DENSE];
-            rec[2] = (long long)P.ctr[CTR_L1];
+            rec[2] = list_len(P, CTR_L1);
             rec[3] = (long long)P.ctr[CTR_PAIRS];
             rec[4] = (long long)P.ctr[CTR_DIST];
             rec[5] = (long long)P.ctr[CTR_L3];
             rec[6] = (long long)P.ctr[CTR_MOVED];
-            rec[7] = 0;
+            rec[7] = __double_as_longlong(red[0]);
+            rec[8] = (long long)P.ctr[CTR_VISITS];
             *P.iter = t;
         }
     }
@@ -182,39 +213,140 @@ __global__ void k_begin(ProbDev P, int dense)
 {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < NCTR) P.ctr[tid] = (tid == CTR_DENSE) ? (unsigned long long)dense : 0ull;
-    for (int s = tid; s <= P.kg; s += gridDim.x * blockDim.x) P.hist[s] = 0;
+    for (int s = tid; s <= P.kg; s += gridDim.x * blockDim.x) {
+        P.hist[s] = 0;
+        P.hist1[s] = 0;
+    }
 }
 
 // ========================================================== bound filter
-// Point-level filter.  ub_eff = ub + drift of the own centroid since tx,
-// lbp_eff = lbp - largest drift of any centroid since tx.  A point is kept
-// (list L1) unless ub_eff < lbp_eff; points whose stamp is W-1 iterations old
-// are kept as well so that their stored bounds are refreshed before the
-// drift ring wraps.
+// Point-level filter over all points, one chunk of 16 points per thread
+// (256 threads = 4096 points per workgroup step).  A point is kept in L1
+// unless ub < lbp after both are brought to this iteration.  Positions come
+// from one atomic per workgroup step; within it, the order is that of the
+// points.
+constexpr int BF_PER_THREAD = 16;
+
 __global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
 {
-    const int t = *P.iter + 1;
-    const int W = P.W;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < P.n; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        bool keep = false;
-        if (i < P.n) {
-            const PointState s = P.st[i];
-            const double ub = up_eff(s.ub, drift_between(P.Sc, P.kg, s.a, t, s.tx, W));
-            const double lp = lo_eff(s.lbp, drift_between(P.Sd, 1, 0, t, s.tx, W));
-            keep = !(ub < lp) || (t - s.tx >= W - 1);
+    __shared__ int wcount[4];
+    __shared__ unsigned long long base_s;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    const float sdu = P.Sdud[0];
+    const int64_t chunk = 256 * BF_PER_THREAD;
+    for (int64_t b0 = (int64_t)blockIdx.x * chunk; b0 < P.n; b0 += (int64_t)gridDim.x * chunk) {
+        unsigned long long masks[BF_PER_THREAD];
+        int mine = 0;
+#pragma unroll
+        for (int r = 0; r < BF_PER_THREAD; ++r) {
+            const int64_t i = b0 + (int64_t)r * 256 + tid;
+            bool keep = false;
+            if (i < P.n) {
+                const PointState s = P.st[i];
+                keep = !(ub_now(s.u, P.Scu[clamp_slot(P, s.a)]) < lb_now(s.p, sdu));
+            }
+            masks[r] = __ballot(keep);
+            mine += __popcll(masks[r]);
         }
-        const long long pos = wave_append(&P.ctr[CTR_L1], keep);
-        if (pos >= 0) P.L1[pos] = (int)i;
+        if (lane == 0) wcount[wv] = mine;
+        __syncthreads();
+        if (tid == 0) {
+            const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+            base_s = tot ? atomicAdd(&P.ctr[CTR_L1], (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long pos = base_s;
+        for (int w = 0; w < wv; ++w) pos += (unsigned long long)wcount[w];
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int r = 0; r < BF_PER_THREAD; ++r) {
+            if ((masks[r] >> lane) & 1ull) P.L1[pos + __popcll(masks[r] & below)] = (int)(b0 + (int64_t)r * 256 + tid);
+            pos += (unsigned long long)__popcll(masks[r]);
+        }
+        __syncthreads();
+    }
+}
+
+// ======================================================= L1 sort by slot
+// key of L1 entry e: the slot its point is assigned to.
+__global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
+{
+    __shared__ int h[HIST_LDS];
+    const long long n1 = list_len(P, CTR_L1);
+    const bool lds = P.kg <= HIST_LDS;
+    if (lds)
+        for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n1;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int key = clamp_slot(P, P.st[clamp_pid(P, P.L1[e])].a);
+        if (lds) atomicAdd(&h[key], 1);
+        else atomicAdd(&P.hist1[key], 1);
+    }
+    __syncthreads();
+    if (lds)
+        for (int i = threadIdx.x; i < P.kg; i += blockDim.x)
+            if (h[i]) atomicAdd(&P.hist1[i], h[i]);
+}
+
+// Exclusive scan of hist[0..n) into cursor (single workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_scan(const int *hist, int *cursor, int n)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = tid * per, e = min(n, b + per);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += hist[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int i = b; i < e; ++i) {
+        cursor[i] = run;
+        run += hist[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
+{
+    __shared__ int h[HIST_LDS];
+    __shared__ int base[HIST_LDS];
+    const long long E = list_len(P, CTR_L1);
+    const long long b0 = E * blockIdx.x / gridDim.x, b1 = E * (blockIdx.x + 1) / gridDim.x;
+    if (P.kg > HIST_LDS) {
+        for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+            const int pid = clamp_pid(P, P.L1[e]);
+            P.L1s[atomicAdd(&P.cursor1[clamp_slot(P, P.st[pid].a)], 1)] = pid;
+        }
+        return;
+    }
+    if (b0 >= b1) return;   // uniform per block
+    for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) atomicAdd(&h[clamp_slot(P, P.st[clamp_pid(P, P.L1[e])].a)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < P.kg; i += blockDim.x) {
+        base[i] = h[i] ? atomicAdd(&P.cursor1[i], h[i]) : 0;
+        h[i] = 0;
+    }
+    __syncthreads();
+    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        const int pid = clamp_pid(P, P.L1[e]);
+        const int key = clamp_slot(P, P.st[pid].a);
+        P.L1s[base[key] + atomicAdd(&h[key], 1)] = pid;
     }
 }
 
 // ===================================================== FP32 direct distance
 // Squared distance in the direct form with accumulator i mod 4 (see
 // eps2_direct).  x has `DMAX` registers, zero beyond d; c is a row padded
-// with zeros to ldc (a multiple of 4).  The same order is used everywhere a
-// direct distance is computed, so equal inputs give equal results.
+// with zeros to ldc (a multiple of 4).
 template <int DMAX>
 __device__ __forceinline__ float direct_d2(const float (&x)[DMAX], const float *__restrict__ c, int ldc)
 {
@@ -233,13 +365,13 @@ __device__ __forceinline__ float direct_d2(const float (&x)[DMAX], const float *
     return (a0 + a1) + (a2 + a3);
 }
 
-// Same arithmetic with both rows read from memory (x unpadded, length d).
+// Same arithmetic with both rows read from memory (x unpadded, length d; c
+// padded with zeros to a multiple of 4).
 __device__ __forceinline__ float direct_d2_mem(const float *__restrict__ x, const float *__restrict__ c, int d)
 {
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int i = 0;
     if ((d & 3) == 0) {
-        for (; i < d; i += 4) {
+        for (int i = 0; i < d; i += 4) {
             const float4 xv = *(const float4 *)(x + i);
             const float4 cv = *(const float4 *)(c + i);
             const float t0 = xv.x - cv.x, t1 = xv.y - cv.y, t2 = xv.z - cv.z, t3 = xv.w - cv.w;
@@ -249,7 +381,7 @@ __device__ __forceinline__ float direct_d2_mem(const float *__restrict__ x, cons
             a3 = fmaf(t3, t3, a3);
         }
     } else {
-        for (; i < d; i += 4) {
+        for (int i = 0; i < d; i += 4) {
             const float t0 = x[i] - c[i];
             const float t1 = (i + 1 < d ? x[i + 1] : 0.f) - c[i + 1];
             const float t2 = (i + 2 < d ? x[i + 2] : 0.f) - c[i + 2];
@@ -263,189 +395,120 @@ __device__ __forceinline__ float direct_d2_mem(const float *__restrict__ x, cons
     return (a0 + a1) + (a2 + a3);
 }
 
+// Direct form on BF16 rows (both padded with zeros to ldb): the differences
+// of BF16 values are exact in FP32, so the result is ||xb - cb||^2 with the
+// relative error of eps2_direct(ldb).
+__device__ __forceinline__ float direct_d2_bf16(const uint16_t *__restrict__ x, const uint16_t *__restrict__ c,
+                                                int ldb)
+{
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int i = 0; i < ldb; i += 8) {
+        const uint4 xv = *(const uint4 *)(x + i);
+        const uint4 cv = *(const uint4 *)(c + i);
+        const unsigned xs[4] = {xv.x, xv.y, xv.z, xv.w}, cs[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float tlo = __uint_as_float(xs[w] << 16) - __uint_as_float(cs[w] << 16);
+            const float thi = __uint_as_float(xs[w] & 0xFFFF0000u) - __uint_as_float(cs[w] & 0xFFFF0000u);
+            // coordinates i + 2w (accumulator 2w mod 4) and i + 2w + 1
+            if (w & 1) {
+                a2 = fmaf(tlo, tlo, a2);
+                a3 = fmaf(thi, thi, a3);
+            } else {
+                a0 = fmaf(tlo, tlo, a0);
+                a1 = fmaf(thi, thi, a1);
+            }
+        }
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
 // Is (v, slot sa) before (w, slot sb) in (distance, original index) order?
+// A slot outside 0..kg-1 (the "none yet" -1 or a skipped block's sentinel)
+// never wins and loses every tie.
 __device__ __forceinline__ bool before(const ProbDev &P, float v, int sa, float w, int sb)
 {
+    if ((unsigned)sa >= (unsigned)P.kg) return false;
     if (v < w) return true;
-    if (v > w || sb < 0) return sb < 0 && v == w;
+    if (v > w) return false;
+    if ((unsigned)sb >= (unsigned)P.kg) return true;
     return P.perm[sa] < P.perm[sb];
 }
 
-// Per-tile bookkeeping shared by both engines ---------------------------------
-struct TileState {
-    int pid;          // point id (-1: lane empty)
-    bool active;      // still needs the group stage
-    int a, ga, tx;    // old slot, its group, stamp (survivor mode)
-    float d2a;        // direct d^2 to the old centroid
-    float ubt;        // tightened upper bound on d(x, c_a)
-    bool a_sep;       // old centroid tracked separately (its group did not survive)
-    float lbe_a;      // effective lower bound of the old group
-};
 
-// Load the tile's points, tighten ub, retest the point-level bound.  Points
-// that pass after tightening get their stored ub replaced (stamp unchanged:
-// the stored value is shifted back by the drift accumulated since tx).
-__device__ __forceinline__ TileState tile_begin(const ProbDev &P, bool dense, long long tl, long long count,
-                                                int t, double eps2)
+// ====================================================== per-point decisions
+// Running best of one point over the groups examined: best value, its slot
+// and group, the second value of the best's group and the overall second.
+struct Run {
+    float bd, sec, bm2;
+    int bs, bg;
+};
+__device__ __forceinline__ void run_init(Run &r)
 {
-    TileState ts;
-    const int lane = lane_id();
-    const long long idx = tl * WAVE + lane;
-    ts.pid = -1;
-    ts.active = false;
-    ts.a = -1;
-    ts.ga = -1;
-    ts.tx = t;
-    ts.d2a = KP_INF;
-    ts.ubt = KP_INF;
-    ts.a_sep = false;
-    ts.lbe_a = KP_INF;
-    if (idx < count) ts.pid = dense ? (int)idx : P.L1[idx];
-    if (ts.pid < 0) return ts;
-    ts.active = true;
-    if (dense) return ts;
-    const PointState s = P.st[ts.pid];
-    ts.a = s.a;
-    ts.tx = s.tx;
-    ts.ga = P.slot_group[s.a];
-    const int W = P.W;
-    const double lp = lo_eff(s.lbp, drift_between(P.Sd, 1, 0, t, s.tx, W));
-    ts.d2a = direct_d2_mem(P.X + (size_t)ts.pid * P.d, P.c32 + (size_t)s.a * P.ldc, P.d);
-    ts.ubt = dist_hi(ts.d2a, eps2);
-    if ((double)ts.ubt < lp && (t - s.tx) < W - 1) {
-        const double shifted = (double)ts.ubt - drift_between_dn(P.Sc, P.kg, s.a, t, s.tx, W);
-        P.st[ts.pid].ub = d2f_up(shifted + fabs(shifted) * 0x1p-50);
-        ts.active = false;
-        return ts;
+    r.bd = KP_INF;
+    r.sec = KP_INF;
+    r.bm2 = KP_INF;
+    r.bs = -1;
+    r.bg = -1;
+}
+__device__ __forceinline__ void run_fold(const ProbDev &P, Run &r, const Best3 &gb, int g)
+{
+    // A group result of +inf carries no slot (a skipped MFMA block): never a best.
+    if (!(gb.m1 < KP_INF)) return;
+    if (before(P, gb.m1, gb.s1, r.bd, r.bs)) {
+        r.sec = fminf(r.bd, gb.m2);
+        r.bd = gb.m1;
+        r.bs = gb.s1;
+        r.bg = g;
+        r.bm2 = gb.m2;
+    } else {
+        r.sec = fminf(r.sec, gb.m1);
     }
-    const float lbv = P.lb[(size_t)ts.pid * P.gs + ts.ga];
-    ts.lbe_a = d2f_dn(lo_eff(lbv, drift_between(P.Sg, P.g, ts.ga, t, s.tx, W)));
-    ts.a_sep = (ts.ubt < ts.lbe_a);
-    return ts;
 }
 
-// ============================================== FP32 engine: lane per point
-// x lives in registers; the centroid rows of a group are uniform across the
-// wave (scalar loads).  No recheck is needed: decisions are taken on direct
-// FP32 values whose relative error (eps2_direct) is far below the near-tie
-// band, and every bound carries that error.
-template <int DMAX, bool DENSE>
-__global__ __launch_bounds__(256) void k_assign_f32(ProbDev P)
+// FP32 direct distances of a lane's point (x in registers) to every member of
+// group g; the rows are uniform across the wave (scalar loads).
+template <int DMAX>
+__device__ __forceinline__ Best3 direct_group(const ProbDev &P, int g, const float (&x)[DMAX])
 {
-    const int lane = lane_id();
-    const int wpb = blockDim.x / WAVE;
-    const int t = *P.iter + 1;
-    const int W = P.W;
-    const double eps2 = eps2_direct(P.d);
-    const long long count = DENSE ? P.n : (long long)P.ctr[CTR_L1];
-    const long long ntiles = (count + WAVE - 1) / WAVE;
-    unsigned long long n_pairs = 0, n_dist = 0;
-    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)gridDim.x * wpb) {
-        TileState ts = tile_begin(P, DENSE, tl, count, t, eps2);
-        const bool act = ts.active;
-        if (__ballot(act) == 0ull) continue;
-        float x[DMAX];
-#pragma unroll
-        for (int i = 0; i < DMAX; ++i) x[i] = 0.f;
-        if (act) {
-            const float *xr = P.X + (size_t)ts.pid * P.d;
-#pragma unroll
-            for (int i = 0; i < DMAX; ++i)
-                if (i < P.d) x[i] = xr[i];
-        }
-        // running best over everything examined (old centroid included when
-        // its group did not survive)
-        float bd = KP_INF, sec = KP_INF, bm2 = KP_INF, minnc = KP_INF;
-        int bs = -1, bg = -1;
-        if (!DENSE && ts.a_sep) {
-            bd = ts.d2a;
-            bs = ts.a;
-            bg = -1;   // not from a computed group
-        }
-        float *lbrow = act ? P.lb + (size_t)ts.pid * P.gs : nullptr;
-        for (int g4 = 0; g4 < P.g; g4 += 4) {
-            float4 lbq = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (!DENSE && act) lbq = *(const float4 *)(lbrow + g4);
-            float outv[4] = {KP_INF, KP_INF, KP_INF, KP_INF};
-            const float lbin[4] = {lbq.x, lbq.y, lbq.z, lbq.w};
-#pragma unroll
-            for (int gg = 0; gg < 4; ++gg) {
-                const int g = g4 + gg;
-                if (g >= P.g) break;
-                bool cand;
-                float lbe = KP_INF;
-                if (DENSE) {
-                    cand = act;
-                } else {
-                    if (act) lbe = d2f_dn(lo_eff(lbin[gg], drift_between(P.Sg, P.g, g, t, ts.tx, W)));
-                    cand = act && !(ts.ubt < lbe);
-                }
-                const unsigned long long m = __ballot(cand);
-                float gm1 = KP_INF, gm2 = KP_INF;
-                int gs1 = -1;
-                if (m) {
-                    const int s0 = P.gstart[g], ns = P.gsize[g];
-                    for (int r = 0; r < ns; ++r) {
-                        const float v = direct_d2<DMAX>(x, P.c32 + (size_t)(s0 + r) * P.ldc, P.ldc);
-                        if (v < gm1) {
-                            gm2 = gm1;
-                            gm1 = v;
-                            gs1 = s0 + r;
-                        } else {
-                            gm2 = fminf(gm2, v);
-                        }
-                    }
-                    n_pairs += (unsigned long long)__popcll(m);
-                    n_dist += (unsigned long long)__popcll(m) * (unsigned long long)ns;
-                }
-                if (cand) {
-                    outv[gg] = dist_lo(gm1, eps2);
-                    if (before(P, gm1, gs1, bd, bs)) {
-                        sec = fminf(bd, gm2);
-                        bd = gm1;
-                        bs = gs1;
-                        bg = g;
-                        bm2 = gm2;
-                    } else {
-                        sec = fminf(sec, gm1);
-                    }
-                } else if (act) {
-                    outv[gg] = lbe;
-                    minnc = fminf(minnc, lbe);
-                }
-            }
-            if (act) *(float4 *)(lbrow + g4) = make_float4(outv[0], outv[1], outv[2], outv[3]);
-        }
-        bool moved = false;
-        int oldslot = DENSE ? -1 : ts.a;
-        if (act) {
-            if (bg >= 0) lbrow[bg] = dist_lo(bm2, eps2);
-            float lbp = fminf(dist_lo(sec, eps2), minnc);
-            if (!DENSE && ts.a_sep && bs != ts.a) {
-                const float v = fminf(ts.lbe_a, dist_lo(ts.d2a, eps2));
-                lbrow[ts.ga] = v;
-                lbp = fminf(lbp, v);
-            }
-            PointState ns;
-            ns.a = bs;
-            ns.ub = dist_hi(bd, eps2);
-            ns.lbp = lbp;
-            ns.tx = t;
-            P.st[ts.pid] = ns;
-            moved = (bs != oldslot);
-        }
-        const long long pos = wave_append(&P.ctr[CTR_MOVED], moved);
-        if (pos >= 0) {
-            P.mv_pt[pos] = ts.pid;
-            P.mv_old[pos] = oldslot;
-            P.mv_new[pos] = bs;
+    Best3 b = {KP_INF, -1, KP_INF};
+    const int s0 = P.gstart[g], ns = P.gsize[g];
+    for (int r = 0; r < ns; ++r) {
+        const float v = direct_d2<DMAX>(x, P.c32 + (size_t)(s0 + r) * P.ldc, P.ldc);
+        if (v < b.m1) {
+            b.m2 = b.m1;
+            b.m1 = v;
+            b.s1 = s0 + r;
+        } else {
+            b.m2 = fminf(b.m2, v);
         }
     }
-    if (lane == 0 && n_pairs) {
-        atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
-        atomicAdd(&P.ctr[CTR_DIST], n_dist);
+    return b;
+}
+
+// FP32 decision and writes (no recheck: decisions on direct FP32 values).
+// `r` already holds the old centroid when a_sep.
+__device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense, int a, int ga, bool a_sep,
+                                           float d2a, float lbe_a, float minnc, const Run &r, double eps2,
+                                           float sdd)
+{
+    float *lbrow = P.lb + (size_t)pid * P.gs;
+    if (r.bg >= 0) lbrow[r.bg] = store_lb(dist_lo(r.bm2, eps2), P.Sgd[r.bg]);
+    float lbp = fminf(dist_lo(r.sec, eps2), minnc);
+    if (!dense && a_sep && r.bs != a) {
+        const float va = fminf(lbe_a, dist_lo(d2a, eps2));
+        lbrow[ga] = store_lb(va, P.Sgd[ga]);
+        lbp = fminf(lbp, va);
     }
+    // r.bs >= 0 whenever some distance was finite; otherwise keep the old slot
+    const int win = r.bs >= 0 ? r.bs : (a >= 0 ? a : 0);
+    PointState ns;
+    ns.a = win;
+    ns.u = store_u(dist_hi(r.bd, eps2), P.Scd[win]);
+    ns.p = store_lb(lbp, sdd);
+    ns.pad = 0;
+    P.st[pid] = ns;
+    return win != (dense ? -1 : a);
 }
 
 // ============================================== BF16 engine: MFMA per group
@@ -494,326 +557,769 @@ __device__ __forceinline__ Best3 transpose_reduce(const Best3 (&T)[4])
     return merge3(keep, shfl_xor3(send, 16));
 }
 
-template <int KS, bool DENSE>
-__global__ __launch_bounds__(256) void k_assign_bf16(ProbDev P)
+// B fragments of the tile: point 16*blk + (l & 15), k = ks*32 + 8*(l >> 4) .. +7.
+template <int KS>
+__device__ __forceinline__ void load_bfrag(const ProbDev &P, int pid, unsigned long long amask, bf16x8 (&bx)[4][KS],
+                                           float (&xnB)[4])
+{
+    const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+        const int src = 16 * blk + col;
+        const int p = __shfl(pid, src);
+        const bool ok = (amask >> src) & 1ull;
+        xnB[blk] = ok ? P.xn[p] : 0.f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ok) bx[blk][ks] = *(const bf16x8 *)(P.Xb + (size_t)p * P.ldb + ks * 32 + 8 * quad);
+            else bx[blk][ks] = bf16x8{};
+        }
+    }
+}
+
+// Centroid fragments of one 16-slot chunk: A rows slot0 + (l & 15),
+// k = ks*32 + 8*(l >> 4) .. +7, and the four norms of the lane's rows.
+template <int KS>
+struct AFrag {
+    bf16x8 a[KS];
+    float4 cn;
+};
+template <int KS>
+__device__ __forceinline__ void load_afrag(const ProbDev &P, int slot0, AFrag<KS> &f)
+{
+    const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) f.a[ks] = *(const bf16x8 *)(P.cb + (size_t)(slot0 + col) * P.ldb + ks * 32 + 8 * quad);
+    f.cn = *(const float4 *)(P.cn + slot0 + 4 * quad);
+}
+
+// One chunk: MFMA estimates of ||xb - cb||^2 for the blocks named in m,
+// reduced to the lane's own point.
+template <int KS>
+__device__ __forceinline__ Best3 mfma_chunk(const AFrag<KS> &f, int slot0, unsigned long long m,
+                                            const bf16x8 (&bx)[4][KS], const float (&xnB)[4])
+{
+    const int quad = lane_id() >> 4;
+    const float cnv[4] = {f.cn.x, f.cn.y, f.cn.z, f.cn.w};
+    Best3 T[4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+        if ((m >> (16 * blk)) & 0xFFFFull) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks], bx[blk][ks], acc, 0, 0, 0);
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, acc[r], xnB[blk] + cnv[r]);
+            T[blk] = best_of4(v, slot0 + 4 * quad);
+        } else {
+            T[blk].m1 = KP_INF;
+            T[blk].s1 = INT_MAX;
+            T[blk].m2 = KP_INF;
+        }
+    }
+    return transpose_reduce(T);
+}
+
+// The chunks of a list of (group, block mask) visits, with the fragments of
+// the next chunk loaded while the current one is computed.  The visit table
+// is loaded 64 entries at a time, one entry per lane (entry(k, g, m) gives
+// entry k), so the address of every next chunk is known without waiting on
+// memory.  done(g, m, gb) receives each group's result.
+template <int KS, class Entry, class Done>
+__device__ __forceinline__ void mfma_visits(const ProbDev &P, int nvisits, Entry entry, Done done,
+                                            const bf16x8 (&bx)[4][KS], const float (&xnB)[4])
+{
+    if (nvisits <= 0) return;
+    const int lane = lane_id();
+    // lane-held table of visits wb .. wb+63
+    int tg = 0, ts0 = 0, tns = 0;
+    unsigned tmlo = 0u, tmhi = 0u;
+    int wb = -WAVE;
+    auto fetch = [&](int i, int &g, unsigned long long &m, int &s0, int &ns) {
+        if (i >= wb + WAVE) {   // uniform: next window
+            wb = i & ~(WAVE - 1);
+            const int k = wb + lane;
+            if (k < nvisits) {
+                unsigned long long mk;
+                entry(k, tg, mk);
+                tmlo = (unsigned)mk;
+                tmhi = (unsigned)(mk >> 32);
+                ts0 = P.gstart[tg];
+                tns = P.gsize[tg];
+            }
+        }
+        const int l = i - wb;
+        g = __builtin_amdgcn_readlane(tg, l);
+        s0 = __builtin_amdgcn_readlane(ts0, l);
+        ns = __builtin_amdgcn_readlane(tns, l);
+        m = (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)tmlo, l) |
+            ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)tmhi, l) << 32);
+    };
+    int g, s0, ns, i = 0, c0 = 0;
+    unsigned long long m;
+    fetch(0, g, m, s0, ns);
+    AFrag<KS> cur, nxt;
+    load_afrag<KS>(P, s0, cur);
+    Best3 gb = {KP_INF, INT_MAX, KP_INF};
+    for (;;) {
+        // the chunk after (i, c0)
+        int ni = i, nc0 = c0 + CHUNK, ng = g, ns0 = s0, nns = ns;
+        unsigned long long nm = m;
+        if (nc0 >= ns) {
+            ni = i + 1;
+            nc0 = 0;
+            if (ni < nvisits) fetch(ni, ng, nm, ns0, nns);
+        }
+        const bool more = ni < nvisits;
+        if (more) load_afrag<KS>(P, ns0 + nc0, nxt);
+        gb = merge3(gb, mfma_chunk<KS>(cur, s0 + c0, m, bx, xnB));
+        if (nc0 == 0) {   // group i complete
+            done(g, m, gb);
+            gb.m1 = KP_INF;
+            gb.s1 = INT_MAX;
+            gb.m2 = KP_INF;
+        }
+        if (!more) break;
+        i = ni;
+        c0 = nc0;
+        g = ng;
+        m = nm;
+        s0 = ns0;
+        ns = nns;
+        cur = nxt;
+    }
+}
+
+// BF16 decision under the error bound; writes the point's state and bound
+// fix-ups when the decision is certain, else reports it as uncertain with
+// U* (an upper bound on its true nearest distance).
+__device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, int ga, bool a_sep,
+                                            float ubt, float d2a, float lbe_a, float minnc, const Run &r,
+                                            double eta, double rho, double eps2, float sdd, bool &moved,
+                                            bool &amb, int &win, float &umin)
+{
+    float *lbrow = P.lb + (size_t)pid * P.gs;
+    const float Lb = mfma_lo(r.bd, eta, rho), Ub = mfma_hi(r.bd, eta, rho);
+    const float Ls = mfma_lo(r.sec, eta, rho);
+    float La = KP_INF;
+    amb = false;
+    if (a_sep) {
+        La = dist_lo(d2a, eps2, rho);
+        if (ubt < Lb) {
+            win = a;   // the old centroid is certainly nearest
+        } else if (Ub < La && Ub < Ls) {
+            win = r.bs;
+        } else {
+            amb = true;
+            umin = fminf(Ub, ubt);
+        }
+    } else if (Ub < Ls) {
+        win = r.bs;
+    } else {
+        amb = true;
+        umin = Ub;
+    }
+    moved = false;
+    if (amb) return;
+    PointState nsv;
+    nsv.a = win;
+    nsv.pad = 0;
+    float ubn, lbp;
+    if (a_sep && win == a) {
+        ubn = ubt;
+        lbp = fminf(minnc, Lb);
+    } else {
+        lbrow[r.bg] = store_lb(mfma_lo(r.bm2, eta, rho), P.Sgd[r.bg]);
+        ubn = Ub;
+        lbp = fminf(minnc, Ls);
+        if (a_sep) {
+            const float va = fminf(lbe_a, La);
+            lbrow[ga] = store_lb(va, P.Sgd[ga]);
+            lbp = fminf(lbp, va);
+        }
+    }
+    nsv.u = store_u(ubn, P.Scd[win]);
+    nsv.p = store_lb(lbp, sdd);
+    P.st[pid] = nsv;
+    moved = win != (dense ? -1 : a);
+}
+
+// ============================================================ dense (iteration 1)
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
 {
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
-    const int t = *P.iter + 1;
-    const int W = P.W;
     const double eps2 = eps2_direct(P.d);
-    const float bmax = P.scal[0], rcmax = P.scal[1];
-    const long long count = DENSE ? P.n : (long long)P.ctr[CTR_L1];
-    const long long ntiles = (count + WAVE - 1) / WAVE;
-    const int col = lane & 15, quad = lane >> 4;
-    unsigned long long n_pairs = 0, n_dist = 0;
+    const float sdd = P.Sdud[1];
+    const long long ntiles = (P.n + WAVE - 1) / WAVE;
+    unsigned long long n_moved = 0;
     for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
          tl += (long long)gridDim.x * wpb) {
-        TileState ts = tile_begin(P, DENSE, tl, count, t, eps2);
-        const bool act = ts.active;
-        const unsigned long long amask = __ballot(act);
-        if (amask == 0ull) continue;
-        // B fragments: point 16*blk + col, k = ks*32 + 8*quad .. +7
-        bf16x8 bx[4][KS];
-        float xnB[4];
+        const long long idx = tl * WAVE + lane;
+        const bool act = idx < P.n;
+        const int pid = act ? (int)idx : 0;
+        float x[DMAX];
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) {
-            const int src = 16 * blk + col;
-            const int p = __shfl(ts.pid, src);
-            const bool ok = (amask >> src) & 1ull;
-            xnB[blk] = ok ? P.xn[p] : 0.f;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                if (ok) {
-                    bx[blk][ks] = *(const bf16x8 *)(P.Xb + (size_t)p * P.ldb + ks * 32 + 8 * quad);
-                } else {
-                    bx[blk][ks] = bf16x8{};
-                }
-            }
-        }
-        double eta = 0.0, rho = 0.0;
-        if (act) {
-            eta = mfma_eta(P.xn[ts.pid], bmax, P.ldb);
-            rho = (double)P.xr[ts.pid] + (double)rcmax;
-        }
-        float mb = KP_INF, msec = KP_INF, mbm2 = KP_INF, minnc = KP_INF;
-        int ms = -1, mbg = -1;
-        float *lbrow = act ? P.lb + (size_t)ts.pid * P.gs : nullptr;
+        for (int i = 0; i < DMAX; ++i) x[i] = (act && i < P.d) ? P.X[(size_t)pid * P.d + i] : 0.f;
+        Run r;
+        run_init(r);
+        float *lbrow = P.lb + (size_t)pid * P.gs;
         for (int g4 = 0; g4 < P.g; g4 += 4) {
-            float4 lbq = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (!DENSE && act) lbq = *(const float4 *)(lbrow + g4);
-            float outv[4] = {KP_INF, KP_INF, KP_INF, KP_INF};
-            const float lbin[4] = {lbq.x, lbq.y, lbq.z, lbq.w};
-#pragma unroll 1
+            float outv[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
             for (int gg = 0; gg < 4; ++gg) {
                 const int g = g4 + gg;
                 if (g >= P.g) break;
-                bool cand;
-                float lbe = KP_INF;
-                if (DENSE) {
-                    cand = act;
-                } else {
-                    if (act) lbe = d2f_dn(lo_eff(lbin[gg], drift_between(P.Sg, P.g, g, t, ts.tx, W)));
-                    cand = act && !(ts.ubt < lbe);
-                }
-                const unsigned long long m = __ballot(cand);
-                Best3 gb = {KP_INF, INT_MAX, KP_INF};
-                if (m) {
-                    const int s0 = P.gstart[g], ns = P.gsize[g];
-                    for (int c0 = 0; c0 < ns; c0 += CHUNK) {
-                        const int slot0 = s0 + c0;
-                        bf16x8 af[KS];
-#pragma unroll
-                        for (int ks = 0; ks < KS; ++ks)
-                            af[ks] = *(const bf16x8 *)(P.cb + (size_t)(slot0 + col) * P.ldb + ks * 32 + 8 * quad);
-                        const float4 cn4 = *(const float4 *)(P.cn + slot0 + 4 * quad);
-                        const float cnv[4] = {cn4.x, cn4.y, cn4.z, cn4.w};
-                        Best3 T[4];
-#pragma unroll
-                        for (int blk = 0; blk < 4; ++blk) {
-                            if ((m >> (16 * blk)) & 0xFFFFull) {
-                                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                                for (int ks = 0; ks < KS; ++ks)
-                                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], bx[blk][ks], acc, 0, 0, 0);
-                                float v[4];
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, acc[r], xnB[blk] + cnv[r]);
-                                T[blk] = best_of4(v, slot0 + 4 * quad);
-                            } else {
-                                T[blk].m1 = KP_INF;
-                                T[blk].s1 = INT_MAX;
-                                T[blk].m2 = KP_INF;
-                            }
-                        }
-                        gb = merge3(gb, transpose_reduce(T));
-                    }
-                    n_pairs += (unsigned long long)__popcll(m);
-                    n_dist += (unsigned long long)__popcll(m) * (unsigned long long)ns;
-                }
-                if (cand) {
-                    outv[gg] = mfma_lo(gb.m1, eta, rho);
-                    if (before(P, gb.m1, gb.s1, mb, ms)) {
-                        msec = fminf(mb, gb.m2);
-                        mb = gb.m1;
-                        ms = gb.s1;
-                        mbg = g;
-                        mbm2 = gb.m2;
-                    } else {
-                        msec = fminf(msec, gb.m1);
-                    }
-                } else if (act) {
-                    outv[gg] = lbe;
-                    minnc = fminf(minnc, lbe);
+                const Best3 gb = direct_group<DMAX>(P, g, x);
+                if (act) {
+                    outv[gg] = store_lb(dist_lo(gb.m1, eps2), P.Sgd[g]);
+                    run_fold(P, r, gb, g);
                 }
             }
             if (act) *(float4 *)(lbrow + g4) = make_float4(outv[0], outv[1], outv[2], outv[3]);
         }
-        // decision under the error bound
-        const int oldslot = DENSE ? -1 : ts.a;
+        bool moved = false;
+        if (act) {
+            moved = finish_f32(P, pid, true, -1, -1, false, KP_INF, KP_INF, KP_INF, r, eps2, sdd);
+            P.mv_pt[pid] = pid;
+            P.mv_old[pid] = -1;
+            P.mv_new[pid] = moved ? P.st[pid].a : -1;
+        }
+        n_moved += (unsigned long long)__popcll(__ballot(moved));
+    }
+    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&P.ctr[CTR_PAIRS], (unsigned long long)P.n * (unsigned long long)P.g);
+        atomicAdd(&P.ctr[CTR_DIST], (unsigned long long)P.n * (unsigned long long)P.k);
+    }
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_dense_bf16(ProbDev P)
+{
+    const int lane = lane_id();
+    const int wpb = blockDim.x / WAVE;
+    const double eps2 = eps2_direct(P.ldb);
+    const float bmax = P.scal[0], rcmax = P.scal[1];
+    const float sdd = P.Sdud[1];
+    const long long ntiles = (P.n + WAVE - 1) / WAVE;
+    unsigned long long n_moved = 0, n_amb = 0;
+    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
+         tl += (long long)gridDim.x * wpb) {
+        const long long idx = tl * WAVE + lane;
+        const bool act = idx < P.n;
+        const int pid = act ? (int)idx : 0;
+        const unsigned long long amask = __ballot(act);
+        bf16x8 bx[4][KS];
+        float xnB[4];
+        load_bfrag<KS>(P, pid, amask, bx, xnB);
+        const double eta = mfma_eta(P.xn[pid], bmax, P.ldb);
+        const double rho = (double)P.xr[pid] + (double)rcmax;
+        Run r;
+        run_init(r);
+        float *lbrow = P.lb + (size_t)pid * P.gs;
+        mfma_visits<KS>(
+            P, P.g, [&](int k, int &g, unsigned long long &m) { g = k; m = amask; },
+            [&](int g, unsigned long long, const Best3 &gb) {
+                if (act) {   // lanes past the end may hold a skipped block's sentinel
+                    lbrow[g] = store_lb(mfma_lo(gb.m1, eta, rho), P.Sgd[g]);
+                    run_fold(P, r, gb, g);
+                }
+            },
+            bx, xnB);
         bool moved = false, amb = false;
         int win = -1;
         float umin = KP_INF;
+        if (act)
+            decide_bf16(P, pid, true, -1, -1, false, KP_INF, KP_INF, KP_INF, KP_INF, r, eta, rho, eps2, sdd, moved,
+                        amb, win, umin);
         if (act) {
-            const float Lb = mfma_lo(mb, eta, rho), Ub = mb < KP_INF ? mfma_hi(mb, eta, rho) : KP_INF;
-            const float Ls = mfma_lo(msec, eta, rho);
-            const bool a_sep = !DENSE && ts.a_sep;
-            float La = KP_INF;
-            if (a_sep) {
-                La = dist_lo(ts.d2a, eps2);
-                if (ts.ubt < Lb) {
-                    win = ts.a;   // old centroid certainly nearest
-                } else if (Ub < La && Ub < Ls) {
-                    win = ms;
-                } else {
-                    amb = true;
-                    umin = fminf(Ub, ts.ubt);
-                }
-            } else {
-                if (Ub < Ls) win = ms;
-                else {
-                    amb = true;
-                    umin = Ub;
-                }
-            }
-            if (!amb) {
-                PointState nsv;
-                nsv.a = win;
-                nsv.tx = t;
-                if (win == ts.a && a_sep) {
-                    nsv.ub = ts.ubt;
-                    nsv.lbp = fminf(minnc, Lb);
-                } else {
-                    lbrow[mbg] = mfma_lo(mbm2, eta, rho);
-                    nsv.ub = Ub;
-                    float lbp = fminf(minnc, Ls);
-                    if (a_sep) {
-                        const float v = fminf(ts.lbe_a, La);
-                        lbrow[ts.ga] = v;
-                        lbp = fminf(lbp, v);
-                    }
-                    nsv.lbp = lbp;
-                }
-                P.st[ts.pid] = nsv;
-                moved = (win != oldslot);
-            }
+            P.mv_pt[pid] = pid;
+            P.mv_old[pid] = -1;
+            P.mv_new[pid] = moved ? win : -1;
+            P.psf[pid] = amb ? 4 : 0;
+            if (amb) P.ps4[pid] = make_float4(0.f, 0.f, umin, 0.f);
         }
-        const long long pos = wave_append(&P.ctr[CTR_MOVED], moved);
-        if (pos >= 0) {
-            P.mv_pt[pos] = ts.pid;
-            P.mv_old[pos] = oldslot;
-            P.mv_new[pos] = win;
+        n_moved += (unsigned long long)__popcll(__ballot(moved));
+        n_amb += (unsigned long long)__popcll(__ballot(amb));
+    }
+    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
+    if (lane == 0 && n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&P.ctr[CTR_PAIRS], (unsigned long long)P.n * (unsigned long long)P.g);
+        atomicAdd(&P.ctr[CTR_DIST], (unsigned long long)P.n * (unsigned long long)P.k);
+    }
+}
+
+// ================================================ group-level filter (phase 1)
+// One wave per tile of 64 consecutive entries of the sorted L1 (lane = point
+// of the tile).  Every group bound of each point is tested against the
+// point's upper bound (brought forward by its centroid's drift); the point's
+// own group always stays open, so that the distance kernel recomputes the
+// distance to the current centroid.  For each group open for some point of
+// the tile, (group, 64-bit point mask) is appended to the tile's list; the
+// distance kernel (phase 2) visits only those groups.  Per point it leaves
+// ub and the smallest bound of the closed groups.
+//
+// The bound rows pass through LDS in chunks of 32 groups: lanes over the
+// groups of two points on the way in (contiguous row runs, all loads of a
+// chunk in flight together), lane = point on the way out.
+constexpr int GT_WAVES = 4;
+constexpr int GT_CH = 32;             // groups per LDS chunk
+constexpr int GT_LD = GT_CH + 1;      // LDS row pitch (bank-conflict free)
+
+__global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
+{
+    __shared__ float stage[GT_WAVES][WAVE * GT_LD];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    float *sm = stage[wv];
+    const long long count = list_len(P, CTR_L1);
+    const long long ntiles = (count + WAVE - 1) / WAVE;
+    const int half = lane >> 5, col = lane & 31;
+    unsigned long long n_pairs = 0, n_visits = 0;
+    for (long long tl = (long long)blockIdx.x * GT_WAVES + wv; tl < ntiles; tl += (long long)gridDim.x * GT_WAVES) {
+        const long long idx = tl * WAVE + lane;
+        const bool act = idx < count;
+        const int pid = act ? clamp_pid(P, P.L1s[idx]) : 0;
+        float ubt = KP_INF, minnc = KP_INF;
+        int ga = -1;
+        if (act) {
+            const PointState s = P.st[pid];
+            const int a = clamp_slot(P, s.a);
+            ga = P.slot_group[a];
+            ubt = ub_now(s.u, P.Scu[a]);
         }
-        const long long p3 = wave_append(&P.ctr[CTR_L3], amb);
-        if (p3 >= 0) {
-            const bool a_sep = !DENSE && ts.a_sep;
-            P.L3[p3] = make_int4(ts.pid, oldslot, __float_as_int(umin), a_sep ? 1 : 0);
+        const unsigned long long amask = __ballot(act);
+        int cnt = 0;
+        int4 *lst = P.tlist + (size_t)tl * P.g;
+        for (int g0 = 0; g0 < P.g; g0 += GT_CH) {
+            const int gw = min(GT_CH, P.g - g0);
+            // in: row chunks of the tile's points, two points per step; every
+            // load is issued before the first store (no branch between them)
+            float rv[WAVE / 2];
+            const int cc = min(col, gw - 1);
+#pragma unroll
+            for (int p0 = 0; p0 < WAVE; p0 += 2) {
+                const int pp = __shfl(pid, p0 + half);   // inactive points carry pid 0
+                rv[p0 / 2] = P.lb[(size_t)pp * P.gs + g0 + cc];
+            }
+#pragma unroll
+            for (int p0 = 0; p0 < WAVE; p0 += 2) sm[(p0 + half) * GT_LD + col] = rv[p0 / 2];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // out: lane = point
+            for (int j = 0; j < gw; ++j) {
+                const int g = g0 + j;
+                const float sgu = P.Sgu[g];
+                const float v = act ? sm[lane * GT_LD + j] : 0.f;
+                const bool cand = act && (g == ga || group_open(ubt, sgu, v));
+                const unsigned long long m = __ballot(cand);
+                if (m) {
+                    if (lane == 0) lst[cnt] = make_int4(g, (int)(unsigned)m, (int)(unsigned)(m >> 32), 0);
+                    ++cnt;
+                    n_pairs += (unsigned long long)__popcll(m);
+                }
+                if (act && !cand) minnc = fminf(minnc, v - sgu);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane == 0) P.tcnt[tl] = cnt;
+        n_visits += (unsigned long long)cnt;
+        if (act) {
+            P.ps4[idx] = make_float4(ubt, f_dn(minnc), 0.f, 0.f);
+            P.psf[idx] = 1;
         }
     }
-    if (lane == 0 && n_pairs) {
-        atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
-        atomicAdd(&P.ctr[CTR_DIST], n_dist);
+    if (lane == 0 && n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
+    if (lane == 0 && n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
+}
+
+// ================================================== distance kernels (phase 2)
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
+{
+    const int lane = lane_id();
+    const int wpb = blockDim.x / WAVE;
+    const double eps2 = eps2_direct(P.d);
+    const float sdd = P.Sdud[1];
+    const long long count = list_len(P, CTR_L1);
+    const long long ntiles = (count + WAVE - 1) / WAVE;
+    unsigned long long n_dist = 0, n_moved = 0;
+    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
+         tl += (long long)gridDim.x * wpb) {
+        const long long idx = tl * WAVE + lane;
+        const bool in = idx < count;
+        const int flags = in ? P.psf[idx] : 0;
+        const bool act = flags & 1, a_sep = flags & 2;
+        if (__ballot(act) == 0ull) continue;
+        const int pid = in ? clamp_pid(P, P.L1s[idx]) : 0;
+        const float4 q = in ? P.ps4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float d2a = q.w, lbe_a = q.z, minnc = q.y;
+        const int a = act ? clamp_slot(P, P.st[pid].a) : 0;
+        const int ga = P.slot_group[a];
+        float x[DMAX];
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) x[i] = (act && i < P.d) ? P.X[(size_t)pid * P.d + i] : 0.f;
+        Run r;
+        run_init(r);
+        if (a_sep) {
+            r.bd = d2a;
+            r.bs = a;
+        }
+        const int cnt = min(max(P.tcnt[tl], 0), P.g);
+        const int4 *lst = P.tlist + (size_t)tl * P.g;
+        for (int k = 0; k < cnt; ++k) {
+            int4 e = lst[k];
+            e.x = min(max(e.x, 0), P.g - 1);
+            const unsigned long long m = (unsigned long long)(unsigned)e.y | ((unsigned long long)(unsigned)e.z << 32);
+            const Best3 gb = direct_group<DMAX>(P, e.x, x);
+            n_dist += (unsigned long long)__popcll(m) * (unsigned long long)P.gsize[e.x];
+            if ((m >> lane) & 1ull) {
+                P.lb[(size_t)pid * P.gs + e.x] = store_lb(dist_lo(gb.m1, eps2), P.Sgd[e.x]);
+                run_fold(P, r, gb, e.x);
+            }
+        }
+        bool moved = false;
+        if (act) moved = finish_f32(P, pid, false, a, ga, a_sep, d2a, lbe_a, minnc, r, eps2, sdd);
+        if (in) {
+            P.mv_pt[idx] = pid;
+            P.mv_old[idx] = a;
+            P.mv_new[idx] = moved ? P.st[pid].a : -1;
+        }
+        n_moved += (unsigned long long)__popcll(__ballot(moved));
     }
+    if (lane == 0 && n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
+    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_tile_bf16(ProbDev P)
+{
+    const int lane = lane_id();
+    const int wpb = blockDim.x / WAVE;
+    const double eps2 = eps2_direct(P.ldb);
+    const float bmax = P.scal[0], rcmax = P.scal[1];
+    const float sdd = P.Sdud[1];
+    const long long count = list_len(P, CTR_L1);
+    const long long ntiles = (count + WAVE - 1) / WAVE;
+    unsigned long long n_dist = 0, n_moved = 0, n_amb = 0;
+    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
+         tl += (long long)gridDim.x * wpb) {
+        const long long idx = tl * WAVE + lane;
+        const bool in = idx < count;
+        const int flags = in ? P.psf[idx] : 0;
+        const bool act = flags & 1, a_sep = flags & 2;
+        const unsigned long long amask = __ballot(act);
+        if (amask == 0ull) continue;
+        const int pid = in ? clamp_pid(P, P.L1s[idx]) : 0;
+        const float4 q = in ? P.ps4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float ubt = q.x, minnc = q.y, lbe_a = q.z, d2a = q.w;
+        const int a = act ? clamp_slot(P, P.st[pid].a) : 0;
+        const int ga = P.slot_group[a];
+        bf16x8 bx[4][KS];
+        float xnB[4];
+        load_bfrag<KS>(P, pid, amask, bx, xnB);
+        const double eta = mfma_eta(P.xn[pid], bmax, P.ldb);
+        const double rho = (double)P.xr[pid] + (double)rcmax;
+        Run r;
+        run_init(r);
+        const int cnt = min(max(P.tcnt[tl], 0), P.g);
+        const int4 *lst = P.tlist + (size_t)tl * P.g;
+        mfma_visits<KS>(
+            P, cnt,
+            [&](int k, int &g, unsigned long long &m) {
+                const int4 e = lst[k];
+                g = min(max(e.x, 0), P.g - 1);
+                m = (unsigned long long)(unsigned)e.y | ((unsigned long long)(unsigned)e.z << 32);
+            },
+            [&](int g, unsigned long long m, const Best3 &gb) {
+                n_dist += (unsigned long long)__popcll(m) * (unsigned long long)P.gsize[g];
+                if ((m >> lane) & 1ull) {
+                    P.lb[(size_t)pid * P.gs + g] = store_lb(mfma_lo(gb.m1, eta, rho), P.Sgd[g]);
+                    run_fold(P, r, gb, g);
+                }
+            },
+            bx, xnB);
+        bool moved = false, amb = false;
+        int win = -1;
+        float umin = KP_INF;
+        if (act)
+            decide_bf16(P, pid, false, a, ga, a_sep, ubt, d2a, lbe_a, minnc, r, eta, rho, eps2, sdd, moved, amb, win,
+                        umin);
+        if (in) {
+            P.mv_pt[idx] = pid;
+            P.mv_old[idx] = a;
+            P.mv_new[idx] = moved ? win : -1;
+            P.psf[idx] = amb ? 4 : 0;
+            if (amb) P.ps4[idx] = make_float4(0.f, 0.f, umin, 0.f);
+        }
+        n_moved += (unsigned long long)__popcll(__ballot(moved));
+        n_amb += (unsigned long long)__popcll(__ballot(amb));
+    }
+    if (lane == 0 && n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
+    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
+    if (lane == 0 && n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
 }
 
 // ================================================================ recheck
-// One wave per uncertain point.  Candidates: every group whose (provisional)
-// lower bound is <= U*, an upper bound on the point's true nearest distance,
-// plus the old centroid when it was tracked separately.  Every other centroid
-// is provably farther than the nearest one.  Distances are recomputed in FP32
-// direct form; lane (r, q) = (lane >> 2, lane & 3) sums coordinates
-// i = q mod 4 of member r, so the value equals direct_d2 bit for bit.
-constexpr int RECHECK_MAXG = 1024;
+// Eight lanes per uncertain point (32 points per workgroup).  Candidates:
+// every group whose lower bound is <= U*, an upper bound on the point's true
+// nearest distance, plus the old centroid when it was tracked separately;
+// every other centroid is provably farther than the nearest one.  Their
+// distances are recomputed in FP32 direct form on the FP32 point, which the
+// team holds in registers: lane t owns coordinates 4t + 32j .. 4t + 32j + 3,
+// sums its d/8 terms in coordinate order, then a three-level tree combines
+// the lanes (relative error below eps2_direct).  The point is decided on
+// those values (lowest original index on exact ties).
+constexpr int RT = 8;                 // lanes per point
+constexpr int RMAX = 64;              // candidate groups kept in LDS per point
 
-__device__ __forceinline__ float direct_lane(const float *__restrict__ x, const float *__restrict__ c, int d, int q)
+__device__ __forceinline__ float team_sum(float v)
 {
-    float acc = 0.f;
-    for (int i = q; i < d; i += 4) {
-        const float t0 = x[i] - c[i];
-        acc = fmaf(t0, t0, acc);
-    }
-    float v = acc + __shfl_xor(acc, 1);
-    return v + __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    return v;
+}
+__device__ __forceinline__ float team_min(float v)
+{
+    v = fminf(v, __shfl_xor(v, 1));
+    v = fminf(v, __shfl_xor(v, 2));
+    v = fminf(v, __shfl_xor(v, 4));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
 }
 
+template <int NV>   // float4 per lane: d <= 32 * NV
+__device__ __forceinline__ void team_load(float4 (&c4)[NV], const float *__restrict__ c, int ldc, int t)
+{
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int i = 4 * t + 32 * j;
+        c4[j] = i < ldc ? *(const float4 *)(c + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+template <int NV>
+__device__ __forceinline__ float team_dist(const float4 (&x)[NV], const float4 (&c4)[NV])
+{
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const float t0 = x[j].x - c4[j].x, t1 = x[j].y - c4[j].y, t2 = x[j].z - c4[j].z, t3 = x[j].w - c4[j].w;
+        acc = fmaf(t0, t0, acc);
+        acc = fmaf(t1, t1, acc);
+        acc = fmaf(t2, t2, acc);
+        acc = fmaf(t3, t3, acc);
+    }
+    return team_sum(acc);
+}
+template <int NV>
+__device__ __forceinline__ float team_d2(const float4 (&x)[NV], const float *__restrict__ c, int ldc, int t)
+{
+    float4 c4[NV];
+    team_load<NV>(c4, c, ldc, t);
+    return team_dist<NV>(x, c4);
+}
+
+template <int NV>
 __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
 {
-    __shared__ int rg[4][RECHECK_MAXG];
-    __shared__ float rm1[4][RECHECK_MAXG], rm2[4][RECHECK_MAXG];
+    __shared__ int rg[256 / RT][RMAX];
+    __shared__ float rm1[256 / RT][RMAX], rm2[256 / RT][RMAX];
     const int lane = lane_id();
-    const int wv = threadIdx.x / WAVE;
-    const int t = *P.iter + 1;
+    const int t = lane & (RT - 1);
+    const int team = threadIdx.x / RT;
     const double eps2 = eps2_direct(P.d);
-    const long long nL3 = (long long)P.ctr[CTR_L3];
-    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
-    const int r = lane >> 2, q = lane & 3;
-    for (long long e = (long long)blockIdx.x * (blockDim.x / WAVE) + wv; e < nL3; e += nw) {
-        const int4 ent = P.L3[e];
-        const int pid = ent.x, olda = ent.y;
-        const float umin = __int_as_float(ent.z);
-        const bool a_sep = ent.w & 1;
+    const float sdd = P.Sdud[1];
+    const bool dense = P.ctr[CTR_DENSE] != 0;
+    const long long npos = positions(P);
+    const long long nteams = (long long)gridDim.x * (blockDim.x / RT);
+    const long long trips = (npos + nteams - 1) / nteams;   // the same for every lane of the grid
+    unsigned long long n_moved = 0;
+    for (long long it = 0; it < trips; ++it) {
+        const long long e = it * nteams + (long long)blockIdx.x * (blockDim.x / RT) + team;
+        const bool live = e < npos && (P.psf[e] & 4);
+        if (__ballot(live) == 0ull) continue;   // no uncertain point in this wave's four... eight teams
+        const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
+        const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
+        const float umin = live ? P.ps4[e].z : 0.f;
+        const bool a_sep = false;
+        float4 x[NV];
         const float *xrow = P.X + (size_t)pid * P.d;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int i = 4 * t + 32 * j;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (live && i + q < P.d) ? xrow[i + q] : 0.f;
+            x[j] = make_float4(v[0], v[1], v[2], v[3]);
+        }
         float *lbrow = P.lb + (size_t)pid * P.gs;
+        // groups that may hold the nearest centroid
         float minnr = KP_INF;
         int nR = 0;
-        for (int g0 = 0; g0 < P.g; g0 += WAVE) {
-            const int g = g0 + lane;
-            const float v = g < P.g ? lbrow[g] : KP_INF;
-            const bool inR = g < P.g && v <= umin;
-            if (!inR) minnr = fminf(minnr, v);
+        const int ng = live ? P.g : 0;
+        const int gpad = (P.g + RT - 1) / RT * RT;
+        for (int g0 = 0; g0 < gpad; g0 += RT) {
+            const int g = g0 + t;
+            bool inR = false;
+            if (g < ng) {
+                const float lbe = lb_now(lbrow[g], P.Sgu[g]);
+                inR = lbe <= umin;
+                if (!inR) minnr = fminf(minnr, lbe);
+            }
+            // (the loads of later steps do not depend on this one, so the
+            // compiler keeps several in flight)
             const unsigned long long m = __ballot(inR);
-            if (inR) rg[wv][nR + __popcll(m & ((1ull << lane) - 1ull))] = g;
-            nR += __popcll(m);
+            const unsigned mt = (unsigned)((m >> (lane & ~(RT - 1))) & ((1u << RT) - 1u));
+            if (inR) {
+                const int pos = nR + __popc(mt & ((1u << t) - 1u));
+                if (pos < RMAX) rg[team][pos] = g;
+            }
+            nR += __popc(mt);
         }
-        minnr = wave_min(minnr);
+        minnr = team_min(minnr);
+        // more than RMAX candidate groups: examine every group (rare)
+        const bool overflow = nR > RMAX;
+        const int nscan = overflow ? ng : nR;
+        const int nscan_w = wave_max_i(nscan);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float bd = KP_INF;
-        int bs = -1, bgi = -1;
-        for (int i = 0; i < nR; ++i) {
-            const int g = rg[wv][i];
-            const int s0 = P.gstart[g], ns = P.gsize[g];
-            Best3 gb = {KP_INF, INT_MAX, KP_INF};
-            for (int c0 = 0; c0 < ns; c0 += 16) {
-                const int mr = c0 + r;
-                const bool ok = mr < ns;
-                const int slot = s0 + (ok ? mr : 0);
-                const float v = direct_lane(xrow, P.c32 + (size_t)slot * P.ldc, P.d, q);
-                Best3 c;
-                c.m1 = ok ? v : KP_INF;
-                c.s1 = ok ? s0 + mr : INT_MAX;
-                c.m2 = KP_INF;
+        int bs = -1;
+        for (int i = 0; i < nscan_w; ++i) {
+            const bool on = i < nscan;
+            const int g = on ? (overflow ? i : rg[team][i]) : 0;
+            const int s0 = P.gstart[g], ns = on ? P.gsize[g] : 0;
+            const int ns_w = wave_max_i(ns);
+            float m1 = KP_INF, m2 = KP_INF;
+            int s1 = -1;
+            constexpr int BATCH = NV <= 4 ? 4 : 2;   // candidates whose rows are in flight together
+            for (int r = 0; r < ns_w; r += BATCH) {
+                float4 c4[BATCH][NV];
 #pragma unroll
-                for (int o = 4; o < WAVE; o <<= 1) c = merge3(c, shfl_xor3(c, o));
-                gb = merge3(gb, c);
+                for (int q = 0; q < BATCH; ++q)
+                    team_load<NV>(c4[q], P.c32 + (size_t)(s0 + (r + q < ns ? r + q : 0)) * P.ldc, P.ldc, t);
+#pragma unroll
+                for (int q = 0; q < BATCH; ++q) {
+                    const float v = team_dist<NV>(x, c4[q]);
+                    if (r + q < ns) {
+                        if (v < m1) {
+                            m2 = m1;
+                            m1 = v;
+                            s1 = s0 + r + q;
+                        } else {
+                            m2 = fminf(m2, v);
+                        }
+                    }
+                }
             }
-            if (lane == 0) {
-                rm1[wv][i] = gb.m1;
-                rm2[wv][i] = gb.m2;
-            }
-            if (before(P, gb.m1, gb.s1, bd, bs)) {
-                bd = gb.m1;
-                bs = gb.s1;
-                bgi = i;
+            if (on) {
+                if (!overflow && t == 0) {
+                    rm1[team][i] = m1;
+                    rm2[team][i] = m2;
+                }
+                if (before(P, m1, s1, bd, bs)) {
+                    bd = m1;
+                    bs = s1;
+                }
             }
         }
-        float d2a = KP_INF;
-        if (a_sep && olda >= 0) {
-            d2a = __shfl(direct_lane(xrow, P.c32 + (size_t)olda * P.ldc, P.d, q), 0);
-            if (before(P, d2a, olda, bd, bs)) {
-                bd = d2a;
-                bs = olda;
-                bgi = -1;
-            }
+        const float d2a = team_d2<NV>(x, P.c32 + (size_t)(a_sep ? olda : 0) * P.ldc, P.ldc, t);
+        if (a_sep && before(P, d2a, olda, bd, bs)) {
+            bd = d2a;
+            bs = olda;
         }
+        if (bs < 0) bs = olda >= 0 ? olda : 0;   // unreachable: the provisional winner's group is in R
+        const int gbest = P.slot_group[bs];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lower bounds of the examined groups
         float minr = KP_INF;
-        for (int i = lane; i < nR; i += WAVE) {
-            const float v = dist_lo(i == bgi ? rm2[wv][i] : rm1[wv][i], eps2);
-            lbrow[rg[wv][i]] = v;
-            minr = fminf(minr, v);
-        }
-        float lbp = fminf(minnr, wave_min(minr));
-        if (a_sep && olda >= 0 && bs != olda) {
-            const int ga = P.slot_group[olda];
-            const float v = fminf(lbrow[ga], dist_lo(d2a, eps2));
-            if (lane == 0) lbrow[ga] = v;
-            lbp = fminf(lbp, v);
-        }
-        if (lane == 0) {
-            PointState nsv;
-            nsv.a = bs;
-            nsv.ub = dist_hi(bd, eps2);
-            nsv.lbp = lbp;
-            nsv.tx = t;
-            P.st[pid] = nsv;
-            if (bs != olda) {
-                const unsigned long long pos = atomicAdd(&P.ctr[CTR_MOVED], 1ull);
-                P.mv_pt[pos] = pid;
-                P.mv_old[pos] = olda;
-                P.mv_new[pos] = bs;
+        if (!overflow) {
+            for (int i = t; i < nscan; i += RT) {
+                const int g = rg[team][i];
+                const float lbv = dist_lo(g == gbest ? rm2[team][i] : rm1[team][i], eps2);
+                lbrow[g] = store_lb(lbv, P.Sgd[g]);
+                minr = fminf(minr, lbv);
+            }
+        } else {
+            // second pass: the minimum of every group except the winner
+            for (int i = 0; i < nscan_w; ++i) {
+                const bool on = i < nscan;
+                const int g = on ? i : 0;
+                const int s0 = P.gstart[g], ns = on ? P.gsize[g] : 0;
+                const int ns_w = wave_max_i(ns);
+                float m = KP_INF;
+                for (int r = 0; r < ns_w; ++r) {
+                    const bool ok = r < ns && (s0 + r) != bs;
+                    const float v = team_d2<NV>(x, P.c32 + (size_t)(s0 + (r < ns ? r : 0)) * P.ldc, P.ldc, t);
+                    if (ok) m = fminf(m, v);
+                }
+                if (on) {
+                    const float lbv = dist_lo(m, eps2);
+                    if (t == 0) lbrow[g] = store_lb(lbv, P.Sgd[g]);
+                    minr = fminf(minr, lbv);
+                }
             }
         }
+        minr = team_min(minr);
+        if (!live) continue;
+        float lbp = fminf(minnr, minr);
+        if (a_sep && bs != olda) {
+            const int ga = P.slot_group[olda];
+            const float va = fminf(lb_now(lbrow[ga], P.Sgu[ga]), dist_lo(d2a, eps2));
+            if (t == 0) lbrow[ga] = store_lb(va, P.Sgd[ga]);
+            lbp = fminf(lbp, va);
+        }
+        if (t == 0) {
+            PointState nsv;
+            nsv.a = bs;
+            nsv.u = store_u(dist_hi(bd, eps2), P.Scd[bs]);
+            nsv.p = store_lb(lbp, sdd);
+            nsv.pad = 0;
+            P.st[pid] = nsv;
+            P.mv_pt[e] = pid;
+            P.mv_old[e] = olda;
+            P.mv_new[e] = bs != olda ? bs : -1;
+            n_moved += bs != olda ? 1ull : 0ull;
+        }
     }
+    // one atomic per lane that decided points (lane 0 of each team)
+    if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
 
 // ========================================================= centroid update
-// Entries: e < M adds point mv_pt[e] to slot mv_new[e]; M <= e < 2M subtracts
-// point mv_pt[e-M] from slot mv_old[e-M] (skipped when there was none).
-constexpr int HIST_LDS = 8192;
-
+// Entries over the M positions of the iteration: e < M adds point mv_pt[e]
+// to slot mv_new[e]; M <= e < 2M subtracts point mv_pt[e-M] from slot
+// mv_old[e-M].  Positions that did not move (mv_new = -1) and points that had
+// no slot before (mv_old = -1) contribute nothing.
 __device__ __forceinline__ int entry_key(const ProbDev &P, long long e, long long M)
 {
-    return e < M ? P.mv_new[e] : P.mv_old[e - M];
+    const long long q = e < M ? e : e - M;
+    const int kn = P.mv_new[q];
+    if (kn < 0) return -1;
+    const int k = e < M ? kn : P.mv_old[q];
+    return k < 0 ? -1 : clamp_slot(P, k);
 }
 
 __global__ __launch_bounds__(256) void k_hist(ProbDev P)
 {
     __shared__ int h[HIST_LDS];
-    const long long M = (long long)P.ctr[CTR_MOVED];
+    const long long M = positions(P);
     const long long E = 2 * M;
     const bool lds = P.kg <= HIST_LDS;
     if (lds)
@@ -832,36 +1338,11 @@ __global__ __launch_bounds__(256) void k_hist(ProbDev P)
             if (h[i]) atomicAdd(&P.hist[i], h[i]);
 }
 
-// Exclusive scan of hist into cursor (single workgroup of 1024).
-__global__ __launch_bounds__(1024) void k_scan(ProbDev P)
-{
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int n = P.kg;
-    const int per = (n + 1023) / 1024;
-    const int b = tid * per, e = min(n, b + per);
-    int s = 0;
-    for (int i = b; i < e; ++i) s += P.hist[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int run = part[tid] - s;
-    for (int i = b; i < e; ++i) {
-        P.cursor[i] = run;
-        run += P.hist[i];
-    }
-}
-
 __global__ __launch_bounds__(256) void k_scatter(ProbDev P)
 {
     __shared__ int h[HIST_LDS];
     __shared__ int base[HIST_LDS];
-    const long long M = (long long)P.ctr[CTR_MOVED];
+    const long long M = positions(P);
     const long long E = 2 * M;
     const bool lds = P.kg <= HIST_LDS;
     const long long b0 = E * blockIdx.x / gridDim.x, b1 = E * (blockIdx.x + 1) / gridDim.x;
@@ -870,7 +1351,7 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev P)
             const int key = entry_key(P, e, M);
             if (key < 0) continue;
             const int pos = atomicAdd(&P.cursor[key], 1);
-            const int pid = P.mv_pt[e < M ? e : e - M];
+            const int pid = clamp_pid(P, P.mv_pt[e < M ? e : e - M]);
             P.srt_pt[pos] = e < M ? pid : (int)((unsigned)pid | 0x80000000u);
             P.srt_key[pos] = key;
         }
@@ -893,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev P)
         const int key = entry_key(P, e, M);
         if (key < 0) continue;
         const int pos = base[key] + atomicAdd(&h[key], 1);
-        const int pid = P.mv_pt[e < M ? e : e - M];
+        const int pid = clamp_pid(P, P.mv_pt[e < M ? e : e - M]);
         P.srt_pt[pos] = e < M ? pid : (int)((unsigned)pid | 0x80000000u);
         P.srt_key[pos] = key;
     }
@@ -905,13 +1386,9 @@ template <int DCH>
 __global__ __launch_bounds__(256) void k_segsum(ProbDev P)
 {
     const int lane = lane_id();
-    const long long M = (long long)P.ctr[CTR_MOVED];
-    long long E = 0;
-    // number of sorted entries = sum of hist
-    // (entries with no old slot were skipped)
-    E = 2 * M;   // upper bound; the real count is cursor[kg-1] after scatter
-    const long long used = (long long)P.cursor[P.kg - 1];
-    E = used < E ? used : E;
+    const long long M = positions(P);
+    const long long used = (long long)P.cursor[P.kg - 1];   // end of the last bin = entries sorted
+    const long long E = used < 2 * M ? used : 2 * M;
     const long long nchunks = (E + WAVE - 1) / WAVE;
     const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
     for (long long c = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; c < nchunks; c += nw) {
@@ -920,9 +1397,9 @@ __global__ __launch_bounds__(256) void k_segsum(ProbDev P)
 #pragma unroll
         for (int j = 0; j < DCH; ++j) acc[j] = 0.0;
         int cacc = 0;
-        int cur = P.srt_key[p0];
+        int cur = clamp_slot(P, P.srt_key[p0]);
         for (long long p = p0; p < p1; ++p) {
-            const int key = P.srt_key[p];
+            const int key = clamp_slot(P, P.srt_key[p]);
             const int v = P.srt_pt[p];
             if (key != cur) {
 #pragma unroll
@@ -935,7 +1412,7 @@ __global__ __launch_bounds__(256) void k_segsum(ProbDev P)
                 cacc = 0;
                 cur = key;
             }
-            const int pid = v & 0x7FFFFFFF;
+            const int pid = clamp_pid(P, v & 0x7FFFFFFF);
             const bool neg = v < 0;
             const float *xr = P.X + (size_t)pid * P.d;
 #pragma unroll
@@ -961,7 +1438,7 @@ __global__ __launch_bounds__(256) void k_segsum(ProbDev P)
 __global__ void k_labels(ProbDev P, int *out)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = P.perm[P.st[i].a];
+        out[i] = P.perm[clamp_slot(P, P.st[i].a)];
 }
 
 __global__ void k_centroids_out(ProbDev P, float *c32, double *c64)
@@ -991,29 +1468,55 @@ hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
     return hipGetLastError();
 }
 
-template <bool DENSE>
-static void launch_assign(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
+static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
 {
     const int threads = 64 * cfg.waves;
-    const long long work = DENSE ? (P.n + 63) / 64 : (P.n + 63) / 64;
-    const int grid = cap_grid((work + cfg.waves - 1) / cfg.waves, cfg.grid_cap);
+    const int grid = cap_grid(((P.n + 63) / 64 + cfg.waves - 1) / cfg.waves, cfg.grid_cap);
     if (P.prec == 0) {
         const int dm = P.ldc;
-        if (dm <= 8) hipLaunchKernelGGL((k_assign_f32<8, DENSE>), dim3(grid), dim3(threads), 0, s, P);
-        else if (dm <= 16) hipLaunchKernelGGL((k_assign_f32<16, DENSE>), dim3(grid), dim3(threads), 0, s, P);
-        else if (dm <= 32) hipLaunchKernelGGL((k_assign_f32<32, DENSE>), dim3(grid), dim3(threads), 0, s, P);
-        else if (dm <= 64) hipLaunchKernelGGL((k_assign_f32<64, DENSE>), dim3(grid), dim3(threads), 0, s, P);
-        else hipLaunchKernelGGL((k_assign_f32<128, DENSE>), dim3(grid), dim3(threads), 0, s, P);
+        if (dm <= 8) hipLaunchKernelGGL(k_dense_f32<8>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 16) hipLaunchKernelGGL(k_dense_f32<16>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 32) hipLaunchKernelGGL(k_dense_f32<32>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 64) hipLaunchKernelGGL(k_dense_f32<64>, dim3(grid), dim3(threads), 0, s, P);
+        else hipLaunchKernelGGL(k_dense_f32<128>, dim3(grid), dim3(threads), 0, s, P);
     } else {
         switch (P.ldb / 32) {
-        case 1: hipLaunchKernelGGL((k_assign_bf16<1, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 2: hipLaunchKernelGGL((k_assign_bf16<2, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 3: hipLaunchKernelGGL((k_assign_bf16<3, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 4: hipLaunchKernelGGL((k_assign_bf16<4, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 5: hipLaunchKernelGGL((k_assign_bf16<5, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 6: hipLaunchKernelGGL((k_assign_bf16<6, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        case 7: hipLaunchKernelGGL((k_assign_bf16<7, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
-        default: hipLaunchKernelGGL((k_assign_bf16<8, DENSE>), dim3(grid), dim3(threads), 0, s, P); break;
+        case 1: hipLaunchKernelGGL(k_dense_bf16<1>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 2: hipLaunchKernelGGL(k_dense_bf16<2>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 3: hipLaunchKernelGGL(k_dense_bf16<3>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 4: hipLaunchKernelGGL(k_dense_bf16<4>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 5: hipLaunchKernelGGL(k_dense_bf16<5>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 6: hipLaunchKernelGGL(k_dense_bf16<6>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 7: hipLaunchKernelGGL(k_dense_bf16<7>, dim3(grid), dim3(threads), 0, s, P); break;
+        default: hipLaunchKernelGGL(k_dense_bf16<8>, dim3(grid), dim3(threads), 0, s, P); break;
+        }
+    }
+}
+
+static void launch_survivors(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
+{
+    const int threads = 64 * cfg.waves;
+    const int grid = cap_grid(((P.n + 63) / 64 + cfg.waves - 1) / cfg.waves, cfg.grid_cap);
+    const int gt_grid = cap_grid(((P.n + 63) / 64 + GT_WAVES - 1) / GT_WAVES, cfg.grid_cap);
+    if (P.prec == 0) {
+        hipLaunchKernelGGL(k_group_test, dim3(gt_grid), dim3(WAVE * GT_WAVES), 0, s, P);
+        const int dm = P.ldc;
+        if (dm <= 8) hipLaunchKernelGGL(k_tile_f32<8>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 16) hipLaunchKernelGGL(k_tile_f32<16>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 32) hipLaunchKernelGGL(k_tile_f32<32>, dim3(grid), dim3(threads), 0, s, P);
+        else if (dm <= 64) hipLaunchKernelGGL(k_tile_f32<64>, dim3(grid), dim3(threads), 0, s, P);
+        else hipLaunchKernelGGL(k_tile_f32<128>, dim3(grid), dim3(threads), 0, s, P);
+    } else {
+        hipLaunchKernelGGL(k_group_test, dim3(gt_grid), dim3(WAVE * GT_WAVES), 0, s, P);
+        switch (P.ldb / 32) {
+        case 1: hipLaunchKernelGGL(k_tile_bf16<1>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 2: hipLaunchKernelGGL(k_tile_bf16<2>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 3: hipLaunchKernelGGL(k_tile_bf16<3>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 4: hipLaunchKernelGGL(k_tile_bf16<4>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 5: hipLaunchKernelGGL(k_tile_bf16<5>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 6: hipLaunchKernelGGL(k_tile_bf16<6>, dim3(grid), dim3(threads), 0, s, P); break;
+        case 7: hipLaunchKernelGGL(k_tile_bf16<7>, dim3(grid), dim3(threads), 0, s, P); break;
+        default: hipLaunchKernelGGL(k_tile_bf16<8>, dim3(grid), dim3(threads), 0, s, P); break;
         }
     }
 }
@@ -1022,7 +1525,7 @@ static void launch_update(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
 {
     const int ublocks = cap_grid((2 * P.n + 255) / 256, cfg.grid_cap);
     hipLaunchKernelGGL(k_hist, dim3(ublocks), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, P);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist, P.cursor, P.kg);
     const int sblocks = cap_grid((2 * P.n + 4095) / 4096, 1024);
     hipLaunchKernelGGL(k_scatter, dim3(sblocks), dim3(256), 0, s, P);
     const int segblocks = cap_grid((2 * P.n + 255) / 256, cfg.grid_cap);
@@ -1047,8 +1550,8 @@ static void launch_centroid_rows(const ProbDev &P, hipStream_t s)
 
 const char *stage_name(Stage st)
 {
-    static const char *names[ST_COUNT] = {"begin", "bound_filter", "assign_dense", "assign", "recheck",
-                                          "update", "centroids"};
+    static const char *names[ST_COUNT] = {"begin", "bound_filter", "l1_sort", "assign_dense", "assign",
+                                          "recheck", "update", "centroids"};
     return (st >= 0 && st < ST_COUNT) ? names[st] : "?";
 }
 
@@ -1060,6 +1563,7 @@ int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT])
         out[n++] = ST_ASSIGN_DENSE;
     } else {
         out[n++] = ST_FILTER;
+        out[n++] = ST_SORT;
         out[n++] = ST_ASSIGN;
     }
     if (P.prec) out[n++] = ST_RECHECK;
@@ -1075,13 +1579,25 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
         hipLaunchKernelGGL(k_begin, dim3(cap_grid((P.kg + 256) / 256, 64)), dim3(256), 0, s, P, dense ? 1 : 0);
         break;
     case ST_FILTER:
-        hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 255) / 256, cfg.grid_cap)), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 4095) / 4096, cfg.grid_cap)), dim3(256), 0, s, P);
         break;
-    case ST_ASSIGN_DENSE: launch_assign<true>(P, s, cfg); break;
-    case ST_ASSIGN: launch_assign<false>(P, s, cfg); break;
-    case ST_RECHECK:
-        hipLaunchKernelGGL(k_recheck, dim3(cap_grid((P.n + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
+    case ST_SORT: {
+        const int blocks = cap_grid((P.n + 16383) / 16384, 1024);
+        hipLaunchKernelGGL(k_key_hist, dim3(blocks), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist1, P.cursor1, P.kg);
+        hipLaunchKernelGGL(k_l1_scatter, dim3(blocks), dim3(256), 0, s, P);
         break;
+    }
+    case ST_ASSIGN_DENSE: launch_dense(P, s, cfg); break;
+    case ST_ASSIGN: launch_survivors(P, s, cfg); break;
+    case ST_RECHECK: {
+        const int blocks = cap_grid((P.n + 31) / 32, cfg.grid_cap);
+        if (P.ldc <= 32) hipLaunchKernelGGL(k_recheck<1>, dim3(blocks), dim3(256), 0, s, P);
+        else if (P.ldc <= 64) hipLaunchKernelGGL(k_recheck<2>, dim3(blocks), dim3(256), 0, s, P);
+        else if (P.ldc <= 128) hipLaunchKernelGGL(k_recheck<4>, dim3(blocks), dim3(256), 0, s, P);
+        else hipLaunchKernelGGL(k_recheck<8>, dim3(blocks), dim3(256), 0, s, P);
+        break;
+    }
     case ST_UPDATE: launch_update(P, s, cfg); break;
     case ST_CENTROIDS: launch_centroid_rows(P, s); break;
     default: return hipErrorInvalidValue;
@@ -1094,7 +1610,7 @@ hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const L
     Stage sts[ST_COUNT];
     const int n = iteration_stages(P, dense, sts);
     for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_stage(P, s, sts[i], dense, cfg);
+        const hipError_t e = launch_stage(P, s, sts[i], dense, cfg);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

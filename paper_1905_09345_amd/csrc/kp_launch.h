@@ -13,7 +13,7 @@ struct LaunchCfg {
 // Per-point BF16 shadow and norms, initial centroid rows, drift rings at t=0.
 hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev);
 // Stages of one iteration, in launch order.
-enum Stage { ST_BEGIN = 0, ST_FILTER, ST_ASSIGN_DENSE, ST_ASSIGN, ST_RECHECK, ST_UPDATE, ST_CENTROIDS, ST_COUNT };
+enum Stage { ST_BEGIN = 0, ST_FILTER, ST_SORT, ST_ASSIGN_DENSE, ST_ASSIGN, ST_RECHECK, ST_UPDATE, ST_CENTROIDS, ST_COUNT };
 const char *stage_name(Stage st);
 // The stages of a dense (first) or filtered iteration of problem P, in order.
 int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT]);

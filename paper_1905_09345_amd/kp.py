@@ -30,13 +30,13 @@ class kp_problem(ctypes.Structure):
 
 class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("age_limit", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class kp_iter_stats(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("dense", ctypes.c_int32), ("point_filter_fail", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("distances", ctypes.c_int64), ("rechecks", ctypes.c_int64),
-                ("moved", ctypes.c_int64)]
+                ("moved", ctypes.c_int64), ("max_drift", ctypes.c_double), ("tile_groups", ctypes.c_int64)]
 
 
 class kp_stage_time(ctypes.Structure):
@@ -127,7 +127,9 @@ def kp_stats(ctx, problem, cap=1024):
     n = ctypes.c_int32(0)
     _check(lib().kp_stats(ctypes.c_void_p(ctx), int(problem), buf, int(cap), ctypes.byref(n)), "kp_stats")
     return [dict(iter=s.iter, dense=s.dense, point_filter_fail=s.point_filter_fail, pairs=s.pairs,
-                 distances=s.distances, rechecks=s.rechecks, moved=s.moved) for s in buf[:n.value]]
+                 distances=s.distances, rechecks=s.rechecks, moved=s.moved, max_drift=s.max_drift,
+                 tile_groups=s.tile_groups)
+            for s in buf[:n.value]]
 
 
 def kp_stage_times(ctx, cap=16):

@@ -30,9 +30,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 20
+    assert ctypes.sizeof(kp.kp_tuning) == 16
     assert ctypes.sizeof(kp.kp_stage_time) == 40
-    assert ctypes.sizeof(kp.kp_iter_stats) == 48 and kp.kp_iter_stats.point_filter_fail.offset == 8
+    assert ctypes.sizeof(kp.kp_iter_stats) == 64 and kp.kp_iter_stats.point_filter_fail.offset == 8
 
 
 def _prob(**kw):
@@ -61,7 +61,7 @@ def test_invalid_problem_rejected(bad):
 
 
 def test_invalid_tuning_rejected():
-    t = kp.kp_tuning(age_limit=99)
+    t = kp.kp_tuning(timing=7)
     assert kp.kp_workspace_bytes([_prob()], t) == 0
 
 

@@ -98,18 +98,48 @@ def test_ties_duplicates_and_empty_clusters(prec):
     assert r["c64"][6].tolist() == [100.0, 100.0, 100.0]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_age_refresh(prec):
-    """Age limit 2 forces every kept point through a full bound refresh each iteration."""
-    from paper_1905_09345_amd.kp import kp_tuning
-    P = datagen.make_config(2, n=8_191)
-    _print_case("age", prec=prec)
-    run_steplocked(P.X, P.C0, P.g, prec, 7, tuning=kp_tuning(age_limit=2))
-
-
 @pytest.mark.parametrize("use_graph", [1, -1])
 def test_graph_and_plain_launches(use_graph):
     from paper_1905_09345_amd.kp import kp_tuning
     P = datagen.make_config(1, n=4_097)
     _print_case("graph", use_graph=use_graph)
     run_steplocked(P.X, P.C0, P.g, "fp32", 6, tuning=kp_tuning(use_graph=use_graph))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_long_run(prec):
+    """Many iterations: the cumulative drift sums keep growing while bounds stay valid."""
+    P = datagen.make_config(2, n=20_011)
+    _print_case("long", prec=prec)
+    r = run_steplocked(P.X, P.C0, P.g, prec, 45, check_every=3)
+    assert len(r["stats"]) == 45
+
+
+def test_stage_times():
+    import torch
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning
+    P = datagen.make_config(3, n=10_000)
+    _print_case("timing")
+    for use_graph in (1, -1):
+        km = KMeans([(torch.from_numpy(P.X).cuda(), torch.from_numpy(P.C0).cuda(), P.g, "bf16")],
+                    tuning=kp_tuning(timing=1, use_graph=use_graph))
+        km.iterate(4)
+        t = km.stage_times()
+        km.close()
+        assert t["assign_dense"]["launches"] == 1 and t["assign_dense"]["ms"] > 0
+        if use_graph == 1:
+            assert t["filtered_iter"]["launches"] == 3
+        else:
+            assert t["assign"]["launches"] == 3 and t["bound_filter"]["launches"] == 3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [5, 17, 41, 63, 64, 65, 112, 129])
+def test_tail_tiles(prec, n):
+    """Point counts whose last 64-point tile has empty 16-point blocks."""
+    rng = np.random.default_rng(n)
+    X = datagen.gaussian_mixture(rng, n, 16, 3)
+    C0 = X[:5].copy()
+    _print_case("tail", n=n, prec=prec)
+    run_steplocked(X, C0, 2, prec, 4)
