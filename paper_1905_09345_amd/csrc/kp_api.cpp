@@ -36,7 +36,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
-    size_t Xb, xn, xr, st, lb, c32, cb, cn, cr, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
+    size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
     size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
         cursor1, ctr, stats, iter, scal;
     size_t bytes;
@@ -52,6 +52,8 @@ Plan plan_problem(const kp_problem &p)
     o.kgmax = p.k + (kp::CHUNK_SLOTS - 1) * g;
     o.ldc = (d + 3) / 4 * 4;
     o.ldb = (d + 31) / 32 * 32;
+    if (o.ldb == 160) o.ldb = 192;   // BF16 tiles take 1, 2, 3, 4, 6 or 8 steps of 32
+    if (o.ldb == 224) o.ldb = 256;
     o.gs = (g + 3) / 4 * 4;
     const size_t kgm = (size_t)o.kgmax;
     size_t off = 0;
@@ -60,15 +62,13 @@ Plan plan_problem(const kp_problem &p)
         off += up(bytes ? bytes : 1, ALIGN);
         return r;
     };
-    o.Xb = take(bf ? n * o.ldb * 2 : 0);
     o.xn = take(bf ? n * 4 : 0);
-    o.xr = take(bf ? n * 4 : 0);
     o.st = take(n * sizeof(kp::PointState));
     o.lb = take(n * (size_t)o.gs * 4);
     o.c32 = take(kgm * o.ldc * 4);
     o.cb = take(bf ? kgm * o.ldb * 2 : 0);
+    o.cbl = take(bf ? kgm * o.ldb * 2 : 0);
     o.cn = take(kgm * 4);
-    o.cr = take(kgm * 4);
     o.c64 = take(kgm * d * 8);
     o.sums = take(kgm * d * 8);
     o.delta = take(kgm * 8);
@@ -88,8 +88,8 @@ Plan plan_problem(const kp_problem &p)
     o.L1 = take(n * 4);
     o.L1s = take(n * 4);
     const size_t ntiles = (n + 63) / 64;
-    o.tlist = take(ntiles * (size_t)g * 16);
-    o.tcnt = take(ntiles * 4);
+    o.tlist = take(bf ? 0 : ntiles * (size_t)g * 16);   // group-filter lists of the FP32 path
+    o.tcnt = take(bf ? 0 : ntiles * 4);
     o.ps4 = take(n * 16);
     o.psf = take(n * 4);
     o.mvp = take(n * 4);
@@ -377,15 +377,13 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.prec = p.precision;
         P.maxgs = G.maxgs;
         P.X = p.points_dev;
-        P.Xb = (uint16_t *)(base + o.Xb);
         P.xn = (float *)(base + o.xn);
-        P.xr = (float *)(base + o.xr);
         P.st = (kp::PointState *)(base + o.st);
         P.lb = (float *)(base + o.lb);
         P.c32 = (float *)(base + o.c32);
         P.cb = (uint16_t *)(base + o.cb);
+        P.cbl = (uint16_t *)(base + o.cbl);
         P.cn = (float *)(base + o.cn);
-        P.cr = (float *)(base + o.cr);
         P.c64 = (double *)(base + o.c64);
         P.sums = (double *)(base + o.sums);
         P.delta = (double *)(base + o.delta);

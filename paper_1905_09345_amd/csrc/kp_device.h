@@ -2,10 +2,8 @@
 //
 // Layout in HBM (per problem, all carved from the caller's workspace):
 //   X      n x d   FP32  caller's points, row-major, borrowed
-//   Xb     n x ldb BF16  round-to-nearest-even shadow of X, zero-padded to
-//                        ldb = roundup(d, 32) (BF16 mode only)
-//   xn     n       FP32  ||Xb_i||^2 (BF16 mode)
-//   xr     n       FP32  ||X_i - Xb_i|| rounded up (BF16 mode)
+//   xn     n       FP32  ||X_i||^2 (BF16 mode; the BF16 split of a point is
+//                        formed on the fly in LDS, ldb = roundup(d, 32))
 //   st     n       16 B  PointState: assigned slot and two bounds
 //   lb     n x gs  FP32  group-level lower bounds, gs = roundup(g, 4)
 //   centroids in "slot" order: the members of group q occupy slots
@@ -57,13 +55,12 @@ struct ProbDev {
     int prec;                 // 0 fp32 direct, 1 bf16 + recheck
     int maxgs;                // largest group size (real members)
     const float *X;
-    uint16_t *Xb;
-    float *xn, *xr;
+    float *xn;
     PointState *st;
     float *lb;
     float *c32;
-    uint16_t *cb;
-    float *cn, *cr;
+    uint16_t *cb, *cbl;       // BF16 split of c32: cb = bf16(c), cbl = bf16(c - cb)
+    float *cn;                // ||c32||^2 (BF16 mode; +inf for padding)
     double *c64, *sums, *delta;
     int *cnt;
     const int *perm;          // slot -> original index, -1 for padding
@@ -86,7 +83,7 @@ struct ProbDev {
     unsigned long long *ctr;  // NCTR counters of the running iteration
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
-    float *scal;              // [0] max ||c_hat||, [1] max ||c - c_hat||
+    float *scal;              // [0] max ||c32|| (rounded up)
 };
 
 // ---------------------------------------------------------------- rounding
@@ -182,15 +179,28 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
     const double r = s - rho;
     return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
-// eta of one point: the products of BF16 values are exact in FP32, so the
-// MFMA dot product carries at most gamma_ldb * ||xb|| ||cb||; the FP32 norms
-// carry u ||.||^2 each and the two final operations 2u (||xb|| + ||cb||)^2.
-// Everything is below (ldb + 4) u (||xb|| + ||cb||)^2; a factor 2 covers the
-// undocumented internal accumulation order of the matrix cores.
-__device__ __forceinline__ double mfma_eta(float xn, float bmax, int ldb)
+// eta of one point for the BF16x3 estimate v = fl(fl(xn + cn) - 2 S) of
+// ||x - c||^2, where S = hh + (lh + hl) and hh = xh.ch, lh = xl.ch, hl = xh.cl
+// are accumulated separately in FP32 on the matrix cores (exact products).
+// Rounding to nearest with 8-bit significands gives x = xh + xl + rx with
+// |xl_i| <= 2^-8 (1 + 2^-8) |x_i| and |rx_i| <= 2^-16 |x_i|; the same for c.
+// With u = 2^-24, A >= ||x||, C >= ||c||:
+//   |xh.ch + xl.ch + xh.cl - x.c| <= |xl.cl| + |rx.c| + |xh.rc| + |xl.rc|
+//                                  <= 3.02 * 2^-16 A C
+//   sums of ldb products, gamma_ldb sum |products| each, doubled for the
+//   unspecified summation order inside the matrix cores: <= 2.1 (ldb + 2) u A C
+//   the two adds forming S: <= 2.05 u A C
+// so |S - x.c| <= kappa A C.  xn and cn are FP64 norms rounded to FP32 (u each,
+// relative), xn + cn rounds once more, and the final fused multiply-add
+// rounds |xn + cn - 2S| <= 1.01 (A + C)^2 once:
+//   |v - ||x - c||^2| <= 3.02 u (A^2 + C^2) + (2 kappa + 2.02 u) A C.
+// The true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
+__device__ __forceinline__ double mfma_eta3(float xn, float bmax, int ldb)
 {
-    const double a = sqrt((double)xn) + (double)bmax;
-    return 2.0 * (double)(ldb + 4) * 5.9604644775390625e-08 * a * a * (1.0 + 0x1p-20);
+    const double u = 5.9604644775390625e-08;
+    const double A = sqrt((double)xn) * (1.0 + 0x1p-22), C = (double)bmax;
+    const double kappa = 3.02 * 0x1p-16 + 2.1 * (double)(ldb + 2) * u + 2.05 * u;
+    return (3.02 * u * (A * A + C * C) + (2.0 * kappa + 2.02 * u) * A * C) * (1.0 + 0x1p-20);
 }
 
 // --------------------------------------------------- tuple merge (d^2, slot, second)

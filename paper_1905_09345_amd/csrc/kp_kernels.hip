@@ -52,26 +52,15 @@ __device__ __forceinline__ long long positions(const ProbDev &P)
 }
 
 // ===================================================================== prep
-// BF16 shadow of the points, ||xb||^2 and the rounding residual ||x - xb||.
+// ||x||^2 of every point (FP64 sum of the FP32 coordinates, rounded to FP32).
 __global__ __launch_bounds__(256) void k_prep(ProbDev P)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
         const float *x = P.X + i * P.d;
-        uint16_t *xb = P.Xb + i * P.ldb;
-        double s = 0.0, r = 0.0;
-        for (int j = 0; j < P.ldb; j += 2) {
-            const float v0 = j < P.d ? x[j] : 0.f;
-            const float v1 = j + 1 < P.d ? x[j + 1] : 0.f;
-            const uint16_t h0 = f2bf(v0), h1 = f2bf(v1);
-            const float b0 = bf2f(h0), b1 = bf2f(h1);
-            *(uint32_t *)(xb + j) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-            s += (double)b0 * b0 + (double)b1 * b1;
-            const double e0 = (double)v0 - b0, e1 = (double)v1 - b1;
-            r += e0 * e0 + e1 * e1;
-        }
+        double s = 0.0;
+        for (int j = 0; j < P.d; ++j) s += (double)x[j] * x[j];
         P.xn[i] = (float)s;
-        P.xr[i] = d2f_up(sqrt(r) * (1.0 + 0x1p-46));
     }
 }
 
@@ -92,19 +81,21 @@ __global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
             if (INIT) {
                 for (int j = lane; j < L; j += WAVE) {
                     if (j < P.ldc) P.c32[(size_t)s * P.ldc + j] = 0.f;
-                    if (P.prec) P.cb[(size_t)s * P.ldb + j] = 0;
+                    if (P.prec) {
+                        P.cb[(size_t)s * P.ldb + j] = 0;
+                        P.cbl[(size_t)s * P.ldb + j] = 0;
+                    }
                     if (j < P.d) P.c64[(size_t)s * P.d + j] = 0.0;
                 }
                 if (lane == 0) {
                     P.cn[s] = KP_INF;
-                    P.cr[s] = 0.f;
                     P.delta[s] = 0.0;
                 }
             }
             continue;
         }
         const int cntv = INIT ? 0 : P.cnt[s];
-        double dd = 0.0, q = 0.0, r = 0.0;
+        double dd = 0.0, q = 0.0;
         for (int j = lane; j < L; j += WAVE) {
             double c64v = 0.0;
             float oldc = 0.f;
@@ -119,22 +110,20 @@ __global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
             }
             const float c32v = (float)c64v;
             if (j < P.ldc) P.c32[(size_t)s * P.ldc + j] = c32v;
-            const uint16_t h = f2bf(c32v);
-            const float hb = bf2f(h);
-            if (P.prec) P.cb[(size_t)s * P.ldb + j] = h;
+            if (P.prec) {
+                const uint16_t h = f2bf(c32v);
+                P.cb[(size_t)s * P.ldb + j] = h;
+                P.cbl[(size_t)s * P.ldb + j] = f2bf(c32v - bf2f(h));
+            }
             const double df = (double)c32v - (double)oldc;
             dd += df * df;
-            q += (double)hb * hb;
-            const double e = (double)c32v - hb;
-            r += e * e;
+            q += (double)c32v * c32v;
         }
         dd = wave_sum_d(dd);
         q = wave_sum_d(q);
-        r = wave_sum_d(r);
         if (lane == 0) {
             P.delta[s] = INIT ? 0.0 : sqrt(dd) * (1.0 + 0x1p-46);
             P.cn[s] = (float)q;
-            P.cr[s] = d2f_up(sqrt(r) * (1.0 + 0x1p-46));
         }
     }
 }
@@ -167,10 +156,7 @@ __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
         P.Sc[s] = sc;
         P.Scu[s] = d2f_up(sc);
         P.Scd[s] = d2f_dn(sc);
-        if (P.perm[s] >= 0) {
-            bmax = fmaxf(bmax, P.cn[s]);
-            rmax = fmaxf(rmax, P.cr[s]);
-        }
+        if (P.perm[s] >= 0) bmax = fmaxf(bmax, P.cn[s]);
     }
     red[tid] = gmax;
     redf[0][tid] = bmax;
@@ -190,7 +176,7 @@ __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
         P.Sdud[0] = d2f_up(sd);
         P.Sdud[1] = d2f_dn(sd);
         P.scal[0] = d2f_up(sqrt((double)redf[0][0]) * (1.0 + 0x1p-46));
-        P.scal[1] = redf[1][0];
+        P.scal[1] = 0.f;
         if (!first) {
             const int t = *P.iter + 1;
             long long *rec = P.stats + (size_t)((t - 1) % STATS_CAP) * 16;
@@ -512,12 +498,18 @@ __device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense
 }
 
 // ============================================== BF16 engine: MFMA per group
-// A wave owns 64 points (lane l <-> point l of the tile).  For one 16-slot
-// chunk of a group, v_mfma_f32_16x16x32_bf16 with A = the 16 centroids and
-// B = 16 points gives lane l the products of point (l & 15) of the block
-// with centroids 4*(l >> 4) .. +3 of the chunk.  Four blocks cover the 64
-// points; a transposing reduction over the four lane groups leaves lane l
-// with the (best, slot, second) of its own point for the chunk.
+// A FP32 vector is split as x = xh + xl + rx with xh = bf16(x) and
+// xl = bf16(x - xh) (x - xh is exact in FP32); the centroids the same way
+// (cb, cbl).  The dot product x.c is taken as xh.ch + xl.ch + xh.cl, each of
+// the three accumulated on the matrix cores (v_mfma_f32_16x16x32_bf16: exact
+// products, FP32 sums) in an accumulator of its own; mfma_eta3 bounds the
+// error of the resulting squared distance.
+//
+// One wave works on a tile of 16 points.  Lane l holds point (l & 15) of the
+// tile and coordinates 32 ks + 8 (l >> 4) .. +7 of its split row: the B
+// operand.  With A = a 16-slot chunk of one group (rows slot0 + (l & 15)),
+// the product gives lane l the estimates of its point against slots
+// slot0 + 4 (l >> 4) .. +3.
 __device__ __forceinline__ Best3 best_of4(const float v[4], int slot0)
 {
     Best3 b;
@@ -537,158 +529,148 @@ __device__ __forceinline__ Best3 best_of4(const float v[4], int slot0)
     return b;
 }
 
-// T[blk] holds, for point (16 blk + (l & 15)), the result over centroid rows
-// 4q .. 4q+3 (q = l >> 4).  Returns the merge over q of T[q'] for block q,
-// i.e. the result of point l.
-__device__ __forceinline__ Best3 transpose_reduce(const Best3 (&T)[4])
-{
-    const int q = lane_id() >> 4;
-    const bool hi = q >= 2;
-    Best3 U[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const Best3 keep = hi ? T[2 + j] : T[j];
-        const Best3 send = hi ? T[j] : T[2 + j];
-        U[j] = merge3(keep, shfl_xor3(send, 32));
-    }
-    const bool odd = q & 1;
-    const Best3 keep = odd ? U[1] : U[0];
-    const Best3 send = odd ? U[0] : U[1];
-    return merge3(keep, shfl_xor3(send, 16));
-}
-
-// B fragments of the tile: point 16*blk + (l & 15), k = ks*32 + 8*(l >> 4) .. +7.
 template <int KS>
-__device__ __forceinline__ void load_bfrag(const ProbDev &P, int pid, unsigned long long amask, bf16x8 (&bx)[4][KS],
-                                           float (&xnB)[4])
-{
-    const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
-#pragma unroll
-    for (int blk = 0; blk < 4; ++blk) {
-        const int src = 16 * blk + col;
-        const int p = __shfl(pid, src);
-        const bool ok = (amask >> src) & 1ull;
-        xnB[blk] = ok ? P.xn[p] : 0.f;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            if (ok) bx[blk][ks] = *(const bf16x8 *)(P.Xb + (size_t)p * P.ldb + ks * 32 + 8 * quad);
-            else bx[blk][ks] = bf16x8{};
-        }
-    }
-}
-
-// Centroid fragments of one 16-slot chunk: A rows slot0 + (l & 15),
-// k = ks*32 + 8*(l >> 4) .. +7, and the four norms of the lane's rows.
-template <int KS>
-struct AFrag {
-    bf16x8 a[KS];
-    float4 cn;
+struct PtFrag {
+    bf16x8 h[KS], l[KS];
 };
 template <int KS>
-__device__ __forceinline__ void load_afrag(const ProbDev &P, int slot0, AFrag<KS> &f)
+struct CtFrag {
+    bf16x8 h[KS], l[KS];
+    float4 cn;   // ||c||^2 of slots slot0 + 4 (l >> 4) .. +3 (+inf for padding)
+};
+
+// Split of 8 FP32 values (conversions round to nearest even).
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &h, bf16x8 &l)
 {
-    const int lane = lane_id(), col = lane & 15, quad = lane >> 4;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) f.a[ks] = *(const bf16x8 *)(P.cb + (size_t)(slot0 + col) * P.ldb + ks * 32 + 8 * quad);
+    for (int j = 0; j < 8; ++j) {
+        const __bf16 t = (__bf16)v[j];
+        h[j] = t;
+        l[j] = (__bf16)(v[j] - (float)t);
+    }
+}
+
+// The tile's B operand from the FP32 rows; zero beyond d and for absent points.
+template <int KS>
+__device__ __forceinline__ void load_points16(const ProbDev &P, int pid, bool ok, PtFrag<KS> &b)
+{
+    const int quad = lane_id() >> 4;
+    const float *xr = P.X + (size_t)pid * P.d;
+    float v[KS][8];
+    if ((P.d & 3) == 0 && ((uintptr_t)P.X & 15) == 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k0 = 32 * ks + 8 * quad;   // d % 4 == 0: a float4 is wholly inside or outside
+            const float4 p0 = (ok && k0 < P.d) ? *(const float4 *)(xr + k0) : z;
+            const float4 p1 = (ok && k0 + 4 < P.d) ? *(const float4 *)(xr + k0 + 4) : z;
+            v[ks][0] = p0.x;
+            v[ks][1] = p0.y;
+            v[ks][2] = p0.z;
+            v[ks][3] = p0.w;
+            v[ks][4] = p1.x;
+            v[ks][5] = p1.y;
+            v[ks][6] = p1.z;
+            v[ks][7] = p1.w;
+        }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * ks + 8 * quad + j;
+                v[ks][j] = (ok && k < P.d) ? xr[k] : 0.f;
+            }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
+}
+
+// The A operand: one 16-slot chunk (rows padded with zeros to ldb = 32 KS).
+template <int KS>
+__device__ __forceinline__ void load_chunk16(const ProbDev &P, int slot0, CtFrag<KS> &f)
+{
+    const int lane = lane_id(), quad = lane >> 4;
+    const size_t row = (size_t)(slot0 + (lane & 15)) * P.ldb + 8 * quad;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        f.h[ks] = *(const bf16x8 *)(P.cb + row + 32 * ks);
+        f.l[ks] = *(const bf16x8 *)(P.cbl + row + 32 * ks);
+    }
     f.cn = *(const float4 *)(P.cn + slot0 + 4 * quad);
 }
 
-// One chunk: MFMA estimates of ||xb - cb||^2 for the blocks named in m,
-// reduced to the lane's own point.
+// Estimates of one chunk, reduced over the four lane groups: every lane of
+// point p returns the (best, slot, second) of p over the chunk.
 template <int KS>
-__device__ __forceinline__ Best3 mfma_chunk(const AFrag<KS> &f, int slot0, unsigned long long m,
-                                            const bf16x8 (&bx)[4][KS], const float (&xnB)[4])
+__device__ __forceinline__ Best3 chunk16(const CtFrag<KS> &f, const PtFrag<KS> &b, int slot0, float xnp)
 {
-    const int quad = lane_id() >> 4;
-    const float cnv[4] = {f.cn.x, f.cn.y, f.cn.z, f.cn.w};
-    Best3 T[4];
+    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lh = {0.f, 0.f, 0.f, 0.f}, hl = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int blk = 0; blk < 4; ++blk) {
-        if ((m >> (16 * blk)) & 0xFFFFull) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks], bx[blk][ks], acc, 0, 0, 0);
-            float v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, acc[r], xnB[blk] + cnv[r]);
-            T[blk] = best_of4(v, slot0 + 4 * quad);
-        } else {
-            T[blk].m1 = KP_INF;
-            T[blk].s1 = INT_MAX;
-            T[blk].m2 = KP_INF;
-        }
+    for (int ks = 0; ks < KS; ++ks) {
+        hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.h[ks], b.h[ks], hh, 0, 0, 0);
+        lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.l[ks], b.h[ks], lh, 0, 0, 0);
+        hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.h[ks], b.l[ks], hl, 0, 0, 0);
     }
-    return transpose_reduce(T);
+    const float cnv[4] = {f.cn.x, f.cn.y, f.cn.z, f.cn.w};
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, hh[r] + (lh[r] + hl[r]), xnp + cnv[r]);
+    Best3 t = best_of4(v, slot0 + 4 * (lane_id() >> 4));
+    t = merge3(t, shfl_xor3(t, 16));
+    return merge3(t, shfl_xor3(t, 32));
 }
 
-// The chunks of a list of (group, block mask) visits, with the fragments of
-// the next chunk loaded while the current one is computed.  The visit table
-// is loaded 64 entries at a time, one entry per lane (entry(k, g, m) gives
-// entry k), so the address of every next chunk is known without waiting on
-// memory.  done(g, m, gb) receives each group's result.
-template <int KS, class Entry, class Done>
-__device__ __forceinline__ void mfma_visits(const ProbDev &P, int nvisits, Entry entry, Done done,
-                                            const bf16x8 (&bx)[4][KS], const float (&xnB)[4])
+// The visits of one tile.  Each set bit j of vmask names lane j, which holds
+// one visit: group tg, 16-bit point mask tm, first slot ts0 and size tns
+// (>= 1).  The fragments of the next chunk are loaded while the current one
+// is on the matrix cores.  done(g, m, ns, gb) receives each visit's result.
+template <int KS, class Done>
+__device__ __forceinline__ void tile_visits(const ProbDev &P, unsigned long long vmask, int tg, unsigned tm, int ts0,
+                                            int tns, const PtFrag<KS> &b, float xnp, Done done)
 {
-    if (nvisits <= 0) return;
-    const int lane = lane_id();
-    // lane-held table of visits wb .. wb+63
-    int tg = 0, ts0 = 0, tns = 0;
-    unsigned tmlo = 0u, tmhi = 0u;
-    int wb = -WAVE;
-    auto fetch = [&](int i, int &g, unsigned long long &m, int &s0, int &ns) {
-        if (i >= wb + WAVE) {   // uniform: next window
-            wb = i & ~(WAVE - 1);
-            const int k = wb + lane;
-            if (k < nvisits) {
-                unsigned long long mk;
-                entry(k, tg, mk);
-                tmlo = (unsigned)mk;
-                tmhi = (unsigned)(mk >> 32);
-                ts0 = P.gstart[tg];
-                tns = P.gsize[tg];
-            }
-        }
-        const int l = i - wb;
-        g = __builtin_amdgcn_readlane(tg, l);
-        s0 = __builtin_amdgcn_readlane(ts0, l);
-        ns = __builtin_amdgcn_readlane(tns, l);
-        m = (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)tmlo, l) |
-            ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)tmhi, l) << 32);
+    if (vmask == 0ull) return;
+    struct Cur {
+        int g, s0, ns, c0;
+        unsigned m;
     };
-    int g, s0, ns, i = 0, c0 = 0;
-    unsigned long long m;
-    fetch(0, g, m, s0, ns);
-    AFrag<KS> cur, nxt;
-    load_afrag<KS>(P, s0, cur);
+    auto take = [&](Cur &c) {
+        const int j = __ffsll((long long)vmask) - 1;
+        vmask &= vmask - 1ull;
+        c.g = __builtin_amdgcn_readlane(tg, j);
+        c.s0 = __builtin_amdgcn_readlane(ts0, j);
+        c.ns = __builtin_amdgcn_readlane(tns, j);
+        c.m = (unsigned)__builtin_amdgcn_readlane((int)tm, j);
+        c.c0 = 0;
+    };
+    Cur c;
+    take(c);
+    CtFrag<KS> fa, fb;
+    load_chunk16<KS>(P, c.s0, fa);
     Best3 gb = {KP_INF, INT_MAX, KP_INF};
-    for (;;) {
-        // the chunk after (i, c0)
-        int ni = i, nc0 = c0 + CHUNK, ng = g, ns0 = s0, nns = ns;
-        unsigned long long nm = m;
-        if (nc0 >= ns) {
-            ni = i + 1;
-            nc0 = 0;
-            if (ni < nvisits) fetch(ni, ng, nm, ns0, nns);
+    // one chunk; false after the last
+    auto step = [&](const CtFrag<KS> &cur, CtFrag<KS> &nxt) -> bool {
+        Cur n = c;
+        n.c0 += CHUNK;
+        bool more = true;
+        if (n.c0 >= n.ns) {
+            if (vmask) take(n);
+            else more = false;
         }
-        const bool more = ni < nvisits;
-        if (more) load_afrag<KS>(P, ns0 + nc0, nxt);
-        gb = merge3(gb, mfma_chunk<KS>(cur, s0 + c0, m, bx, xnB));
-        if (nc0 == 0) {   // group i complete
-            done(g, m, gb);
+        if (more) load_chunk16<KS>(P, n.s0 + n.c0, nxt);
+        gb = merge3(gb, chunk16<KS>(cur, b, c.s0 + c.c0, xnp));
+        if (!more || n.c0 == 0) {
+            done(c.g, c.m, c.ns, gb);
             gb.m1 = KP_INF;
             gb.s1 = INT_MAX;
             gb.m2 = KP_INF;
         }
-        if (!more) break;
-        i = ni;
-        c0 = nc0;
-        g = ng;
-        m = nm;
-        s0 = ns0;
-        ns = nns;
-        cur = nxt;
+        c = n;
+        return more;
+    };
+    for (;;) {
+        if (!step(fa, fb)) break;
+        if (!step(fb, fa)) break;
     }
 }
 
@@ -797,63 +779,6 @@ __global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
     }
 }
 
-template <int KS>
-__global__ __launch_bounds__(256) void k_dense_bf16(ProbDev P)
-{
-    const int lane = lane_id();
-    const int wpb = blockDim.x / WAVE;
-    const double eps2 = eps2_direct(P.ldb);
-    const float bmax = P.scal[0], rcmax = P.scal[1];
-    const float sdd = P.Sdud[1];
-    const long long ntiles = (P.n + WAVE - 1) / WAVE;
-    unsigned long long n_moved = 0, n_amb = 0;
-    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)gridDim.x * wpb) {
-        const long long idx = tl * WAVE + lane;
-        const bool act = idx < P.n;
-        const int pid = act ? (int)idx : 0;
-        const unsigned long long amask = __ballot(act);
-        bf16x8 bx[4][KS];
-        float xnB[4];
-        load_bfrag<KS>(P, pid, amask, bx, xnB);
-        const double eta = mfma_eta(P.xn[pid], bmax, P.ldb);
-        const double rho = (double)P.xr[pid] + (double)rcmax;
-        Run r;
-        run_init(r);
-        float *lbrow = P.lb + (size_t)pid * P.gs;
-        mfma_visits<KS>(
-            P, P.g, [&](int k, int &g, unsigned long long &m) { g = k; m = amask; },
-            [&](int g, unsigned long long, const Best3 &gb) {
-                if (act) {   // lanes past the end may hold a skipped block's sentinel
-                    lbrow[g] = store_lb(mfma_lo(gb.m1, eta, rho), P.Sgd[g]);
-                    run_fold(P, r, gb, g);
-                }
-            },
-            bx, xnB);
-        bool moved = false, amb = false;
-        int win = -1;
-        float umin = KP_INF;
-        if (act)
-            decide_bf16(P, pid, true, -1, -1, false, KP_INF, KP_INF, KP_INF, KP_INF, r, eta, rho, eps2, sdd, moved,
-                        amb, win, umin);
-        if (act) {
-            P.mv_pt[pid] = pid;
-            P.mv_old[pid] = -1;
-            P.mv_new[pid] = moved ? win : -1;
-            P.psf[pid] = amb ? 4 : 0;
-            if (amb) P.ps4[pid] = make_float4(0.f, 0.f, umin, 0.f);
-        }
-        n_moved += (unsigned long long)__popcll(__ballot(moved));
-        n_amb += (unsigned long long)__popcll(__ballot(amb));
-    }
-    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
-    if (lane == 0 && n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&P.ctr[CTR_PAIRS], (unsigned long long)P.n * (unsigned long long)P.g);
-        atomicAdd(&P.ctr[CTR_DIST], (unsigned long long)P.n * (unsigned long long)P.k);
-    }
-}
-
 // ================================================ group-level filter (phase 1)
 // One wave per tile of 64 consecutive entries of the sorted L1 (lane = point
 // of the tile).  Every group bound of each point is tested against the
@@ -893,7 +818,6 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
             ga = P.slot_group[a];
             ubt = ub_now(s.u, P.Scu[a]);
         }
-        const unsigned long long amask = __ballot(act);
         int cnt = 0;
         int4 *lst = P.tlist + (size_t)tl * P.g;
         for (int g0 = 0; g0 < P.g; g0 += GT_CH) {
@@ -999,73 +923,146 @@ __global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
 
-template <int KS>
-__global__ __launch_bounds__(256) void k_tile_bf16(ProbDev P)
+// One wave per tile of 16 positions (BF16 mode).  DENSE (iteration 1): the
+// positions are the points and every group is visited.  Otherwise the
+// positions are entries of the sorted L1: each point's own group is visited
+// first, which tightens its upper bound to the best estimate there; then the
+// group bounds of the 16 points are tested against the tightened bounds with
+// lanes over groups, and every group open for some point is visited with the
+// mask of those points.  Per point: the decision under the error bound, or
+// the flag that sends it to the FP32 recheck.
+template <int KS, bool DENSE>
+__global__ __launch_bounds__(256, KS <= 4 ? 3 : (KS <= 6 ? 2 : 1)) void k_tile16(ProbDev P)
 {
-    const int lane = lane_id();
-    const int wpb = blockDim.x / WAVE;
-    const double eps2 = eps2_direct(P.ldb);
-    const float bmax = P.scal[0], rcmax = P.scal[1];
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4;
+    const float bmax = P.scal[0];
     const float sdd = P.Sdud[1];
-    const long long count = list_len(P, CTR_L1);
-    const long long ntiles = (count + WAVE - 1) / WAVE;
-    unsigned long long n_dist = 0, n_moved = 0, n_amb = 0;
-    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)gridDim.x * wpb) {
-        const long long idx = tl * WAVE + lane;
+    const long long count = DENSE ? P.n : list_len(P, CTR_L1);
+    const long long ntiles = (count + 15) / 16;
+    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0, n_amb = 0;
+    for (long long tl = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; tl < ntiles; tl += nw) {
+        const long long idx = tl * 16 + pt;
         const bool in = idx < count;
-        const int flags = in ? P.psf[idx] : 0;
-        const bool act = flags & 1, a_sep = flags & 2;
-        const unsigned long long amask = __ballot(act);
-        if (amask == 0ull) continue;
-        const int pid = in ? clamp_pid(P, P.L1s[idx]) : 0;
-        const float4 q = in ? P.ps4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float ubt = q.x, minnc = q.y, lbe_a = q.z, d2a = q.w;
-        const int a = act ? clamp_slot(P, P.st[pid].a) : 0;
-        const int ga = P.slot_group[a];
-        bf16x8 bx[4][KS];
-        float xnB[4];
-        load_bfrag<KS>(P, pid, amask, bx, xnB);
-        const double eta = mfma_eta(P.xn[pid], bmax, P.ldb);
-        const double rho = (double)P.xr[pid] + (double)rcmax;
+        const int pid = in ? (DENSE ? (int)idx : clamp_pid(P, P.L1s[idx])) : 0;
+        int a = -1, ga = -1;
+        float ubt = KP_INF;
+        if (!DENSE && in) {
+            const PointState s = P.st[pid];
+            a = clamp_slot(P, s.a);
+            ga = min(max(P.slot_group[a], 0), P.g - 1);
+            ubt = ub_now(s.u, P.Scu[a]);
+        }
+        const float xnp = in ? P.xn[pid] : 0.f;
+        const double eta = mfma_eta3(xnp, bmax, P.ldb);
+        const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // lanes 0..15 <-> the 16 points
+        PtFrag<KS> b;
+        load_points16<KS>(P, pid, in, b);
         Run r;
         run_init(r);
-        const int cnt = min(max(P.tcnt[tl], 0), P.g);
-        const int4 *lst = P.tlist + (size_t)tl * P.g;
-        mfma_visits<KS>(
-            P, cnt,
-            [&](int k, int &g, unsigned long long &m) {
-                const int4 e = lst[k];
-                g = min(max(e.x, 0), P.g - 1);
-                m = (unsigned long long)(unsigned)e.y | ((unsigned long long)(unsigned)e.z << 32);
-            },
-            [&](int g, unsigned long long m, const Best3 &gb) {
-                n_dist += (unsigned long long)__popcll(m) * (unsigned long long)P.gsize[g];
-                if ((m >> lane) & 1ull) {
-                    P.lb[(size_t)pid * P.gs + g] = store_lb(mfma_lo(gb.m1, eta, rho), P.Sgd[g]);
-                    run_fold(P, r, gb, g);
+        auto done = [&](int g, unsigned m, int ns, const Best3 &gb) {
+            n_visits += 1;
+            n_pairs += (unsigned long long)__popc(m);
+            n_dist += (unsigned long long)__popc(m) * (unsigned long long)ns;
+            if ((m >> pt) & 1u) {
+                run_fold(P, r, gb, g);
+                if (quad == 0) P.lb[(size_t)pid * P.gs + g] = store_lb(mfma_lo(gb.m1, eta, 0.0), P.Sgd[g]);
+            }
+        };
+        float minnc = KP_INF;
+        if (DENSE) {
+            for (int g0 = 0; g0 < P.g; g0 += WAVE) {
+                const int g = g0 + lane;
+                const bool gv = g < P.g;
+                const int s0 = gv ? P.gstart[g] : 0, ns = gv ? P.gsize[g] : 0;
+                tile_visits<KS>(P, __ballot(gv && ns > 0), g, inm, s0, ns, b, xnp, done);
+            }
+        } else {
+            // own groups (at most 16 distinct), visit i held by lane i
+            int tg = 0, nv = 0;
+            unsigned tm = 0u;
+            for (unsigned todo = inm; todo;) {
+                const int p = __ffs(todo) - 1;
+                const int g = __builtin_amdgcn_readlane(ga, p);
+                const unsigned m = (unsigned)__ballot(in && ga == g) & 0xFFFFu;
+                if (lane == nv) {
+                    tg = g;
+                    tm = m;
                 }
-            },
-            bx, xnB);
+                ++nv;
+                todo &= ~m;
+            }
+            {
+                const bool own = lane < nv;
+                const int s0 = own ? P.gstart[tg] : 0, ns = own ? P.gsize[tg] : 0;
+                tile_visits<KS>(P, __ballot(own && ns > 0), tg, tm, s0, ns, b, xnp, done);
+            }
+            const float ubn = fminf(ubt, mfma_hi(r.bd, eta, 0.0));
+            // group-level filter, 64 groups per round: lane (point p, quad q)
+            // tests groups g0 + 16 q .. +15 of point p (one 64-byte run of its
+            // bound row); lane t then holds the visit of group g0 + t
+            const float *lbrow = P.lb + (size_t)pid * P.gs;
+            for (int g0 = 0; g0 < P.g; g0 += WAVE) {
+                const int gq = g0 + 16 * quad;
+                float v[16], sg[16];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int gi = gq + 4 * i;   // gs and the Sgu allocation are padded to 4
+                    const bool ok = in && gi < P.g;
+                    const float4 v4 = ok ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float4 s4 = ok ? *(const float4 *)(P.Sgu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[4 * i] = v4.x;
+                    v[4 * i + 1] = v4.y;
+                    v[4 * i + 2] = v4.z;
+                    v[4 * i + 3] = v4.w;
+                    sg[4 * i] = s4.x;
+                    sg[4 * i + 1] = s4.y;
+                    sg[4 * i + 2] = s4.z;
+                    sg[4 * i + 3] = s4.w;
+                }
+                float cm = KP_INF;
+                unsigned long long mine = 0ull;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int g = gq + j;
+                    const bool cand = in && g < P.g && g != ga;
+                    const bool open = cand && group_open(ubn, sg[j], v[j]);
+                    if (cand && !open) cm = fminf(cm, lb_now(v[j], sg[j]));
+                    const unsigned long long bj = __ballot(open);
+                    if ((lane & 15) == j) mine = bj;
+                }
+                cm = fminf(cm, __shfl_xor(cm, 16));
+                minnc = fminf(minnc, fminf(cm, __shfl_xor(cm, 32)));
+                const unsigned tm = (unsigned)(mine >> (16 * quad)) & 0xFFFFu;
+                const int tg = g0 + lane;
+                const bool gv = tg < P.g;
+                const int s0 = gv ? P.gstart[tg] : 0, ns = gv ? P.gsize[tg] : 0;
+                tile_visits<KS>(P, __ballot(gv && tm != 0u && ns > 0), tg, tm, s0, ns, b, xnp, done);
+            }
+        }
         bool moved = false, amb = false;
-        int win = -1;
-        float umin = KP_INF;
-        if (act)
-            decide_bf16(P, pid, false, a, ga, a_sep, ubt, d2a, lbe_a, minnc, r, eta, rho, eps2, sdd, moved, amb, win,
-                        umin);
-        if (in) {
-            P.mv_pt[idx] = pid;
-            P.mv_old[idx] = a;
-            P.mv_new[idx] = moved ? win : -1;
-            P.psf[idx] = amb ? 4 : 0;
-            if (amb) P.ps4[idx] = make_float4(0.f, 0.f, umin, 0.f);
+        if (in && quad == 0) {
+            int win = -1;
+            float umin = KP_INF;
+            decide_bf16(P, pid, DENSE, a, -1, false, KP_INF, KP_INF, KP_INF, minnc, r, eta, 0.0, 0.0, sdd, moved,
+                        amb, win, umin);
+            const long long pos = DENSE ? (long long)pid : idx;
+            P.mv_pt[pos] = pid;
+            P.mv_old[pos] = a;
+            P.mv_new[pos] = moved ? win : -1;
+            P.psf[pos] = amb ? 4 : 0;
+            if (amb) P.ps4[pos] = make_float4(0.f, 0.f, umin, 0.f);
         }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
         n_amb += (unsigned long long)__popcll(__ballot(amb));
     }
-    if (lane == 0 && n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
-    if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
-    if (lane == 0 && n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
+    if (lane == 0) {
+        if (n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
+        if (n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
+        if (n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
+        if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
+        if (n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
+    }
 }
 
 // ================================================================ recheck
@@ -1468,6 +1465,27 @@ hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
     return hipGetLastError();
 }
 
+// BF16 mode: one wave per 16 positions; KS = ldb / 32 in {1, 2, 3, 4, 6, 8}.
+template <bool DENSE>
+static void launch_tile16_ks(const ProbDev &P, hipStream_t s, int grid)
+{
+    switch (P.ldb / 32) {
+    case 1: hipLaunchKernelGGL((k_tile16<1, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 2: hipLaunchKernelGGL((k_tile16<2, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL((k_tile16<3, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL((k_tile16<4, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 6: hipLaunchKernelGGL((k_tile16<6, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 8: hipLaunchKernelGGL((k_tile16<8, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    default: break;   // excluded when the plan is made
+    }
+}
+static void launch_tile16(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, bool dense)
+{
+    const int grid = cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap);
+    if (dense) launch_tile16_ks<true>(P, s, grid);
+    else launch_tile16_ks<false>(P, s, grid);
+}
+
 static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
 {
     const int threads = 64 * cfg.waves;
@@ -1480,16 +1498,7 @@ static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
         else if (dm <= 64) hipLaunchKernelGGL(k_dense_f32<64>, dim3(grid), dim3(threads), 0, s, P);
         else hipLaunchKernelGGL(k_dense_f32<128>, dim3(grid), dim3(threads), 0, s, P);
     } else {
-        switch (P.ldb / 32) {
-        case 1: hipLaunchKernelGGL(k_dense_bf16<1>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 2: hipLaunchKernelGGL(k_dense_bf16<2>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 3: hipLaunchKernelGGL(k_dense_bf16<3>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 4: hipLaunchKernelGGL(k_dense_bf16<4>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 5: hipLaunchKernelGGL(k_dense_bf16<5>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 6: hipLaunchKernelGGL(k_dense_bf16<6>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 7: hipLaunchKernelGGL(k_dense_bf16<7>, dim3(grid), dim3(threads), 0, s, P); break;
-        default: hipLaunchKernelGGL(k_dense_bf16<8>, dim3(grid), dim3(threads), 0, s, P); break;
-        }
+        launch_tile16(P, s, cfg, true);
     }
 }
 
@@ -1507,17 +1516,7 @@ static void launch_survivors(const ProbDev &P, hipStream_t s, const LaunchCfg &c
         else if (dm <= 64) hipLaunchKernelGGL(k_tile_f32<64>, dim3(grid), dim3(threads), 0, s, P);
         else hipLaunchKernelGGL(k_tile_f32<128>, dim3(grid), dim3(threads), 0, s, P);
     } else {
-        hipLaunchKernelGGL(k_group_test, dim3(gt_grid), dim3(WAVE * GT_WAVES), 0, s, P);
-        switch (P.ldb / 32) {
-        case 1: hipLaunchKernelGGL(k_tile_bf16<1>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 2: hipLaunchKernelGGL(k_tile_bf16<2>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 3: hipLaunchKernelGGL(k_tile_bf16<3>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 4: hipLaunchKernelGGL(k_tile_bf16<4>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 5: hipLaunchKernelGGL(k_tile_bf16<5>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 6: hipLaunchKernelGGL(k_tile_bf16<6>, dim3(grid), dim3(threads), 0, s, P); break;
-        case 7: hipLaunchKernelGGL(k_tile_bf16<7>, dim3(grid), dim3(threads), 0, s, P); break;
-        default: hipLaunchKernelGGL(k_tile_bf16<8>, dim3(grid), dim3(threads), 0, s, P); break;
-        }
+        launch_tile16(P, s, cfg, false);
     }
 }
 
