@@ -159,7 +159,8 @@ def main():
                 "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
-    dom = max(agg, key=lambda nm: agg[nm]["ms"])
+    # the dominant kernel stage (the whole-replay entry is a sum of stages)
+    dom = max((nm for nm in agg if nm != "filtered_iter"), key=lambda nm: agg[nm]["ms"])
     roofline = roofline_of(dom, agg[dom], P, st)
     del runs
     torch.cuda.empty_cache()
@@ -190,19 +191,56 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def assign_bytes(P, s):
+    """Algorithmic HBM bytes of one filtered assignment launch (BF16 mode): per
+    entry of L1 its FP32 row, its bound row, the sorted entry, the new state,
+    the update entries and the flag; per visited (point, group) pair the new
+    bound; per uncertain point its recheck record."""
+    per_point = 4 * P.d + 4 * P.g + 16 + 16 + 12 + 4
+    return s["point_filter_fail"] * per_point + s["pairs"] * 4 + s["rechecks"] * 16
+
+
+def traffic_of(kernel, workload):
+    """Measured HBM bytes per launch from the committed counter summary, if it
+    was taken on the kernel source as it is now; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    import hashlib
+    src = os.path.join(ROOT, "paper_1905_09345_amd", "csrc", "kp_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    ent = rec.get(kernel, {})
+    if ent.get("source_sha256") != digest or ent.get("workload") != workload:
+        return None
+    return ent.get("bytes_per_launch")
+
+
 def roofline_of(stage, a, P, st):
     """Achieved rate of the dominant stage from its algorithmic work per launch."""
     ms_per_launch = a["ms"] / max(a["launches"], 1e-9)
+    wl = P.meta["name"]
+    if stage == "assign" and P.precision == "bf16":
+        filt = [s for s in st if not s["dense"]]
+        byts = sum(assign_bytes(P, s) for s in filt) / max(len(filt), 1)
+        ach = byts / (ms_per_launch * 1e-3) / 1e9
+        return dict(kernel="k_blk64 (filtered iteration: group filter + BF16x3 survivor distances)", bound="hbm",
+                    achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    traffic=traffic_of("k_blk64_filtered", wl),
+                    work_per_launch="%.4g B (per L1 entry 4d+4g+60 B, per pair 4 B, per recheck 16 B)" % byts,
+                    ms_per_launch=ms_per_launch)
     if stage == "assign_dense":
         flops = 2.0 * P.n * P.k * P.d
         ach = flops / (ms_per_launch * 1e-3) / 1e12
         if P.precision == "bf16":
-            return dict(kernel="k_assign_bf16 (dense, iteration 1)", bound="mfma", achieved=ach,
-                        peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / MFMA_BF16_PEAK_TFLOPS,
-                        traffic=None, work_per_launch="2*N*K*D = %.4g flop" % flops,
-                        ms_per_launch=ms_per_launch)
+            # three BF16 products per distance on the matrix cores
+            return dict(kernel="k_blk64 (dense iteration 1, BF16x3)", bound="mfma", achieved=3 * ach,
+                        peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=3 * ach / MFMA_BF16_PEAK_TFLOPS,
+                        traffic=traffic_of("k_blk64_dense", wl),
+                        work_per_launch="3*2*N*K*D = %.4g flop" % (3 * flops), ms_per_launch=ms_per_launch)
         peak = 78.6   # FP32 vector FMA without packed instructions (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
-        return dict(kernel="k_assign_f32 (dense, iteration 1)", bound="alu", achieved=ach, peak=peak,
+        return dict(kernel="k_dense_f32 (dense, iteration 1)", bound="alu", achieved=ach, peak=peak,
                     unit="TFLOP/s", frac=ach / peak, traffic=None,
                     work_per_launch="2*N*K*D = %.4g flop" % flops, ms_per_launch=ms_per_launch)
     if stage == "bound_filter":

@@ -37,7 +37,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
         cursor1, ctr, stats, iter, scal;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
@@ -87,6 +87,7 @@ Plan plan_problem(const kp_problem &p)
     o.Sdud = take(8);
     o.L1 = take(n * 4);
     o.L1s = take(n * 4);
+    o.L1x = take(bf ? n * 16 : 0);
     const size_t ntiles = (n + 63) / 64;
     o.tlist = take(bf ? 0 : ntiles * (size_t)g * 16);   // group-filter lists of the FP32 path
     o.tcnt = take(bf ? 0 : ntiles * 4);
@@ -227,6 +228,26 @@ struct StageTimer {
         pool.pop_back();
         return hipEventRecord(r.a, s);
     }
+    // a fresh event pair for a stage recorded inside a graph replay
+    hipError_t take(int stage, Rec &r)
+    {
+        r.stage = stage;
+        if (pool.empty()) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return e;
+            }
+            pool.push_back({a, b});
+        }
+        r.a = pool.back().first;
+        r.b = pool.back().second;
+        pool.pop_back();
+        return hipSuccess;
+    }
     hipError_t end(hipStream_t s, Rec &r)
     {
         hipError_t e = hipEventRecord(r.b, s);
@@ -274,6 +295,11 @@ struct kp_ctx {
     bool poisoned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // timing inside the graph: event-record nodes around each stage, pointed
+    // at fresh events before every replay
+    std::vector<hipEvent_t> cap_events;        // placeholders recorded at capture
+    std::vector<hipGraphNode_t> ev_nodes;      // 2 per timed stage: begin, end
+    std::vector<int> ev_stage;
 };
 
 // Frees the ctx's host resources, stream, events and graph without touching
@@ -285,6 +311,7 @@ static void release_ctx(kp_ctx *ctx)
     ctx->timer.destroy();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (hipEvent_t e : ctx->cap_events) (void)hipEventDestroy(e);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
@@ -402,6 +429,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Sdud = (float *)(base + o.Sdud);
         P.L1 = (int *)(base + o.L1);
         P.L1s = (int *)(base + o.L1s);
+        P.L1x = (int4 *)(base + o.L1x);
         P.tlist = (int4 *)(base + o.tlist);
         P.tcnt = (int *)(base + o.tcnt);
         P.ps4 = (float4 *)(base + o.ps4);
@@ -467,6 +495,103 @@ static hipError_t launch_all(kp_ctx *ctx, bool dense)
     return hipSuccess;
 }
 
+// Captures one filtered iteration of every problem into ctx->graph.  With
+// timing on, each stage is captured into a graph of its own and the
+// iteration graph chains them as child graphs between event-record nodes
+// (placeholder events, re-pointed before each replay); if the runtime
+// refuses that, the graph is captured in one piece and only the whole
+// replay is timed.
+static hipError_t capture_plain(kp_ctx *ctx)
+{
+    hipError_t e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (auto &P : ctx->P) {
+        e = kp::launch_iteration(P, ctx->own, false, ctx->cfg);
+        if (e != hipSuccess) break;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->own, &g);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    ctx->graph = g;
+    return hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+}
+
+static hipError_t capture_timed(kp_ctx *ctx, const char **where)
+{
+    *where = "create graph";
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    ctx->graph = g;
+    hipGraphNode_t last = nullptr;
+    auto add_event = [&](hipEvent_t &ev) -> hipError_t {
+        hipError_t r = hipEventCreate(&ev);
+        if (r != hipSuccess) return r;
+        ctx->cap_events.push_back(ev);
+        hipGraphNode_t nd = nullptr;
+        r = hipGraphAddEventRecordNode(&nd, g, last ? &last : nullptr, last ? 1 : 0, ev);
+        if (r != hipSuccess) return r;
+        ctx->ev_nodes.push_back(nd);
+        last = nd;
+        return hipSuccess;
+    };
+    for (auto &P : ctx->P) {
+        kp::Stage sts[kp::ST_COUNT];
+        const int n = kp::iteration_stages(P, false, sts);
+        for (int i = 0; i < n; ++i) {
+            hipEvent_t a = nullptr, b = nullptr;
+            *where = "event-record node";
+            if ((e = add_event(a)) != hipSuccess) return e;
+            *where = "stage capture";
+            if ((e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+            e = kp::launch_stage(P, ctx->own, sts[i], false, ctx->cfg);
+            hipGraph_t sg = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(ctx->own, &sg);
+            if (e == hipSuccess) e = e2;
+            if (e != hipSuccess) {
+                if (sg) (void)hipGraphDestroy(sg);
+                return e;
+            }
+            *where = "child graph node";
+            hipGraphNode_t cn = nullptr;
+            e = hipGraphAddChildGraphNode(&cn, g, &last, 1, sg);
+            (void)hipGraphDestroy(sg);   // the node holds its own copy
+            if (e != hipSuccess) return e;
+            last = cn;
+            *where = "event-record node";
+            if ((e = add_event(b)) != hipSuccess) return e;
+            ctx->ev_stage.push_back(sts[i]);
+        }
+    }
+    *where = "instantiate";
+    return hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+}
+
+static hipError_t capture_iteration(kp_ctx *ctx)
+{
+    if (ctx->timing) {
+        const char *where = "";
+        const hipError_t e = capture_timed(ctx, &where);
+        if (e == hipSuccess) return hipSuccess;
+        // not an error of the call: the graph is captured again in one piece
+        // and only whole replays are timed; the reason is kept
+        set_error("stage events inside the graph unavailable (%s: %s); timing whole replays", where,
+                  hipGetErrorString(e));
+        (void)hipGetLastError();
+        if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->gexec = nullptr;
+        ctx->graph = nullptr;
+        ctx->ev_nodes.clear();
+        ctx->ev_stage.clear();
+    }
+    return capture_plain(ctx);
+}
+
 kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
 {
     kp_status st = check_ctx(ctx);
@@ -485,25 +610,23 @@ kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
     }
     if (todo > 0) {
         if (ctx->use_graph) {
-            if (!ctx->gexec) {
-                KP_HIP(hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal));
-                for (auto &P : ctx->P) {
-                    hipError_t e = kp::launch_iteration(P, ctx->own, false, ctx->cfg);
-                    if (e != hipSuccess) {
-                        hipGraph_t junk = nullptr;
-                        (void)hipStreamEndCapture(ctx->own, &junk);
-                        if (junk) (void)hipGraphDestroy(junk);
-                        KP_HIP(e);
-                    }
-                }
-                KP_HIP(hipStreamEndCapture(ctx->own, &ctx->graph));
-                KP_HIP(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
-            }
+            if (!ctx->gexec) KP_HIP(capture_iteration(ctx));
             for (int i = 0; i < todo; ++i) {
                 StageTimer::Rec r;
-                if (ctx->timing) KP_HIP(ctx->timer.begin(kp::ST_COUNT, ctx->own, r));
+                std::vector<StageTimer::Rec> inner(ctx->ev_stage.size());
+                if (ctx->timing) {
+                    KP_HIP(ctx->timer.begin(kp::ST_COUNT, ctx->own, r));
+                    for (size_t k = 0; k < inner.size(); ++k) {
+                        KP_HIP(ctx->timer.take(ctx->ev_stage[k], inner[k]));
+                        KP_HIP(hipGraphExecEventRecordNodeSetEvent(ctx->gexec, ctx->ev_nodes[2 * k], inner[k].a));
+                        KP_HIP(hipGraphExecEventRecordNodeSetEvent(ctx->gexec, ctx->ev_nodes[2 * k + 1], inner[k].b));
+                    }
+                }
                 KP_HIP(hipGraphLaunch(ctx->gexec, ctx->own));
-                if (ctx->timing) KP_HIP(ctx->timer.end(ctx->own, r));
+                if (ctx->timing) {
+                    for (auto &q : inner) ctx->timer.pending.push_back(q);
+                    KP_HIP(ctx->timer.end(ctx->own, r));
+                }
             }
         } else {
             for (int i = 0; i < todo; ++i) KP_HIP(launch_all(ctx, false));

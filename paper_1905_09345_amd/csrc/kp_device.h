@@ -42,7 +42,7 @@ struct __attribute__((aligned(16))) PointState {
     int a;        // slot of the assigned centroid
     float u;      // ub - Sc[a] (rounded up)
     float p;      // lbp + Sd (rounded down): lbp bounds min_{j != a} d(x, c_j)
-    int pad;
+    int ga;       // group of slot a
 };
 
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
@@ -72,6 +72,7 @@ struct ProbDev {
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
     int *L1;                  // point ids failing the point-level filter (filter order)
     int *L1s;                 // the same ids sorted by assigned slot
+    int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int4 *tlist;              // per tile of sorted L1: (group, point mask lo, hi, 0), g entries per tile
     int *tcnt;                // entries used per tile
     float4 *ps4;              // per position: ub, min closed-group bound, U* of an uncertain point
@@ -87,19 +88,29 @@ struct ProbDev {
 };
 
 // ---------------------------------------------------------------- rounding
+// (selects rather than branches: these sit in the innermost loops)
 __device__ __forceinline__ float f_up(float f)
 {
-    if (!(f < __builtin_huge_valf())) return f;                  // +inf, nan
-    unsigned u = __float_as_uint(f);
-    if (f > 0.f) u += 1u; else if (f < 0.f) u -= 1u; else u = 1u;
-    return __uint_as_float(u);
+    const unsigned u = __float_as_uint(f);
+    const unsigned r = f > 0.f ? u + 1u : (f < 0.f ? u - 1u : 1u);
+    return f < __builtin_huge_valf() ? __uint_as_float(r) : f;   // +inf, nan unchanged
 }
 __device__ __forceinline__ float f_dn(float f)
 {
-    if (!(f > -__builtin_huge_valf())) return f;
-    unsigned u = __float_as_uint(f);
-    if (f > 0.f) u -= 1u; else if (f < 0.f) u += 1u; else u = 0x80000001u;
-    return __uint_as_float(u);
+    const unsigned u = __float_as_uint(f);
+    const unsigned r = f > 0.f ? u - 1u : (f < 0.f ? u + 1u : 0x80000001u);
+    return f > -__builtin_huge_valf() ? __uint_as_float(r) : f;  // -inf, nan unchanged
+}
+// One step down / up for values whose exact counterpart is known to be >= 0
+// (sums of non-negative terms, square roots): the result bounds the exact
+// value from below / above.  Non-positive and NaN inputs give 0 / stay.
+__device__ __forceinline__ float dn_nonneg(float x)
+{
+    return x > 0.f ? __uint_as_float(__float_as_uint(x) - 1u) : 0.f;
+}
+__device__ __forceinline__ float up_nonneg(float x)
+{
+    return x < __builtin_huge_valf() ? __uint_as_float(__float_as_uint(fmaxf(x, 0.f)) + 1u) : x;
 }
 // FP64 -> FP32 rounded toward +inf / -inf.
 __device__ __forceinline__ float d2f_up(double v)
@@ -194,13 +205,16 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 // relative), xn + cn rounds once more, and the final fused multiply-add
 // rounds |xn + cn - 2S| <= 1.01 (A + C)^2 once:
 //   |v - ||x - c||^2| <= 3.02 u (A^2 + C^2) + (2 kappa + 2.02 u) A C.
-// The true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
+// The estimates are then compared with their low 4 significand bits
+// cleared (at most 2^-19 v <= 2^-19 * 1.01 (A + C)^2 less), which the last
+// term adds.  The true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
 __device__ __forceinline__ double mfma_eta3(float xn, float bmax, int ldb)
 {
     const double u = 5.9604644775390625e-08;
     const double A = sqrt((double)xn) * (1.0 + 0x1p-22), C = (double)bmax;
     const double kappa = 3.02 * 0x1p-16 + 2.1 * (double)(ldb + 2) * u + 2.05 * u;
-    return (3.02 * u * (A * A + C * C) + (2.0 * kappa + 2.02 * u) * A * C) * (1.0 + 0x1p-20);
+    const double q = 1.01 * 0x1p-19 * (A + C) * (A + C);
+    return (3.02 * u * (A * A + C * C) + (2.0 * kappa + 2.02 * u) * A * C + q) * (1.0 + 0x1p-20);
 }
 
 // --------------------------------------------------- tuple merge (d^2, slot, second)

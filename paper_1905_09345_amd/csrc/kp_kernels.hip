@@ -308,7 +308,11 @@ __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
     if (P.kg > HIST_LDS) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
             const int pid = clamp_pid(P, P.L1[e]);
-            P.L1s[atomicAdd(&P.cursor1[clamp_slot(P, P.st[pid].a)], 1)] = pid;
+            const PointState st = P.st[pid];
+            const int key = clamp_slot(P, st.a);
+            const int pos = atomicAdd(&P.cursor1[key], 1);
+            P.L1s[pos] = pid;
+            if (P.prec) P.L1x[pos] = make_int4(pid, key, __float_as_int(ub_now(st.u, P.Scu[key])), st.ga);
         }
         return;
     }
@@ -324,8 +328,11 @@ __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
     __syncthreads();
     for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
         const int pid = clamp_pid(P, P.L1[e]);
-        const int key = clamp_slot(P, P.st[pid].a);
-        P.L1s[base[key] + atomicAdd(&h[key], 1)] = pid;
+        const PointState st = P.st[pid];
+        const int key = clamp_slot(P, st.a);
+        const int pos = base[key] + atomicAdd(&h[key], 1);
+        P.L1s[pos] = pid;
+        if (P.prec) P.L1x[pos] = make_int4(pid, key, __float_as_int(ub_now(st.u, P.Scu[key])), st.ga);
     }
 }
 
@@ -492,7 +499,7 @@ __device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense
     ns.a = win;
     ns.u = store_u(dist_hi(r.bd, eps2), P.Scd[win]);
     ns.p = store_lb(lbp, sdd);
-    ns.pad = 0;
+    ns.ga = P.slot_group[win];
     P.st[pid] = ns;
     return win != (dense ? -1 : a);
 }
@@ -532,11 +539,6 @@ __device__ __forceinline__ Best3 best_of4(const float v[4], int slot0)
 template <int KS>
 struct PtFrag {
     bf16x8 h[KS], l[KS];
-};
-template <int KS>
-struct CtFrag {
-    bf16x8 h[KS], l[KS];
-    float4 cn;   // ||c||^2 of slots slot0 + 4 (l >> 4) .. +3 (+inf for padding)
 };
 
 // Split of 8 FP32 values (conversions round to nearest even).
@@ -586,92 +588,86 @@ __device__ __forceinline__ void load_points16(const ProbDev &P, int pid, bool ok
     for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
 }
 
-// The A operand: one 16-slot chunk (rows padded with zeros to ldb = 32 KS).
-template <int KS>
-__device__ __forceinline__ void load_chunk16(const ProbDev &P, int slot0, CtFrag<KS> &f)
+// Per-point results of a chunk in key form: the estimate (clamped at 0, FP32
+// bits with the low 4 bits cleared, so at most 2^-19 relative below it) with
+// the slot's offset in the chunk in those 4 bits.  Unsigned order of keys is
+// the order of the truncated estimates, ties to the lower slot.  k1 <= k2 are
+// the two smallest keys.
+struct Key2 {
+    unsigned k1, k2;
+};
+__device__ __forceinline__ Key2 key2_merge(Key2 a, Key2 b)
 {
-    const int lane = lane_id(), quad = lane >> 4;
-    const size_t row = (size_t)(slot0 + (lane & 15)) * P.ldb + 8 * quad;
+    Key2 r;
+    r.k1 = min(a.k1, b.k1);
+    r.k2 = min(max(a.k1, b.k1), min(a.k2, b.k2));
+    return r;
+}
+__device__ __forceinline__ Key2 key2_xor(Key2 a, int mask)
+{
+    Key2 r;
+    r.k1 = (unsigned)__shfl_xor((int)a.k1, mask);
+    r.k2 = (unsigned)__shfl_xor((int)a.k2, mask);
+    return r;
+}
+__device__ __forceinline__ Key2 key2_swz16(Key2 a)   // lane l <-> lane l ^ 16 (within 32 lanes)
+{
+    Key2 r;
+    r.k1 = (unsigned)__builtin_amdgcn_ds_swizzle((int)a.k1, 0x401F);
+    r.k2 = (unsigned)__builtin_amdgcn_ds_swizzle((int)a.k2, 0x401F);
+    return r;
+}
+__device__ __forceinline__ float key_value(unsigned k) { return __uint_as_float(k & ~15u); }
+
+// Keys of the estimates v = ||x||^2 + ||c||^2 - 2 (hh + (lh + hl)) of lane
+// l's point against slots 4 (l >> 4) .. +3 of the chunk, reduced over the
+// four lane groups: every lane of point p returns p's two smallest keys.
+__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lh, const f32x4 &hl, float4 c4, float xnp)
+{
+    const float cnv[4] = {c4.x, c4.y, c4.z, c4.w};
+    const unsigned base = 4u * (unsigned)(lane_id() >> 4);
+    unsigned k[4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        f.h[ks] = *(const bf16x8 *)(P.cb + row + 32 * ks);
-        f.l[ks] = *(const bf16x8 *)(P.cbl + row + 32 * ks);
+    for (int r = 0; r < 4; ++r) {
+        const float v = fmaxf(fmaf(-2.f, hh[r] + (lh[r] + hl[r]), xnp + cnv[r]), 0.f);
+        k[r] = (__float_as_uint(v) & ~15u) | (base + (unsigned)r);
     }
-    f.cn = *(const float4 *)(P.cn + slot0 + 4 * quad);
+    Key2 p = {min(k[0], k[1]), max(k[0], k[1])}, q = {min(k[2], k[3]), max(k[2], k[3])};
+    Key2 t = key2_merge(p, q);
+    t = key2_merge(t, key2_swz16(t));
+    return key2_merge(t, key2_xor(t, 32));
 }
 
-// Estimates of one chunk, reduced over the four lane groups: every lane of
-// point p returns the (best, slot, second) of p over the chunk.
-template <int KS>
-__device__ __forceinline__ Best3 chunk16(const CtFrag<KS> &f, const PtFrag<KS> &b, int slot0, float xnp)
+// Bounds on the true distance from an estimate v of its square with
+// |v - d^2| <= eta (eta_f: eta rounded up to FP32).  v_sqrt_f32 is within
+// 1 ulp of the square root (normal inputs); two steps cover it, and one step
+// each covers the rounding of v -/+ eta.  Tiny arguments give the bound 0.
+__device__ __forceinline__ float est_lo(float v, float eta_f)
 {
-    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lh = {0.f, 0.f, 0.f, 0.f}, hl = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.h[ks], b.h[ks], hh, 0, 0, 0);
-        lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.l[ks], b.h[ks], lh, 0, 0, 0);
-        hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.h[ks], b.l[ks], hl, 0, 0, 0);
-    }
-    const float cnv[4] = {f.cn.x, f.cn.y, f.cn.z, f.cn.w};
-    float v[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, hh[r] + (lh[r] + hl[r]), xnp + cnv[r]);
-    Best3 t = best_of4(v, slot0 + 4 * (lane_id() >> 4));
-    t = merge3(t, shfl_xor3(t, 16));
-    return merge3(t, shfl_xor3(t, 32));
+    const float t = dn_nonneg(v - eta_f);
+    return t > 0x1p-100f ? __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(t)) - 2u) : 0.f;
+}
+__device__ __forceinline__ float est_hi(float v, float eta_f)
+{
+    const float t = up_nonneg(v + eta_f);
+    if (!(t < __builtin_huge_valf())) return t;
+    return __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(fmaxf(t, 0x1p-100f))) + 2u);
 }
 
-// The visits of one tile.  Each set bit j of vmask names lane j, which holds
-// one visit: group tg, 16-bit point mask tm, first slot ts0 and size tns
-// (>= 1).  The fragments of the next chunk are loaded while the current one
-// is on the matrix cores.  done(g, m, ns, gb) receives each visit's result.
-template <int KS, class Done>
-__device__ __forceinline__ void tile_visits(const ProbDev &P, unsigned long long vmask, int tg, unsigned tm, int ts0,
-                                            int tns, const PtFrag<KS> &b, float xnp, Done done)
+// Fold one chunk's result (m1 at slot s1, second m2) of group g into the
+// running best, when `on`.  gprev: minimum over the group's earlier chunks
+// (+inf for its first).  A tie of estimates can never be decided under the
+// error bound, so ties keep the earlier result.
+__device__ __forceinline__ void run_fold_part(Run &r, bool on, float m1, int s1, float m2, int g, float gprev)
 {
-    if (vmask == 0ull) return;
-    struct Cur {
-        int g, s0, ns, c0;
-        unsigned m;
-    };
-    auto take = [&](Cur &c) {
-        const int j = __ffsll((long long)vmask) - 1;
-        vmask &= vmask - 1ull;
-        c.g = __builtin_amdgcn_readlane(tg, j);
-        c.s0 = __builtin_amdgcn_readlane(ts0, j);
-        c.ns = __builtin_amdgcn_readlane(tns, j);
-        c.m = (unsigned)__builtin_amdgcn_readlane((int)tm, j);
-        c.c0 = 0;
-    };
-    Cur c;
-    take(c);
-    CtFrag<KS> fa, fb;
-    load_chunk16<KS>(P, c.s0, fa);
-    Best3 gb = {KP_INF, INT_MAX, KP_INF};
-    // one chunk; false after the last
-    auto step = [&](const CtFrag<KS> &cur, CtFrag<KS> &nxt) -> bool {
-        Cur n = c;
-        n.c0 += CHUNK;
-        bool more = true;
-        if (n.c0 >= n.ns) {
-            if (vmask) take(n);
-            else more = false;
-        }
-        if (more) load_chunk16<KS>(P, n.s0 + n.c0, nxt);
-        gb = merge3(gb, chunk16<KS>(cur, b, c.s0 + c.c0, xnp));
-        if (!more || n.c0 == 0) {
-            done(c.g, c.m, c.ns, gb);
-            gb.m1 = KP_INF;
-            gb.s1 = INT_MAX;
-            gb.m2 = KP_INF;
-        }
-        c = n;
-        return more;
-    };
-    for (;;) {
-        if (!step(fa, fb)) break;
-        if (!step(fb, fa)) break;
-    }
+    const bool nb = on && m1 < r.bd;
+    const float sec = nb ? fminf(r.bd, m2) : fminf(r.sec, m1);
+    const float bm2 = nb ? fminf(m2, gprev) : (g == r.bg ? fminf(r.bm2, m1) : r.bm2);
+    r.sec = on ? sec : r.sec;
+    r.bm2 = on ? bm2 : r.bm2;
+    r.bd = nb ? m1 : r.bd;
+    r.bs = nb ? s1 : r.bs;
+    r.bg = nb ? g : r.bg;
 }
 
 // BF16 decision under the error bound; writes the point's state and bound
@@ -707,7 +703,7 @@ __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dens
     if (amb) return;
     PointState nsv;
     nsv.a = win;
-    nsv.pad = 0;
+    nsv.ga = P.slot_group[win];
     float ubn, lbp;
     if (a_sep && win == a) {
         ubn = ubt;
@@ -923,81 +919,252 @@ __global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
 
-// One wave per tile of 16 positions (BF16 mode).  DENSE (iteration 1): the
-// positions are the points and every group is visited.  Otherwise the
-// positions are entries of the sorted L1: each point's own group is visited
-// first, which tightens its upper bound to the best estimate there; then the
-// group bounds of the 16 points are tested against the tightened bounds with
-// lanes over groups, and every group open for some point is visited with the
-// mask of those points.  Per point: the decision under the error bound, or
-// the flag that sends it to the FP32 recheck.
-template <int KS, bool DENSE>
-__global__ __launch_bounds__(256, KS <= 4 ? 3 : (KS <= 6 ? 2 : 1)) void k_tile16(ProbDev P)
+// ---------------------------------------------- workgroup of 64 positions
+// Four waves; wave w holds positions 16 w .. 16 w + 15 of the tile in its B
+// operand.  The workgroup walks one list of chunks, the union of its waves'
+// visits: each chunk's A operand is staged in LDS once for the four waves,
+// the next chunk loading while the current one is on the matrix cores.  A
+// staged chunk keeps fragment (part, ks) of lane l at a[part * KS + ks][l]
+// (one conflict-free 16-byte read per lane and fragment), then the norms.
+template <int KS>
+struct ChunkStage {
+    bf16x8 a[2 * KS][WAVE];
+    float4 cn[4];
+};
+constexpr int GMAX_BF16 = 1024;      // largest g of the BF16 mode (group tables kept in LDS)
+template <int KS>
+struct BlockLds {
+    ChunkStage<KS> st[2];
+    unsigned short mask[4][WAVE];   // filter round: wave w's point mask of group g0 + t
+    int ga[64];                     // own group of each position of the tile (-1: none)
+    int gst[GMAX_BF16], gsz[GMAX_BF16];
+    float gsd[GMAX_BF16], gsu[GMAX_BF16];   // Sg rounded down / up
+};
+template <int KS>
+struct StageRegs {
+    bf16x8 r[(2 * KS * WAVE + 255) / 256];
+    float4 c;
+};
+
+// Loads of the chunk at slot0 into this thread's staging registers.
+template <int KS>
+__device__ __forceinline__ void stage_load(const ProbDev &P, int slot0, StageRegs<KS> &s)
 {
-    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < (2 * KS * WAVE + 255) / 256; ++i) {
+        const int e = t + 256 * i;
+        if ((2 * KS * WAVE) % 256 == 0 || e < 2 * KS * WAVE) {
+            const int f = e / WAVE, l = e % WAVE;   // f = part * KS + ks
+            const uint16_t *base = (f >= KS) ? P.cbl : P.cb;
+            const int ks = f % KS;
+            s.r[i] = *(const bf16x8 *)(base + (size_t)(slot0 + (l & 15)) * P.ldb + 32 * ks + 8 * (l >> 4));
+        }
+    }
+    if (t < 4) s.c = *(const float4 *)(P.cn + slot0 + 4 * t);
+}
+template <int KS>
+__device__ __forceinline__ void stage_store(ChunkStage<KS> &S, const StageRegs<KS> &s)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < (2 * KS * WAVE + 255) / 256; ++i) {
+        const int e = t + 256 * i;
+        if ((2 * KS * WAVE) % 256 == 0 || e < 2 * KS * WAVE) S.a[e / WAVE][e % WAVE] = s.r[i];
+    }
+    if (t < 4) S.cn[t] = s.c;
+}
+
+template <int KS>
+__device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp)
+{
+    const int lane = lane_id();
+    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lh = {0.f, 0.f, 0.f, 0.f}, hl = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 ah = S.a[ks][lane], al = S.a[KS + ks][lane];
+        hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.h[ks], hh, 0, 0, 0);
+        lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.h[ks], lh, 0, 0, 0);
+        hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], hl, 0, 0, 0);
+    }
+    return chunk_keys(hh, lh, hl, S.cn[lane >> 4], xnp);
+}
+
+// Chunks of the visits named by the set bits of vm (workgroup-uniform);
+// lane j holds visit j's first slot ts0 and size tns (>= 1).
+struct ChunkSeq {
+    unsigned long long rest;
+    int j, c0, s0, ns;
+    bool valid;
+};
+__device__ __forceinline__ void seq_take(ChunkSeq &q, int ts0, int tns)
+{
+    q.j = __ffsll((long long)q.rest) - 1;
+    q.rest &= q.rest - 1ull;
+    q.s0 = __builtin_amdgcn_readlane(ts0, q.j);
+    q.ns = __builtin_amdgcn_readlane(tns, q.j);
+    q.c0 = 0;
+}
+__device__ __forceinline__ void seq_begin(ChunkSeq &q, unsigned long long vm, int ts0, int tns)
+{
+    q.rest = vm;
+    q.valid = vm != 0ull;
+    q.j = q.c0 = q.s0 = q.ns = 0;
+    if (q.valid) seq_take(q, ts0, tns);
+}
+__device__ __forceinline__ void seq_next(ChunkSeq &q, int ts0, int tns)
+{
+    q.c0 += CHUNK;
+    if (q.c0 >= q.ns) {
+        if (q.rest) seq_take(q, ts0, tns);
+        else q.valid = false;
+    }
+}
+
+// The workgroup's visits named by vm: lane j holds group tg, this wave's
+// 16-bit point mask tmw, first slot ts0, size tns and the group's rounded-
+// down drift sum tsgd.  fold(g, m, slot0, nreal, first, sgd, key2) receives
+// each chunk's two smallest keys per point of this wave (skipped when the
+// wave has no point in the visit).  Every thread of the workgroup calls it.
+template <int KS, class Fold>
+__device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, unsigned long long vm, int tg,
+                                             unsigned tmw, int ts0, int tns, float tsgd, const PtFrag<KS> &b,
+                                             float xnp, Fold fold)
+{
+    if (vm == 0ull) return;
+    ChunkSeq cp, ld;
+    seq_begin(cp, vm, ts0, tns);
+    ld = cp;
+    StageRegs<KS> sr;
+    stage_load<KS>(P, ld.s0, sr);
+    stage_store<KS>(L.st[0], sr);
+    seq_next(ld, ts0, tns);
+    __syncthreads();
+    int buf = 0;
+    while (cp.valid) {
+        const bool pre = ld.valid;
+        if (pre) stage_load<KS>(P, ld.s0 + ld.c0, sr);
+        const unsigned m = (unsigned)__builtin_amdgcn_readlane((int)tmw, cp.j);
+        if (m) {
+            const Key2 t = chunk_lds<KS>(L.st[buf], b, xnp);
+            fold(__builtin_amdgcn_readlane(tg, cp.j), m, cp.s0 + cp.c0, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0,
+                 __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tsgd), cp.j)), t);
+        }
+        if (pre) stage_store<KS>(L.st[buf ^ 1], sr);
+        __syncthreads();
+        seq_next(cp, ts0, tns);
+        if (pre) seq_next(ld, ts0, tns);
+        buf ^= 1;
+    }
+}
+
+// BF16 mode, one workgroup per tile of 64 positions.  DENSE (iteration 1):
+// the positions are the points and every group is visited.  Otherwise the
+// positions are entries of the sorted L1: the own groups of the tile's
+// points are visited first, which tightens each point's upper bound to its
+// best estimate there; then each wave tests its points' group bounds
+// against the tightened bounds (lanes over groups) and the workgroup visits
+// every group open for some point of the tile.  Per point: the decision
+// under the error bound, or the flag that sends it to the FP32 recheck.
+template <int KS, bool DENSE>
+__global__ __launch_bounds__(256) void k_blk64(ProbDev P)
+{
+    __shared__ BlockLds<KS> L;
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const float bmax = P.scal[0];
     const float sdd = P.Sdud[1];
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
-    const long long ntiles = (count + 15) / 16;
-    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    const long long ntiles = (count + 63) / 64;
+    for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
+        L.gst[i] = P.gstart[i];
+        L.gsz[i] = P.gsize[i];
+        L.gsd[i] = P.Sgd[i];
+        L.gsu[i] = P.Sgu[i];
+    }
+    for (int i = P.g + threadIdx.x; i < ((P.g + 3) & ~3); i += blockDim.x) L.gsu[i] = 0.f;   // float4 tail
+    __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0, n_amb = 0;
-    for (long long tl = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; tl < ntiles; tl += nw) {
-        const long long idx = tl * 16 + pt;
+    // sorted entry of this lane's position in the next tile, loaded one tile ahead
+    int4 nxt = make_int4(0, 0, 0, 0);
+    if (!DENSE) {
+        const long long i0 = (long long)blockIdx.x * 64 + 16 * wv + pt;
+        if (i0 < count) nxt = P.L1x[i0];
+    }
+    for (long long tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {   // uniform per workgroup
+        const long long idx = tl * 64 + 16 * wv + pt;
         const bool in = idx < count;
-        const int pid = in ? (DENSE ? (int)idx : clamp_pid(P, P.L1s[idx])) : 0;
+        int pid = in && DENSE ? (int)idx : 0;
         int a = -1, ga = -1;
         float ubt = KP_INF;
-        if (!DENSE && in) {
-            const PointState s = P.st[pid];
-            a = clamp_slot(P, s.a);
-            ga = min(max(P.slot_group[a], 0), P.g - 1);
-            ubt = ub_now(s.u, P.Scu[a]);
+        if (!DENSE) {
+            const int4 e = nxt;
+            const long long inext = idx + 64ll * gridDim.x;
+            if (inext < count) nxt = P.L1x[inext];
+            if (in) {
+                pid = clamp_pid(P, e.x);
+                a = clamp_slot(P, e.y);
+                ubt = __int_as_float(e.z);
+                ga = min(max(e.w, 0), P.g - 1);
+            }
         }
         const float xnp = in ? P.xn[pid] : 0.f;
         const double eta = mfma_eta3(xnp, bmax, P.ldb);
-        const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // lanes 0..15 <-> the 16 points
+        const float eta_f = d2f_up(eta);
+        const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
         PtFrag<KS> b;
         load_points16<KS>(P, pid, in, b);
         Run r;
         run_init(r);
-        auto done = [&](int g, unsigned m, int ns, const Best3 &gb) {
-            n_visits += 1;
-            n_pairs += (unsigned long long)__popc(m);
-            n_dist += (unsigned long long)__popc(m) * (unsigned long long)ns;
-            if ((m >> pt) & 1u) {
-                run_fold(P, r, gb, g);
-                if (quad == 0) P.lb[(size_t)pid * P.gs + g] = store_lb(mfma_lo(gb.m1, eta, 0.0), P.Sgd[g]);
-            }
+        float gmin = KP_INF;   // running minimum of the group being visited
+        auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
+            n_pairs += first ? (unsigned long long)__popc(m) : 0ull;
+            n_dist += (unsigned long long)__popc(m) * (unsigned long long)nreal;
+            const bool mine = (m >> pt) & 1u;
+            const float m1 = key_value(kk.k1);
+            const float gprev = first ? KP_INF : gmin;
+            gmin = fminf(gprev, m1);
+            run_fold_part(r, mine, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev);
+            const float lbv = dn_nonneg(est_lo(gmin, eta_f) + sgd);   // offset form, rounded down
+            if (mine && quad == 0) P.lb[(size_t)pid * P.gs + g] = lbv;
         };
         float minnc = KP_INF;
         if (DENSE) {
             for (int g0 = 0; g0 < P.g; g0 += WAVE) {
                 const int g = g0 + lane;
                 const bool gv = g < P.g;
-                const int s0 = gv ? P.gstart[g] : 0, ns = gv ? P.gsize[g] : 0;
-                tile_visits<KS>(P, __ballot(gv && ns > 0), g, inm, s0, ns, b, xnp, done);
+                const int s0 = gv ? L.gst[g] : 0, ns = gv ? L.gsz[g] : 0;
+                const float sgd = gv ? L.gsd[g] : 0.f;
+                const unsigned long long vm = __ballot(gv && ns > 0);
+                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
+                block_visits<KS>(P, L, vm, g, inm, s0, ns, sgd, b, xnp, fold);
             }
         } else {
-            // own groups (at most 16 distinct), visit i held by lane i
+            // own groups of the 64 positions; visit i held by lane i
+            if (quad == 0) L.ga[16 * wv + pt] = in ? ga : -1;
+            __syncthreads();
+            const int gt = L.ga[lane];
             int tg = 0, nv = 0;
-            unsigned tm = 0u;
-            for (unsigned todo = inm; todo;) {
-                const int p = __ffs(todo) - 1;
-                const int g = __builtin_amdgcn_readlane(ga, p);
-                const unsigned m = (unsigned)__ballot(in && ga == g) & 0xFFFFu;
+            unsigned tmw = 0u;
+            for (unsigned long long todo = __ballot(gt >= 0); todo;) {
+                const int p = __ffsll((long long)todo) - 1;
+                const int g = __builtin_amdgcn_readlane(gt, p);
+                const unsigned long long m64 = __ballot(gt == g);
                 if (lane == nv) {
                     tg = g;
-                    tm = m;
+                    tmw = (unsigned)(m64 >> (16 * wv)) & 0xFFFFu;
                 }
                 ++nv;
-                todo &= ~m;
+                todo &= ~m64;
             }
             {
                 const bool own = lane < nv;
-                const int s0 = own ? P.gstart[tg] : 0, ns = own ? P.gsize[tg] : 0;
-                tile_visits<KS>(P, __ballot(own && ns > 0), tg, tm, s0, ns, b, xnp, done);
+                const int s0 = own ? L.gst[tg] : 0, ns = own ? L.gsz[tg] : 0;
+                const float sgd = own ? L.gsd[tg] : 0.f;
+                const unsigned long long vm = __ballot(own && ns > 0);
+                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
+                block_visits<KS>(P, L, vm, tg, tmw, s0, ns, sgd, b, xnp, fold);
             }
-            const float ubn = fminf(ubt, mfma_hi(r.bd, eta, 0.0));
+            const float ubn = fminf(ubt, est_hi(r.bd, eta_f));
             // group-level filter, 64 groups per round: lane (point p, quad q)
             // tests groups g0 + 16 q .. +15 of point p (one 64-byte run of its
             // bound row); lane t then holds the visit of group g0 + t
@@ -1007,10 +1174,10 @@ __global__ __launch_bounds__(256, KS <= 4 ? 3 : (KS <= 6 ? 2 : 1)) void k_tile16
                 float v[16], sg[16];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int gi = gq + 4 * i;   // gs and the Sgu allocation are padded to 4
+                    const int gi = gq + 4 * i;   // gs and the LDS table are padded to 4
                     const bool ok = in && gi < P.g;
                     const float4 v4 = ok ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
-                    const float4 s4 = ok ? *(const float4 *)(P.Sgu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float4 s4 = ok ? *(const float4 *)(L.gsu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
                     v[4 * i] = v4.x;
                     v[4 * i + 1] = v4.y;
                     v[4 * i + 2] = v4.z;
@@ -1027,17 +1194,24 @@ __global__ __launch_bounds__(256, KS <= 4 ? 3 : (KS <= 6 ? 2 : 1)) void k_tile16
                     const int g = gq + j;
                     const bool cand = in && g < P.g && g != ga;
                     const bool open = cand && group_open(ubn, sg[j], v[j]);
-                    if (cand && !open) cm = fminf(cm, lb_now(v[j], sg[j]));
+                    cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
                     const unsigned long long bj = __ballot(open);
                     if ((lane & 15) == j) mine = bj;
                 }
                 cm = fminf(cm, __shfl_xor(cm, 16));
-                minnc = fminf(minnc, fminf(cm, __shfl_xor(cm, 32)));
+                minnc = fminf(minnc, f_dn(fminf(cm, __shfl_xor(cm, 32))));
                 const unsigned tm = (unsigned)(mine >> (16 * quad)) & 0xFFFFu;
-                const int tg = g0 + lane;
-                const bool gv = tg < P.g;
-                const int s0 = gv ? P.gstart[tg] : 0, ns = gv ? P.gsize[tg] : 0;
-                tile_visits<KS>(P, __ballot(gv && tm != 0u && ns > 0), tg, tm, s0, ns, b, xnp, done);
+                L.mask[wv][lane] = (unsigned short)tm;
+                __syncthreads();
+                const unsigned any = (unsigned)L.mask[0][lane] | L.mask[1][lane] | L.mask[2][lane] | L.mask[3][lane];
+                __syncthreads();   // the masks are rewritten by the next round
+                const int tgr = g0 + lane;
+                const bool gv = tgr < P.g;
+                const int s0 = gv ? L.gst[tgr] : 0, ns = gv ? L.gsz[tgr] : 0;
+                const float sgd = gv ? L.gsd[tgr] : 0.f;
+                const unsigned long long vm = __ballot(gv && any != 0u && ns > 0);
+                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
+                block_visits<KS>(P, L, vm, tgr, tm, s0, ns, sgd, b, xnp, fold);
             }
         }
         bool moved = false, amb = false;
@@ -1287,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
             nsv.a = bs;
             nsv.u = store_u(dist_hi(bd, eps2), P.Scd[bs]);
             nsv.p = store_lb(lbp, sdd);
-            nsv.pad = 0;
+            nsv.ga = gbest;
             P.st[pid] = nsv;
             P.mv_pt[e] = pid;
             P.mv_old[e] = olda;
@@ -1465,25 +1639,25 @@ hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
     return hipGetLastError();
 }
 
-// BF16 mode: one wave per 16 positions; KS = ldb / 32 in {1, 2, 3, 4, 6, 8}.
+// BF16 mode: one workgroup per 64 positions; KS = ldb / 32 in {1, 2, 3, 4, 6, 8}.
 template <bool DENSE>
-static void launch_tile16_ks(const ProbDev &P, hipStream_t s, int grid)
+static void launch_blk64_ks(const ProbDev &P, hipStream_t s, int grid)
 {
     switch (P.ldb / 32) {
-    case 1: hipLaunchKernelGGL((k_tile16<1, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 2: hipLaunchKernelGGL((k_tile16<2, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL((k_tile16<3, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL((k_tile16<4, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 6: hipLaunchKernelGGL((k_tile16<6, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 8: hipLaunchKernelGGL((k_tile16<8, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL((k_blk64<1, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 2: hipLaunchKernelGGL((k_blk64<2, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL((k_blk64<3, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL((k_blk64<4, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 6: hipLaunchKernelGGL((k_blk64<6, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 8: hipLaunchKernelGGL((k_blk64<8, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
     default: break;   // excluded when the plan is made
     }
 }
-static void launch_tile16(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, bool dense)
+static void launch_blk64(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, bool dense)
 {
-    const int grid = cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap);
-    if (dense) launch_tile16_ks<true>(P, s, grid);
-    else launch_tile16_ks<false>(P, s, grid);
+    const int grid = cap_grid((P.n + 63) / 64, cfg.grid_cap);
+    if (dense) launch_blk64_ks<true>(P, s, grid);
+    else launch_blk64_ks<false>(P, s, grid);
 }
 
 static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
@@ -1498,7 +1672,7 @@ static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
         else if (dm <= 64) hipLaunchKernelGGL(k_dense_f32<64>, dim3(grid), dim3(threads), 0, s, P);
         else hipLaunchKernelGGL(k_dense_f32<128>, dim3(grid), dim3(threads), 0, s, P);
     } else {
-        launch_tile16(P, s, cfg, true);
+        launch_blk64(P, s, cfg, true);
     }
 }
 
@@ -1516,7 +1690,7 @@ static void launch_survivors(const ProbDev &P, hipStream_t s, const LaunchCfg &c
         else if (dm <= 64) hipLaunchKernelGGL(k_tile_f32<64>, dim3(grid), dim3(threads), 0, s, P);
         else hipLaunchKernelGGL(k_tile_f32<128>, dim3(grid), dim3(threads), 0, s, P);
     } else {
-        launch_tile16(P, s, cfg, false);
+        launch_blk64(P, s, cfg, false);
     }
 }
 

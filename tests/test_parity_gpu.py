@@ -130,8 +130,11 @@ def test_stage_times():
         assert t["assign_dense"]["launches"] == 1 and t["assign_dense"]["ms"] > 0
         if use_graph == 1:
             assert t["filtered_iter"]["launches"] == 3
-        else:
-            assert t["assign"]["launches"] == 3 and t["bound_filter"]["launches"] == 3
+        # every stage is timed on its own, inside graph replays as well
+        from paper_1905_09345_amd.kp import kp_last_error
+        assert "assign" in t, (sorted(t), kp_last_error())
+        assert t["assign"]["launches"] == 3 and t["bound_filter"]["launches"] == 3
+        assert t["assign"]["ms"] > 0
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
