@@ -48,7 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--stats", action="store_true", help="print per-iteration filter statistics")
     ap.add_argument("--plain", action="store_true",
-                    help="plain launches instead of graph replays (per-stage timing of every iteration)")
+                    help="plain launches instead of graph replays")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device to device twice (reference for the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -111,6 +113,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 2 x %d bytes" % (src.numel() * 4))
+        return
     import datagen
     from paper_1905_09345_amd import KMeans
     from paper_1905_09345_amd.kp import kp_tuning
