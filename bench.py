@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--stats", action="store_true", help="print per-iteration filter statistics")
     ap.add_argument("--plain", action="store_true",
                     help="plain launches instead of graph replays")
+    ap.add_argument("--depth", type=int, default=0, choices=[0, 1, 3],
+                    help="centroid chunks in flight per workgroup (0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device twice (reference for the HBM byte counters) and exit")
     return ap.parse_args()
@@ -133,7 +135,7 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(P.X).to(dev)
     C0d = torch.from_numpy(P.C0).to(dev)
-    tun = kp_tuning(timing=1, use_graph=-1 if args.plain else 1)
+    tun = kp_tuning(timing=1, use_graph=-1 if args.plain else 1, chunk_depth=args.depth)
     runs = []
     for i in range(args.warmup + args.steps):
         runs.append(KMeans([(Xd, C0d, P.g, prec, P.seed)], tuning=tun))

@@ -37,8 +37,8 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, stats, iter, scal;
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, L3, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+        cursor1, ctr, stats, iter, scal, sink;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
 };
@@ -88,6 +88,7 @@ Plan plan_problem(const kp_problem &p)
     o.L1 = take(n * 4);
     o.L1s = take(n * 4);
     o.L1x = take(bf ? n * 16 : 0);
+    o.L3 = take(bf ? n * 4 : 0);
     const size_t ntiles = (n + 63) / 64;
     o.tlist = take(bf ? 0 : ntiles * (size_t)g * 16);   // group-filter lists of the FP32 path
     o.tcnt = take(bf ? 0 : ntiles * 4);
@@ -106,6 +107,7 @@ Plan plan_problem(const kp_problem &p)
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
     o.scal = take(16);
+    o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
     o.bytes = off;
     return o;
 }
@@ -127,6 +129,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
         }
         if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) {
             set_error("blocks_per_cu=%d outside 0..64", t->blocks_per_cu);
+            return false;
+        }
+        if (t->chunk_depth != 0 && t->chunk_depth != 1 && t->chunk_depth != 3) {
+            set_error("chunk_depth=%d not 0, 1 or 3", t->chunk_depth);
             return false;
         }
         if (t->use_graph < -1 || t->use_graph > 1) {
@@ -289,7 +295,7 @@ struct kp_ctx {
     hipStream_t user = nullptr, own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<kp::ProbDev> P;
-    kp::LaunchCfg cfg{4, 2048};
+    kp::LaunchCfg cfg{4, 2048, 1};
     int use_graph = 1;
     int iters = 0;
     bool poisoned = false;
@@ -373,6 +379,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
     if (tuning) {
         if (tuning->waves_per_block) ctx->cfg.waves = tuning->waves_per_block;
         if (tuning->blocks_per_cu) ctx->cfg.grid_cap = 256 * tuning->blocks_per_cu;
+        if (tuning->chunk_depth) ctx->cfg.depth = tuning->chunk_depth;
         if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
         ctx->timing = tuning->timing;
     }
@@ -430,6 +437,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.L1 = (int *)(base + o.L1);
         P.L1s = (int *)(base + o.L1s);
         P.L1x = (int4 *)(base + o.L1x);
+        P.L3 = (int *)(base + o.L3);
         P.tlist = (int4 *)(base + o.tlist);
         P.tcnt = (int *)(base + o.tcnt);
         P.ps4 = (float4 *)(base + o.ps4);
@@ -447,6 +455,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
         P.scal = (float *)(base + o.scal);
+        P.sink = (float *)(base + o.sink);
         KP_HIP(hipMemcpyAsync((void *)P.perm, G.perm.data(), G.perm.size() * 4, hipMemcpyHostToDevice, ctx->user));
         KP_HIP(hipMemcpyAsync((void *)P.slot_group, G.slot_group.data(), G.slot_group.size() * 4,
                               hipMemcpyHostToDevice, ctx->user));

@@ -34,6 +34,7 @@ constexpr int CHUNK = 16;             // centroid slots per MFMA tile / group pa
 constexpr int STATS_CAP = 1024;       // per-iteration stats ring
 constexpr int NCTR = 8;               // per-iteration counters
 constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
+constexpr int SINK_SLOTS = 1024;      // 64-byte slots taking the stores of lanes with nothing to write
 
 // counters (unsigned long long) per problem
 enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6 };
@@ -73,6 +74,7 @@ struct ProbDev {
     int *L1;                  // point ids failing the point-level filter (filter order)
     int *L1s;                 // the same ids sorted by assigned slot
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
+    int *L3;                  // positions of the points whose BF16 decision is uncertain
     int4 *tlist;              // per tile of sorted L1: (group, point mask lo, hi, 0), g entries per tile
     int *tcnt;                // entries used per tile
     float4 *ps4;              // per position: ub, min closed-group bound, U* of an uncertain point
@@ -85,6 +87,7 @@ struct ProbDev {
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
     float *scal;              // [0] max ||c32|| (rounded up)
+    float *sink;              // SINK_SLOTS x 16 floats, written and never read
 };
 
 // ---------------------------------------------------------------- rounding

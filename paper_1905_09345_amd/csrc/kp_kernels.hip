@@ -552,15 +552,19 @@ __device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &h, bf16x8 &l
     }
 }
 
-// The tile's B operand from the FP32 rows; zero beyond d and for absent points.
-template <int KS>
-__device__ __forceinline__ void load_points16(const ProbDev &P, int pid, bool ok, PtFrag<KS> &b)
+// The tile's B operand from the FP32 rows; zero beyond d and for absent
+// points.  With crow (OWN): also this lane's part of the FP32 direct-form
+// squared distance to that centroid row (c32, padded with zeros to ldc):
+// the lane's 8 KS coordinates summed in order with fused multiply-adds; the
+// four lanes of a point are combined by the caller (eps2_tile bounds it).
+template <int KS, bool OWN>
+__device__ __forceinline__ float load_points16(const ProbDev &P, int pid, bool ok, const float *crow, PtFrag<KS> &b)
 {
     const int quad = lane_id() >> 4;
     const float *xr = P.X + (size_t)pid * P.d;
-    float v[KS][8];
+    float v[KS][8], c[KS][8];
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     if ((P.d & 3) == 0 && ((uintptr_t)P.X & 15) == 0) {
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int k0 = 32 * ks + 8 * quad;   // d % 4 == 0: a float4 is wholly inside or outside
@@ -584,8 +588,40 @@ __device__ __forceinline__ void load_points16(const ProbDev &P, int pid, bool ok
                 v[ks][j] = (ok && k < P.d) ? xr[k] : 0.f;
             }
     }
+    float d2 = 0.f;
+    if (OWN) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k0 = 32 * ks + 8 * quad;   // ldc % 4 == 0 and the row is 16-byte aligned
+            const float4 q0 = (ok && k0 < P.ldc) ? *(const float4 *)(crow + k0) : z;
+            const float4 q1 = (ok && k0 + 4 < P.ldc) ? *(const float4 *)(crow + k0 + 4) : z;
+            c[ks][0] = q0.x;
+            c[ks][1] = q0.y;
+            c[ks][2] = q0.z;
+            c[ks][3] = q0.w;
+            c[ks][4] = q1.x;
+            c[ks][5] = q1.y;
+            c[ks][6] = q1.z;
+            c[ks][7] = q1.w;
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float t = v[ks][j] - c[ks][j];
+                d2 = fmaf(t, t, d2);
+            }
+    }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
+    return d2;
+}
+// Relative error of that distance after combining the four lanes: each of
+// the 8 KS terms adds one rounding to its lane's sum, each rounded
+// difference squared 2u, the two combining adds 2u; doubled as margin.
+__host__ __device__ __forceinline__ double eps2_tile(int ks)
+{
+    return (double)(8 * ks + 8) * 2.0 * 5.9604644775390625e-08;
 }
 
 // Per-point results of a chunk in key form: the estimate (clamped at 0, FP32
@@ -936,7 +972,6 @@ template <int KS>
 struct BlockLds {
     ChunkStage<KS> st[2];
     unsigned short mask[4][WAVE];   // filter round: wave w's point mask of group g0 + t
-    int ga[64];                     // own group of each position of the tile (-1: none)
     int gst[GMAX_BF16], gsz[GMAX_BF16];
     float gsd[GMAX_BF16], gsu[GMAX_BF16];   // Sg rounded down / up
 };
@@ -946,22 +981,23 @@ struct StageRegs {
     float4 c;
 };
 
-// Loads of the chunk at slot0 into this thread's staging registers.
+// Loads of the chunk at slot0 into this thread's staging registers.  Every
+// thread issues the same loads whatever the sizes (entries past the chunk
+// repeat one inside it), so that the memory counters of the pipelined loop
+// below stay exact.
 template <int KS>
 __device__ __forceinline__ void stage_load(const ProbDev &P, int slot0, StageRegs<KS> &s)
 {
     const int t = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < (2 * KS * WAVE + 255) / 256; ++i) {
-        const int e = t + 256 * i;
-        if ((2 * KS * WAVE) % 256 == 0 || e < 2 * KS * WAVE) {
-            const int f = e / WAVE, l = e % WAVE;   // f = part * KS + ks
-            const uint16_t *base = (f >= KS) ? P.cbl : P.cb;
-            const int ks = f % KS;
-            s.r[i] = *(const bf16x8 *)(base + (size_t)(slot0 + (l & 15)) * P.ldb + 32 * ks + 8 * (l >> 4));
-        }
+        const int e = (t + 256 * i) % (2 * KS * WAVE);
+        const int f = e / WAVE, l = e % WAVE;   // f = part * KS + ks
+        const uint16_t *base = (f >= KS) ? P.cbl : P.cb;
+        const int ks = f % KS;
+        s.r[i] = *(const bf16x8 *)(base + (size_t)(slot0 + (l & 15)) * P.ldb + 32 * ks + 8 * (l >> 4));
     }
-    if (t < 4) s.c = *(const float4 *)(P.cn + slot0 + 4 * t);
+    s.c = *(const float4 *)(P.cn + slot0 + 4 * (t & 3));
 }
 template <int KS>
 __device__ __forceinline__ void stage_store(ChunkStage<KS> &S, const StageRegs<KS> &s)
@@ -1021,58 +1057,90 @@ __device__ __forceinline__ void seq_next(ChunkSeq &q, int ts0, int tns)
     }
 }
 
+// Advance a load cursor; past the last chunk it stays on it.
+__device__ __forceinline__ void seq_next_load(ChunkSeq &q, int ts0, int tns)
+{
+    if (q.c0 + CHUNK < q.ns) q.c0 += CHUNK;
+    else if (q.rest) seq_take(q, ts0, tns);
+}
+
 // The workgroup's visits named by vm: lane j holds group tg, this wave's
 // 16-bit point mask tmw, first slot ts0, size tns and the group's rounded-
 // down drift sum tsgd.  fold(g, m, slot0, nreal, first, sgd, key2) receives
-// each chunk's two smallest keys per point of this wave (skipped when the
-// wave has no point in the visit).  Every thread of the workgroup calls it.
-template <int KS, class Fold>
+// each chunk's two smallest keys per point of this wave; a wave with no
+// point in the visit skips the chunk and calls skip() instead, which issues
+// the same memory operations.  Every thread of the workgroup calls it.
+//
+// DEPTH chunks are in flight: chunk i is read from LDS while chunks
+// i+1 .. i+DEPTH-1 are loading into registers; after chunk i the loads of
+// chunk i+DEPTH are issued and chunk i+1 goes to LDS.  With DEPTH = 1 the
+// next chunk's loads are issued before the current chunk's work.
+template <int KS, int DEPTH, class Fold, class Skip>
 __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, unsigned long long vm, int tg,
                                              unsigned tmw, int ts0, int tns, float tsgd, const PtFrag<KS> &b,
-                                             float xnp, Fold fold)
+                                             float xnp, Fold fold, Skip skip)
 {
     if (vm == 0ull) return;
     ChunkSeq cp, ld;
     seq_begin(cp, vm, ts0, tns);
     ld = cp;
-    StageRegs<KS> sr;
-    stage_load<KS>(P, ld.s0, sr);
-    stage_store<KS>(L.st[0], sr);
-    seq_next(ld, ts0, tns);
+    StageRegs<KS> R[DEPTH];
+#pragma unroll
+    for (int k = 0; k < DEPTH; ++k) {
+        stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
+        seq_next_load(ld, ts0, tns);
+    }
+    stage_store<KS>(L.st[0], R[0]);
     __syncthreads();
     int buf = 0;
-    while (cp.valid) {
-        const bool pre = ld.valid;
-        if (pre) stage_load<KS>(P, ld.s0 + ld.c0, sr);
+    auto work = [&]() {
         const unsigned m = (unsigned)__builtin_amdgcn_readlane((int)tmw, cp.j);
         if (m) {
             const Key2 t = chunk_lds<KS>(L.st[buf], b, xnp);
             fold(__builtin_amdgcn_readlane(tg, cp.j), m, cp.s0 + cp.c0, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0,
                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tsgd), cp.j)), t);
+        } else {
+            skip();
         }
-        if (pre) stage_store<KS>(L.st[buf ^ 1], sr);
-        __syncthreads();
-        seq_next(cp, ts0, tns);
-        if (pre) seq_next(ld, ts0, tns);
-        buf ^= 1;
+    };
+    for (;;) {
+#pragma unroll
+        for (int k = 0; k < DEPTH; ++k) {
+            if (DEPTH == 1) {
+                stage_load<KS>(P, ld.s0 + ld.c0, R[0]);
+                seq_next_load(ld, ts0, tns);
+                work();
+            } else {
+                work();
+                stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
+                seq_next_load(ld, ts0, tns);
+            }
+            stage_store<KS>(L.st[buf ^ 1], R[(k + 1) % DEPTH]);
+            __syncthreads();
+            seq_next(cp, ts0, tns);
+            buf ^= 1;
+            if (!cp.valid) return;
+        }
     }
 }
 
 // BF16 mode, one workgroup per tile of 64 positions.  DENSE (iteration 1):
 // the positions are the points and every group is visited.  Otherwise the
-// positions are entries of the sorted L1: the own groups of the tile's
-// points are visited first, which tightens each point's upper bound to its
-// best estimate there; then each wave tests its points' group bounds
-// against the tightened bounds (lanes over groups) and the workgroup visits
-// every group open for some point of the tile.  Per point: the decision
-// under the error bound, or the flag that sends it to the FP32 recheck.
-template <int KS, bool DENSE>
+// positions are entries of the sorted L1: while its row loads, each point's
+// upper bound is tightened to the FP32 distance to its assigned centroid;
+// then each wave tests its points' group bounds against the tightened
+// bounds (lanes over groups; the own group stays open) and the workgroup
+// visits every group open for some point of the tile.  Per point: the
+// decision under the error bound, or the flag that sends it to the FP32
+// recheck.
+template <int KS, bool DENSE, int DEPTH>
 __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
 {
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const float bmax = P.scal[0];
     const float sdd = P.Sdud[1];
+    float *sink = P.sink + 16 * (blockIdx.x % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
     for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
@@ -1083,7 +1151,7 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
     }
     for (int i = P.g + threadIdx.x; i < ((P.g + 3) & ~3); i += blockDim.x) L.gsu[i] = 0.f;   // float4 tail
     __syncthreads();
-    unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0, n_amb = 0;
+    unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
     // sorted entry of this lane's position in the next tile, loaded one tile ahead
     int4 nxt = make_int4(0, 0, 0, 0);
     if (!DENSE) {
@@ -1112,7 +1180,16 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
         const float eta_f = d2f_up(eta);
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
         PtFrag<KS> b;
-        load_points16<KS>(P, pid, in, b);
+        float ubn = KP_INF;
+        if (DENSE) {
+            load_points16<KS, false>(P, pid, in, nullptr, b);
+        } else {
+            // the upper bound tightened to the FP32 distance to the assigned centroid
+            float d2a = load_points16<KS, true>(P, pid, in, P.c32 + (size_t)(a < 0 ? 0 : a) * P.ldc, b);
+            d2a += __shfl_xor(d2a, 16);
+            d2a += __shfl_xor(d2a, 32);
+            ubn = in ? fminf(ubt, dist_hi(d2a, eps2_tile(KS))) : KP_INF;
+        }
         Run r;
         run_init(r);
         float gmin = KP_INF;   // running minimum of the group being visited
@@ -1125,8 +1202,12 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
             gmin = fminf(gprev, m1);
             run_fold_part(r, mine, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev);
             const float lbv = dn_nonneg(est_lo(gmin, eta_f) + sgd);   // offset form, rounded down
-            if (mine && quad == 0) P.lb[(size_t)pid * P.gs + g] = lbv;
+            // one unconditional store per chunk: lanes without a bound to
+            // write send it to the workgroup's sink slot
+            float *dst = (mine && quad == 0) ? P.lb + (size_t)pid * P.gs + g : sink;
+            *dst = lbv;
         };
+        auto skip = [&]() { *sink = 0.f; };
         float minnc = KP_INF;
         if (DENSE) {
             for (int g0 = 0; g0 < P.g; g0 += WAVE) {
@@ -1136,35 +1217,9 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
                 const float sgd = gv ? L.gsd[g] : 0.f;
                 const unsigned long long vm = __ballot(gv && ns > 0);
                 n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
-                block_visits<KS>(P, L, vm, g, inm, s0, ns, sgd, b, xnp, fold);
+                block_visits<KS, DEPTH>(P, L, vm, g, inm, s0, ns, sgd, b, xnp, fold, skip);
             }
         } else {
-            // own groups of the 64 positions; visit i held by lane i
-            if (quad == 0) L.ga[16 * wv + pt] = in ? ga : -1;
-            __syncthreads();
-            const int gt = L.ga[lane];
-            int tg = 0, nv = 0;
-            unsigned tmw = 0u;
-            for (unsigned long long todo = __ballot(gt >= 0); todo;) {
-                const int p = __ffsll((long long)todo) - 1;
-                const int g = __builtin_amdgcn_readlane(gt, p);
-                const unsigned long long m64 = __ballot(gt == g);
-                if (lane == nv) {
-                    tg = g;
-                    tmw = (unsigned)(m64 >> (16 * wv)) & 0xFFFFu;
-                }
-                ++nv;
-                todo &= ~m64;
-            }
-            {
-                const bool own = lane < nv;
-                const int s0 = own ? L.gst[tg] : 0, ns = own ? L.gsz[tg] : 0;
-                const float sgd = own ? L.gsd[tg] : 0.f;
-                const unsigned long long vm = __ballot(own && ns > 0);
-                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
-                block_visits<KS>(P, L, vm, tg, tmw, s0, ns, sgd, b, xnp, fold);
-            }
-            const float ubn = fminf(ubt, est_hi(r.bd, eta_f));
             // group-level filter, 64 groups per round: lane (point p, quad q)
             // tests groups g0 + 16 q .. +15 of point p (one 64-byte run of its
             // bound row); lane t then holds the visit of group g0 + t
@@ -1192,8 +1247,9 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const int g = gq + j;
-                    const bool cand = in && g < P.g && g != ga;
-                    const bool open = cand && group_open(ubn, sg[j], v[j]);
+                    // the point's own group is always visited
+                    const bool cand = in && g < P.g;
+                    const bool open = cand && (g == ga || group_open(ubn, sg[j], v[j]));
                     cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
                     const unsigned long long bj = __ballot(open);
                     if ((lane & 15) == j) mine = bj;
@@ -1211,31 +1267,31 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
                 const float sgd = gv ? L.gsd[tgr] : 0.f;
                 const unsigned long long vm = __ballot(gv && any != 0u && ns > 0);
                 n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
-                block_visits<KS>(P, L, vm, tgr, tm, s0, ns, sgd, b, xnp, fold);
+                block_visits<KS, DEPTH>(P, L, vm, tgr, tm, s0, ns, sgd, b, xnp, fold, skip);
             }
         }
         bool moved = false, amb = false;
+        const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
             int win = -1;
             float umin = KP_INF;
             decide_bf16(P, pid, DENSE, a, -1, false, KP_INF, KP_INF, KP_INF, minnc, r, eta, 0.0, 0.0, sdd, moved,
                         amb, win, umin);
-            const long long pos = DENSE ? (long long)pid : idx;
             P.mv_pt[pos] = pid;
             P.mv_old[pos] = a;
             P.mv_new[pos] = moved ? win : -1;
-            P.psf[pos] = amb ? 4 : 0;
             if (amb) P.ps4[pos] = make_float4(0.f, 0.f, umin, 0.f);
         }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
-        n_amb += (unsigned long long)__popcll(__ballot(amb));
+        // uncertain points: compact list of positions for the FP32 recheck
+        const long long q3 = wave_append(&P.ctr[CTR_L3], amb);
+        if (q3 >= 0) P.L3[q3] = (int)pos;
     }
     if (lane == 0) {
         if (n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
         if (n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
         if (n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
         if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
-        if (n_amb) atomicAdd(&P.ctr[CTR_L3], n_amb);
     }
 }
 
@@ -1314,14 +1370,15 @@ __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
     const double eps2 = eps2_direct(P.d);
     const float sdd = P.Sdud[1];
     const bool dense = P.ctr[CTR_DENSE] != 0;
-    const long long npos = positions(P);
+    const long long n3 = list_len(P, CTR_L3);   // uncertain positions, listed by the distance kernel
     const long long nteams = (long long)gridDim.x * (blockDim.x / RT);
-    const long long trips = (npos + nteams - 1) / nteams;   // the same for every lane of the grid
+    const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
     unsigned long long n_moved = 0;
     for (long long it = 0; it < trips; ++it) {
-        const long long e = it * nteams + (long long)blockIdx.x * (blockDim.x / RT) + team;
-        const bool live = e < npos && (P.psf[e] & 4);
-        if (__ballot(live) == 0ull) continue;   // no uncertain point in this wave's four... eight teams
+        const long long e3 = it * nteams + (long long)blockIdx.x * (blockDim.x / RT) + team;
+        const bool live = e3 < n3;
+        if (__ballot(live) == 0ull) continue;   // past the end of the list for this wave's eight teams
+        const long long e = live ? (long long)max(min(P.L3[e3], (int)(positions(P) - 1)), 0) : 0;
         const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
         const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
         const float umin = live ? P.ps4[e].z : 0.f;
@@ -1639,25 +1696,31 @@ hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
     return hipGetLastError();
 }
 
-// BF16 mode: one workgroup per 64 positions; KS = ldb / 32 in {1, 2, 3, 4, 6, 8}.
-template <bool DENSE>
+// BF16 mode: one workgroup per 64 positions; KS = ldb / 32 in {1, 2, 3, 4, 6, 8};
+// DEPTH = chunks in flight (1 or 3; 1 is the default).
+template <bool DENSE, int DEPTH>
 static void launch_blk64_ks(const ProbDev &P, hipStream_t s, int grid)
 {
     switch (P.ldb / 32) {
-    case 1: hipLaunchKernelGGL((k_blk64<1, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 2: hipLaunchKernelGGL((k_blk64<2, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL((k_blk64<3, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL((k_blk64<4, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 6: hipLaunchKernelGGL((k_blk64<6, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
-    case 8: hipLaunchKernelGGL((k_blk64<8, DENSE>), dim3(grid), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL((k_blk64<1, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
+    case 2: hipLaunchKernelGGL((k_blk64<2, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL((k_blk64<3, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL((k_blk64<4, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
+    case 6: hipLaunchKernelGGL((k_blk64<6, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
+    case 8: hipLaunchKernelGGL((k_blk64<8, DENSE, DEPTH>), dim3(grid), dim3(256), 0, s, P); break;
     default: break;   // excluded when the plan is made
     }
 }
 static void launch_blk64(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, bool dense)
 {
     const int grid = cap_grid((P.n + 63) / 64, cfg.grid_cap);
-    if (dense) launch_blk64_ks<true>(P, s, grid);
-    else launch_blk64_ks<false>(P, s, grid);
+    if (cfg.depth == 1) {
+        if (dense) launch_blk64_ks<true, 1>(P, s, grid);
+        else launch_blk64_ks<false, 1>(P, s, grid);
+    } else {
+        if (dense) launch_blk64_ks<true, 3>(P, s, grid);
+        else launch_blk64_ks<false, 3>(P, s, grid);
+    }
 }
 
 static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)

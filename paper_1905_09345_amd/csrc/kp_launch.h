@@ -8,6 +8,7 @@ namespace kp {
 struct LaunchCfg {
     int waves;      // waves of 64 lanes per workgroup of the assignment kernels
     int grid_cap;   // upper bound on workgroups of grid-stride kernels
+    int depth;      // centroid chunks in flight per workgroup (BF16 mode): 1 or 3
 };
 
 // Per-point BF16 shadow and norms, initial centroid rows, drift rings at t=0.

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 16
+    assert ctypes.sizeof(kp.kp_tuning) == 20
     assert ctypes.sizeof(kp.kp_stage_time) == 40
     assert ctypes.sizeof(kp.kp_iter_stats) == 64 and kp.kp_iter_stats.point_filter_fail.offset == 8
 
@@ -60,9 +60,16 @@ def test_invalid_problem_rejected(bad):
     assert e.value.status == kp.KP_ERR_INVALID
 
 
-def test_invalid_tuning_rejected():
-    t = kp.kp_tuning(timing=7)
+@pytest.mark.parametrize("field,value", [("timing", 7), ("chunk_depth", 2), ("chunk_depth", -1),
+                                         ("waves_per_block", 5), ("use_graph", 3)])
+def test_invalid_tuning_rejected(field, value):
+    t = kp.kp_tuning(**{field: value})
     assert kp.kp_workspace_bytes([_prob()], t) == 0
+
+
+def test_valid_tuning_accepted():
+    for depth in (0, 1, 3):
+        assert kp.kp_workspace_bytes([_prob()], kp.kp_tuning(chunk_depth=depth)) > 0
 
 
 def test_init_argument_errors_before_device_use():
