@@ -295,6 +295,7 @@ struct kp_ctx {
     hipStream_t user = nullptr, own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<kp::ProbDev> P;
+    kp::Batch batch;                           // count > 1: batched launches
     kp::LaunchCfg cfg{4, 2048, 1};
     int use_graph = 1;
     int iters = 0;
@@ -336,12 +337,23 @@ static void release_ctx(kp_ctx *ctx)
 
 extern "C" {
 
+static size_t batch_header_bytes(int count);
+
 size_t kp_workspace_bytes(const kp_problem *problems, int32_t count, const kp_tuning *tuning)
 {
     if (!validate(problems, count, tuning)) return 0;
     size_t total = 0;
     for (int i = 0; i < count; ++i) total += plan_problem(problems[i]).bytes;
-    return total;
+    return total + batch_header_bytes(count);
+}
+
+// A ctx with several problems keeps, after the problems' regions, a device
+// copy of every problem descriptor and the block tables of the batched
+// launches.
+static size_t batch_header_bytes(int count)
+{
+    if (count <= 1) return 0;
+    return up((size_t)count * sizeof(kp::ProbDev), ALIGN) + up((size_t)kp::TB_COUNT * (count + 1) * 4, ALIGN);
 }
 
 kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void *workspace, size_t ws_bytes,
@@ -364,6 +376,8 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         plans.push_back(plan_problem(problems[i]));
         need += plans.back().bytes;
     }
+    const size_t problem_bytes = need;
+    need += batch_header_bytes(count);
     if (ws_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", ws_bytes, need);
         return KP_ERR_INVALID;
@@ -468,6 +482,17 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         ctx->P.push_back(P);
         base += o.bytes;
     }
+    if (count > 1) {
+        char *hdr = (char *)workspace + problem_bytes;
+        kp::Batch &B = ctx->batch;
+        kp::build_tables(B, ctx->P, ctx->cfg);
+        B.probs = (const kp::ProbDev *)hdr;
+        B.tabs = (const int *)(hdr + up((size_t)count * sizeof(kp::ProbDev), ALIGN));
+        KP_HIP(hipMemcpyAsync((void *)B.probs, ctx->P.data(), (size_t)count * sizeof(kp::ProbDev),
+                              hipMemcpyHostToDevice, ctx->user));
+        KP_HIP(hipMemcpyAsync((void *)B.tabs, B.htabs.data(), B.htabs.size() * 4, hipMemcpyHostToDevice, ctx->user));
+        KP_HIP(hipStreamSynchronize(ctx->user));
+    }
     *out = guard.release();
     g_last_error.clear();
     return KP_OK;
@@ -486,20 +511,30 @@ static kp_status check_ctx(kp_ctx *ctx)
     return KP_OK;
 }
 
+// The stages of one iteration: those of the single problem, or each stage
+// once for the whole batch.
+static int iteration_calls(kp_ctx *ctx, bool dense, kp::Stage sts[kp::ST_COUNT])
+{
+    return ctx->count > 1 ? kp::batch_stages(ctx->P, dense, sts) : kp::iteration_stages(ctx->P[0], dense, sts);
+}
+static hipError_t launch_call(kp_ctx *ctx, kp::Stage st, bool dense)
+{
+    return ctx->count > 1 ? kp::launch_stage_batch(ctx->batch, ctx->own, st, dense, ctx->cfg)
+                          : kp::launch_stage(ctx->P[0], ctx->own, st, dense, ctx->cfg);
+}
+
 // One iteration of every problem as plain launches, each stage bracketed by
 // timing events when timing is on.
 static hipError_t launch_all(kp_ctx *ctx, bool dense)
 {
-    for (auto &P : ctx->P) {
-        kp::Stage sts[kp::ST_COUNT];
-        const int n = kp::iteration_stages(P, dense, sts);
-        for (int i = 0; i < n; ++i) {
-            StageTimer::Rec r;
-            hipError_t e;
-            if (ctx->timing && (e = ctx->timer.begin(sts[i], ctx->own, r)) != hipSuccess) return e;
-            if ((e = kp::launch_stage(P, ctx->own, sts[i], dense, ctx->cfg)) != hipSuccess) return e;
-            if (ctx->timing && (e = ctx->timer.end(ctx->own, r)) != hipSuccess) return e;
-        }
+    kp::Stage sts[kp::ST_COUNT];
+    const int n = iteration_calls(ctx, dense, sts);
+    for (int i = 0; i < n; ++i) {
+        StageTimer::Rec r;
+        hipError_t e;
+        if (ctx->timing && (e = ctx->timer.begin(sts[i], ctx->own, r)) != hipSuccess) return e;
+        if ((e = launch_call(ctx, sts[i], dense)) != hipSuccess) return e;
+        if (ctx->timing && (e = ctx->timer.end(ctx->own, r)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -514,10 +549,9 @@ static hipError_t capture_plain(kp_ctx *ctx)
 {
     hipError_t e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    for (auto &P : ctx->P) {
-        e = kp::launch_iteration(P, ctx->own, false, ctx->cfg);
-        if (e != hipSuccess) break;
-    }
+    kp::Stage sts[kp::ST_COUNT];
+    const int n = iteration_calls(ctx, false, sts);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_call(ctx, sts[i], false);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(ctx->own, &g);
     if (e == hipSuccess) e = e2;
@@ -548,16 +582,16 @@ static hipError_t capture_timed(kp_ctx *ctx, const char **where)
         last = nd;
         return hipSuccess;
     };
-    for (auto &P : ctx->P) {
+    {
         kp::Stage sts[kp::ST_COUNT];
-        const int n = kp::iteration_stages(P, false, sts);
+        const int n = iteration_calls(ctx, false, sts);
         for (int i = 0; i < n; ++i) {
             hipEvent_t a = nullptr, b = nullptr;
             *where = "event-record node";
             if ((e = add_event(a)) != hipSuccess) return e;
             *where = "stage capture";
             if ((e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-            e = kp::launch_stage(P, ctx->own, sts[i], false, ctx->cfg);
+            e = launch_call(ctx, sts[i], false);
             hipGraph_t sg = nullptr;
             const hipError_t e2 = hipStreamEndCapture(ctx->own, &sg);
             if (e == hipSuccess) e = e2;

@@ -26,6 +26,8 @@
 // result is that of standard K-means (Abstract).
 #include "kp_device.h"
 #include "kp_launch.h"
+#include <algorithm>
+#include <cmath>
 #include <climits>
 
 namespace kp {
@@ -51,18 +53,39 @@ __device__ __forceinline__ long long positions(const ProbDev &P)
     return P.ctr[CTR_DENSE] ? P.n : list_len(P, CTR_L1);
 }
 
+// =============================================================== batches
+// A batched launch covers every problem of a ctx: problem i owns blocks
+// tab[i] .. tab[i+1]-1 (possibly none) and runs the single-problem body with
+// its own block index and count.  Returns the problem of this block.
+__device__ __forceinline__ int batch_problem(const int *__restrict__ tab, int count)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = count;   // tab[lo] <= b < tab[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // ===================================================================== prep
 // ||x||^2 of every point (FP64 sum of the FP32 coordinates, rounded to FP32).
-__global__ __launch_bounds__(256) void k_prep(ProbDev P)
+__device__ __forceinline__ void b_prep(const ProbDev &P, const int bid_, const int nblk_)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
+    const int64_t stride = (int64_t)nblk_ * blockDim.x;
+    for (int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x; i < P.n; i += stride) {
         const float *x = P.X + i * P.d;
         double s = 0.0;
         for (int j = 0; j < P.d; ++j) s += (double)x[j] * x[j];
         P.xn[i] = (float)s;
     }
 }
+__global__ __launch_bounds__(256) void k_prep(ProbDev P)
+{
+    b_prep(P, (int)blockIdx.x, (int)gridDim.x);
+}
+
 
 // ============================================================ centroid rows
 // One wave per slot.  INIT: take the caller's initial centroids (original
@@ -70,12 +93,12 @@ __global__ __launch_bounds__(256) void k_prep(ProbDev P)
 // value), then the FP32 copy, its BF16 rounding, ||c_hat||^2, ||c - c_hat||
 // and the drift ||c32_new - c32_old|| (FP64, rounded up).
 template <bool INIT>
-__global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
+__device__ __forceinline__ void b_centroids(const ProbDev &P, const int bid_, const int nblk_, const float *init)
 {
     const int lane = lane_id();
-    const int nw = (int)(gridDim.x * blockDim.x / WAVE);
+    const int nw = (int)(nblk_ * blockDim.x / WAVE);
     const int L = P.prec ? P.ldb : P.ldc;
-    for (int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE); s < P.kg; s += nw) {
+    for (int s = (int)((bid_ * blockDim.x + threadIdx.x) / WAVE); s < P.kg; s += nw) {
         const int orig = P.perm[s];
         if (orig < 0) {
             if (INIT) {
@@ -127,13 +150,26 @@ __global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
         }
     }
 }
+template <bool INIT>
+__global__ __launch_bounds__(256) void k_centroids(ProbDev P, const float *init)
+{
+    b_centroids<INIT>(P, (int)blockIdx.x, (int)gridDim.x, init);
+}
+template <bool INIT>
+__global__ __launch_bounds__(256) void kb_centroids(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count, const float *init)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_centroids<INIT>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi], init);
+}
+
 
 // ================================================================== drifts
 // Single workgroup.  After the update of iteration t: per-group maximum
 // drift, the global maximum, the cumulative sums (FP64, each increment
 // rounded up) and their FP32 copies, the error-bound scalars and the
 // iteration's statistics.  first = 1 at init.
-__global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
+__device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const int nblk_, int first)
 {
     __shared__ double red[1024];
     __shared__ float redf[2][1024];
@@ -193,17 +229,39 @@ __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
         }
     }
 }
+__global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
+{
+    b_drift(P, (int)blockIdx.x, (int)gridDim.x, first);
+}
+__global__ __launch_bounds__(1024) void kb_drift(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count, int first)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_drift(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi], first);
+}
+
 
 // ================================================================= begin
-__global__ void k_begin(ProbDev P, int dense)
+__device__ __forceinline__ void b_begin(const ProbDev &P, const int bid_, const int nblk_, int dense)
 {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = bid_ * blockDim.x + threadIdx.x;
     if (tid < NCTR) P.ctr[tid] = (tid == CTR_DENSE) ? (unsigned long long)dense : 0ull;
-    for (int s = tid; s <= P.kg; s += gridDim.x * blockDim.x) {
+    for (int s = tid; s <= P.kg; s += nblk_ * blockDim.x) {
         P.hist[s] = 0;
         P.hist1[s] = 0;
     }
 }
+__global__ void k_begin(ProbDev P, int dense)
+{
+    b_begin(P, (int)blockIdx.x, (int)gridDim.x, dense);
+}
+__global__ void kb_begin(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count, int dense)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_begin(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi], dense);
+}
+
 
 // ========================================================== bound filter
 // Point-level filter over all points, one chunk of 16 points per thread
@@ -213,14 +271,14 @@ __global__ void k_begin(ProbDev P, int dense)
 // points.
 constexpr int BF_PER_THREAD = 16;
 
-__global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
+__device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int wcount[4];
     __shared__ unsigned long long base_s;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
     const float sdu = P.Sdud[0];
     const int64_t chunk = 256 * BF_PER_THREAD;
-    for (int64_t b0 = (int64_t)blockIdx.x * chunk; b0 < P.n; b0 += (int64_t)gridDim.x * chunk) {
+    for (int64_t b0 = (int64_t)bid_ * chunk; b0 < P.n; b0 += (int64_t)nblk_ * chunk) {
         unsigned long long masks[BF_PER_THREAD];
         int mine = 0;
 #pragma unroll
@@ -252,10 +310,21 @@ __global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
         __syncthreads();
     }
 }
+__global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
+{
+    b_bound_filter(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(256) void kb_bound_filter(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_bound_filter(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ======================================================= L1 sort by slot
 // key of L1 entry e: the slot its point is assigned to.
-__global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
+__device__ __forceinline__ void b_key_hist(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
     const long long n1 = list_len(P, CTR_L1);
@@ -263,8 +332,8 @@ __global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
     if (lds)
         for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n1;
-         e += (long long)gridDim.x * blockDim.x) {
+    for (long long e = (long long)bid_ * blockDim.x + threadIdx.x; e < n1;
+         e += (long long)nblk_ * blockDim.x) {
         const int key = clamp_slot(P, P.st[clamp_pid(P, P.L1[e])].a);
         if (lds) atomicAdd(&h[key], 1);
         else atomicAdd(&P.hist1[key], 1);
@@ -274,9 +343,20 @@ __global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
         for (int i = threadIdx.x; i < P.kg; i += blockDim.x)
             if (h[i]) atomicAdd(&P.hist1[i], h[i]);
 }
+__global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
+{
+    b_key_hist(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(256) void kb_key_hist(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_key_hist(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // Exclusive scan of hist[0..n) into cursor (single workgroup of 1024).
-__global__ __launch_bounds__(1024) void k_scan(const int *hist, int *cursor, int n)
+__device__ __forceinline__ void b_scan(const int *hist, int *cursor, int n)
 {
     __shared__ int part[1024];
     const int tid = threadIdx.x;
@@ -298,13 +378,22 @@ __global__ __launch_bounds__(1024) void k_scan(const int *hist, int *cursor, int
         run += hist[i];
     }
 }
+__global__ __launch_bounds__(1024) void k_scan(const int *hist, int *cursor, int n) { b_scan(hist, cursor, n); }
+// One workgroup per problem: which = 1 scans the L1 sort histogram, 0 the update one.
+__global__ __launch_bounds__(1024) void kb_scan(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count, int which)
+{
+    const ProbDev P = probs[batch_problem(tab, count)];
+    if (which) b_scan(P.hist1, P.cursor1, P.kg);
+    else b_scan(P.hist, P.cursor, P.kg);
+}
 
-__global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
+
+__device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
     __shared__ int base[HIST_LDS];
     const long long E = list_len(P, CTR_L1);
-    const long long b0 = E * blockIdx.x / gridDim.x, b1 = E * (blockIdx.x + 1) / gridDim.x;
+    const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
     if (P.kg > HIST_LDS) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
             const int pid = clamp_pid(P, P.L1[e]);
@@ -335,6 +424,17 @@ __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
         if (P.prec) P.L1x[pos] = make_int4(pid, key, __float_as_int(ub_now(st.u, P.Scu[key])), st.ga);
     }
 }
+__global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
+{
+    b_l1_scatter(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(256) void kb_l1_scatter(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_l1_scatter(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ===================================================== FP32 direct distance
 // Squared distance in the direct form with accumulator i mod 4 (see
@@ -762,7 +862,7 @@ __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dens
 
 // ============================================================ dense (iteration 1)
 template <int DMAX>
-__global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
+__device__ __forceinline__ void b_dense_f32(const ProbDev &P, const int bid_, const int nblk_)
 {
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
@@ -770,8 +870,8 @@ __global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
     const float sdd = P.Sdud[1];
     const long long ntiles = (P.n + WAVE - 1) / WAVE;
     unsigned long long n_moved = 0;
-    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)gridDim.x * wpb) {
+    for (long long tl = (long long)bid_ * wpb + threadIdx.x / WAVE; tl < ntiles;
+         tl += (long long)nblk_ * wpb) {
         const long long idx = tl * WAVE + lane;
         const bool act = idx < P.n;
         const int pid = act ? (int)idx : 0;
@@ -805,11 +905,24 @@ __global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
         n_moved += (unsigned long long)__popcll(__ballot(moved));
     }
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid_ == 0 && threadIdx.x == 0) {
         atomicAdd(&P.ctr[CTR_PAIRS], (unsigned long long)P.n * (unsigned long long)P.g);
         atomicAdd(&P.ctr[CTR_DIST], (unsigned long long)P.n * (unsigned long long)P.k);
     }
 }
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_dense_f32(ProbDev P)
+{
+    b_dense_f32<DMAX>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+template <int DMAX>
+__global__ __launch_bounds__(256) void kb_dense_f32(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_dense_f32<DMAX>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ================================================ group-level filter (phase 1)
 // One wave per tile of 64 consecutive entries of the sorted L1 (lane = point
@@ -828,7 +941,7 @@ constexpr int GT_WAVES = 4;
 constexpr int GT_CH = 32;             // groups per LDS chunk
 constexpr int GT_LD = GT_CH + 1;      // LDS row pitch (bank-conflict free)
 
-__global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
+__device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ float stage[GT_WAVES][WAVE * GT_LD];
     const int lane = lane_id();
@@ -838,7 +951,7 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
     const long long ntiles = (count + WAVE - 1) / WAVE;
     const int half = lane >> 5, col = lane & 31;
     unsigned long long n_pairs = 0, n_visits = 0;
-    for (long long tl = (long long)blockIdx.x * GT_WAVES + wv; tl < ntiles; tl += (long long)gridDim.x * GT_WAVES) {
+    for (long long tl = (long long)bid_ * GT_WAVES + wv; tl < ntiles; tl += (long long)nblk_ * GT_WAVES) {
         const long long idx = tl * WAVE + lane;
         const bool act = idx < count;
         const int pid = act ? clamp_pid(P, P.L1s[idx]) : 0;
@@ -896,10 +1009,21 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
     if (lane == 0 && n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
     if (lane == 0 && n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
 }
+__global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
+{
+    b_group_test(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(WAVE * GT_WAVES) void kb_group_test(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_group_test(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ================================================== distance kernels (phase 2)
 template <int DMAX>
-__global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
+__device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, const int nblk_)
 {
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
@@ -908,8 +1032,8 @@ __global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
     const long long count = list_len(P, CTR_L1);
     const long long ntiles = (count + WAVE - 1) / WAVE;
     unsigned long long n_dist = 0, n_moved = 0;
-    for (long long tl = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)gridDim.x * wpb) {
+    for (long long tl = (long long)bid_ * wpb + threadIdx.x / WAVE; tl < ntiles;
+         tl += (long long)nblk_ * wpb) {
         const long long idx = tl * WAVE + lane;
         const bool in = idx < count;
         const int flags = in ? P.psf[idx] : 0;
@@ -954,6 +1078,19 @@ __global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
     if (lane == 0 && n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_tile_f32(ProbDev P)
+{
+    b_tile_f32<DMAX>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+template <int DMAX>
+__global__ __launch_bounds__(256) void kb_tile_f32(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_tile_f32<DMAX>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ---------------------------------------------- workgroup of 64 positions
 // Four waves; wave w holds positions 16 w .. 16 w + 15 of the tile in its B
@@ -1134,13 +1271,13 @@ __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, 
 // decision under the error bound, or the flag that sends it to the FP32
 // recheck.
 template <int KS, bool DENSE, int DEPTH>
-__global__ __launch_bounds__(256) void k_blk64(ProbDev P)
+__device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const float bmax = P.scal[0];
     const float sdd = P.Sdud[1];
-    float *sink = P.sink + 16 * (blockIdx.x % SINK_SLOTS);
+    float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
     for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
@@ -1155,10 +1292,10 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
     // sorted entry of this lane's position in the next tile, loaded one tile ahead
     int4 nxt = make_int4(0, 0, 0, 0);
     if (!DENSE) {
-        const long long i0 = (long long)blockIdx.x * 64 + 16 * wv + pt;
+        const long long i0 = (long long)bid_ * 64 + 16 * wv + pt;
         if (i0 < count) nxt = P.L1x[i0];
     }
-    for (long long tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {   // uniform per workgroup
+    for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
         const long long idx = tl * 64 + 16 * wv + pt;
         const bool in = idx < count;
         int pid = in && DENSE ? (int)idx : 0;
@@ -1166,7 +1303,7 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
         float ubt = KP_INF;
         if (!DENSE) {
             const int4 e = nxt;
-            const long long inext = idx + 64ll * gridDim.x;
+            const long long inext = idx + 64ll * nblk_;
             if (inext < count) nxt = P.L1x[inext];
             if (in) {
                 pid = clamp_pid(P, e.x);
@@ -1294,6 +1431,19 @@ __global__ __launch_bounds__(256) void k_blk64(ProbDev P)
         if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
     }
 }
+template <int KS, bool DENSE, int DEPTH>
+__global__ __launch_bounds__(256) void k_blk64(ProbDev P)
+{
+    b_blk64<KS, DENSE, DEPTH>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+template <int KS, bool DENSE, int DEPTH>
+__global__ __launch_bounds__(256) void kb_blk64(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_blk64<KS, DENSE, DEPTH>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ================================================================ recheck
 // Eight lanes per uncertain point (32 points per workgroup).  Candidates:
@@ -1360,7 +1510,7 @@ __device__ __forceinline__ float team_d2(const float4 (&x)[NV], const float *__r
 }
 
 template <int NV>
-__global__ __launch_bounds__(256) void k_recheck(ProbDev P)
+__device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int rg[256 / RT][RMAX];
     __shared__ float rm1[256 / RT][RMAX], rm2[256 / RT][RMAX];
@@ -1371,11 +1521,11 @@ __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
     const float sdd = P.Sdud[1];
     const bool dense = P.ctr[CTR_DENSE] != 0;
     const long long n3 = list_len(P, CTR_L3);   // uncertain positions, listed by the distance kernel
-    const long long nteams = (long long)gridDim.x * (blockDim.x / RT);
+    const long long nteams = (long long)nblk_ * (blockDim.x / RT);
     const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
     unsigned long long n_moved = 0;
     for (long long it = 0; it < trips; ++it) {
-        const long long e3 = it * nteams + (long long)blockIdx.x * (blockDim.x / RT) + team;
+        const long long e3 = it * nteams + (long long)bid_ * (blockDim.x / RT) + team;
         const bool live = e3 < n3;
         if (__ballot(live) == 0ull) continue;   // past the end of the list for this wave's eight teams
         const long long e = live ? (long long)max(min(P.L3[e3], (int)(positions(P) - 1)), 0) : 0;
@@ -1529,6 +1679,19 @@ __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
     // one atomic per lane that decided points (lane 0 of each team)
     if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
+template <int NV>
+__global__ __launch_bounds__(256) void k_recheck(ProbDev P)
+{
+    b_recheck<NV>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+template <int NV>
+__global__ __launch_bounds__(256) void kb_recheck(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_recheck<NV>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ========================================================= centroid update
 // Entries over the M positions of the iteration: e < M adds point mv_pt[e]
@@ -1544,7 +1707,7 @@ __device__ __forceinline__ int entry_key(const ProbDev &P, long long e, long lon
     return k < 0 ? -1 : clamp_slot(P, k);
 }
 
-__global__ __launch_bounds__(256) void k_hist(ProbDev P)
+__device__ __forceinline__ void b_hist(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
     const long long M = positions(P);
@@ -1553,8 +1716,8 @@ __global__ __launch_bounds__(256) void k_hist(ProbDev P)
     if (lds)
         for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-         e += (long long)gridDim.x * blockDim.x) {
+    for (long long e = (long long)bid_ * blockDim.x + threadIdx.x; e < E;
+         e += (long long)nblk_ * blockDim.x) {
         const int key = entry_key(P, e, M);
         if (key < 0) continue;
         if (lds) atomicAdd(&h[key], 1);
@@ -1565,15 +1728,26 @@ __global__ __launch_bounds__(256) void k_hist(ProbDev P)
         for (int i = threadIdx.x; i < P.kg; i += blockDim.x)
             if (h[i]) atomicAdd(&P.hist[i], h[i]);
 }
+__global__ __launch_bounds__(256) void k_hist(ProbDev P)
+{
+    b_hist(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(256) void kb_hist(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_hist(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
 
-__global__ __launch_bounds__(256) void k_scatter(ProbDev P)
+
+__device__ __forceinline__ void b_scatter(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
     __shared__ int base[HIST_LDS];
     const long long M = positions(P);
     const long long E = 2 * M;
     const bool lds = P.kg <= HIST_LDS;
-    const long long b0 = E * blockIdx.x / gridDim.x, b1 = E * (blockIdx.x + 1) / gridDim.x;
+    const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
     if (!lds) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
             const int key = entry_key(P, e, M);
@@ -1607,19 +1781,30 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev P)
         P.srt_key[pos] = key;
     }
 }
+__global__ __launch_bounds__(256) void k_scatter(ProbDev P)
+{
+    b_scatter(P, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ __launch_bounds__(256) void kb_scatter(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_scatter(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // One wave per run of 64 sorted entries; lanes over coordinates.  Sums are
 // FP64; a change of key flushes the run with FP64 atomics.
 template <int DCH>
-__global__ __launch_bounds__(256) void k_segsum(ProbDev P)
+__device__ __forceinline__ void b_segsum(const ProbDev &P, const int bid_, const int nblk_)
 {
     const int lane = lane_id();
     const long long M = positions(P);
     const long long used = (long long)P.cursor[P.kg - 1];   // end of the last bin = entries sorted
     const long long E = used < 2 * M ? used : 2 * M;
     const long long nchunks = (E + WAVE - 1) / WAVE;
-    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
-    for (long long c = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; c < nchunks; c += nw) {
+    const long long nw = (long long)nblk_ * (blockDim.x / WAVE);
+    for (long long c = (long long)bid_ * (blockDim.x / WAVE) + threadIdx.x / WAVE; c < nchunks; c += nw) {
         const long long p0 = c * WAVE, p1 = (p0 + WAVE < E) ? p0 + WAVE : E;
         double acc[DCH];
 #pragma unroll
@@ -1661,6 +1846,19 @@ __global__ __launch_bounds__(256) void k_segsum(ProbDev P)
         if (lane == 0) atomicAdd(&P.cnt[cur], cacc);
     }
 }
+template <int DCH>
+__global__ __launch_bounds__(256) void k_segsum(ProbDev P)
+{
+    b_segsum<DCH>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+template <int DCH>
+__global__ __launch_bounds__(256) void kb_segsum(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_segsum<DCH>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 
 // ================================================================ outputs
 __global__ void k_labels(ProbDev P, int *out)
@@ -1851,6 +2049,172 @@ hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const L
     }
     return hipSuccess;
 }
+
+// ------------------------------------------------------------- batches
+static int dmax_class(int ldc) { return ldc <= 8 ? 0 : ldc <= 16 ? 1 : ldc <= 32 ? 2 : ldc <= 64 ? 3 : 4; }
+static int ks_class(int ldb)
+{
+    switch (ldb / 32) {
+    case 1: return 0;
+    case 2: return 1;
+    case 3: return 2;
+    case 4: return 3;
+    case 6: return 4;
+    default: return 5;
+    }
+}
+static int nv_class(int ldc) { return ldc <= 32 ? 0 : ldc <= 64 ? 1 : ldc <= 128 ? 2 : 3; }
+static int dch_class(int d)
+{
+    const int c = (d + 63) / 64;
+    return c <= 4 ? c - 1 : c <= 8 ? 4 : 5;
+}
+
+// Blocks of problem P in table id (the shapes of the single-problem launches
+// above, with `cap` for the grid-stride kernels).
+static int tab_blocks(int id, const ProbDev &P, const LaunchCfg &cfg, int cap)
+{
+    const long long n = P.n;
+    const bool f32 = P.prec == 0;
+    if (id >= TB_DENSE_F32 && id < TB_TILE_F32)
+        return f32 && dmax_class(P.ldc) == id - TB_DENSE_F32 ? cap_grid(((n + 63) / 64 + cfg.waves - 1) / cfg.waves, cap)
+                                                              : 0;
+    if (id >= TB_TILE_F32 && id < TB_BLK64)
+        return f32 && dmax_class(P.ldc) == id - TB_TILE_F32 ? cap_grid(((n + 63) / 64 + cfg.waves - 1) / cfg.waves, cap)
+                                                             : 0;
+    if (id >= TB_BLK64 && id < TB_RECHECK)
+        return !f32 && ks_class(P.ldb) == id - TB_BLK64 ? cap_grid((n + 63) / 64, cap) : 0;
+    if (id >= TB_RECHECK && id < TB_SEGSUM)
+        return !f32 && nv_class(P.ldc) == id - TB_RECHECK ? cap_grid((n + 31) / 32, cap) : 0;
+    if (id >= TB_SEGSUM && id < TB_COUNT)
+        return dch_class(P.d) == id - TB_SEGSUM ? cap_grid((2 * n + 255) / 256, cap) : 0;
+    switch (id) {
+    case TB_BEGIN: return cap_grid((P.kg + 256) / 256, 64);
+    case TB_FILTER: return cap_grid((n + 4095) / 4096, cap);
+    case TB_SORT: return cap_grid((n + 16383) / 16384, 1024);
+    case TB_ONE: return 1;
+    case TB_CENT: return cap_grid((P.kg + 3) / 4, 4096);
+    case TB_GT: return f32 ? cap_grid(((n + 63) / 64 + GT_WAVES - 1) / GT_WAVES, cap) : 0;
+    case TB_HIST: return cap_grid((2 * n + 255) / 256, cap);
+    case TB_SCATTER: return cap_grid((2 * n + 4095) / 4096, 1024);
+    default: return 0;
+    }
+}
+
+void build_tables(Batch &B, const std::vector<ProbDev> &hp, const LaunchCfg &cfg)
+{
+    const int count = (int)hp.size();
+    B.count = count;
+    B.htabs.assign((size_t)TB_COUNT * (count + 1), 0);
+    double ntot = 0.0;
+    for (const ProbDev &P : hp) ntot += (double)P.n;
+    for (int id = 0; id < TB_COUNT; ++id) {
+        int *t = &B.htabs[(size_t)id * (count + 1)];
+        long long acc = 0;
+        for (int i = 0; i < count; ++i) {
+            // grid-stride kernels: four times the single-problem cap, shared in proportion to N
+            const int cap = count == 1 ? cfg.grid_cap
+                                       : (int)std::max(8.0, std::ceil(4.0 * cfg.grid_cap * (double)hp[i].n / ntot));
+            t[i] = (int)acc;
+            acc += tab_blocks(id, hp[i], cfg, cap);
+        }
+        t[count] = (int)acc;
+    }
+}
+
+int batch_stages(const std::vector<ProbDev> &hp, bool dense, Stage out[ST_COUNT])
+{
+    bool any_bf16 = false;
+    for (const ProbDev &P : hp) any_bf16 |= P.prec != 0;
+    int n = 0;
+    out[n++] = ST_BEGIN;
+    if (dense) {
+        out[n++] = ST_ASSIGN_DENSE;
+    } else {
+        out[n++] = ST_FILTER;
+        out[n++] = ST_SORT;
+        out[n++] = ST_ASSIGN;
+    }
+    if (any_bf16) out[n++] = ST_RECHECK;
+    out[n++] = ST_UPDATE;
+    out[n++] = ST_CENTROIDS;
+    return n;
+}
+
+#define KB_LAUNCH(id, kern, threads, ...)                                                                   \
+    do {                                                                                                    \
+        const int tot_ = B.total(id);                                                                       \
+        if (tot_ > 0) hipLaunchKernelGGL(kern, dim3(tot_), dim3(threads), 0, s, B.probs, B.tab(id), B.count, \
+                                         ##__VA_ARGS__);                                                    \
+    } while (0)
+
+template <bool DENSE, int DEPTH>
+static void batch_blk64(const Batch &B, hipStream_t s)
+{
+    KB_LAUNCH(TB_BLK64 + 0, (kb_blk64<1, DENSE, DEPTH>), 256);
+    KB_LAUNCH(TB_BLK64 + 1, (kb_blk64<2, DENSE, DEPTH>), 256);
+    KB_LAUNCH(TB_BLK64 + 2, (kb_blk64<3, DENSE, DEPTH>), 256);
+    KB_LAUNCH(TB_BLK64 + 3, (kb_blk64<4, DENSE, DEPTH>), 256);
+    KB_LAUNCH(TB_BLK64 + 4, (kb_blk64<6, DENSE, DEPTH>), 256);
+    KB_LAUNCH(TB_BLK64 + 5, (kb_blk64<8, DENSE, DEPTH>), 256);
+}
+
+hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dense, const LaunchCfg &cfg)
+{
+    const int wthreads = 64 * cfg.waves;
+    switch (st) {
+    case ST_BEGIN: KB_LAUNCH(TB_BEGIN, kb_begin, 256, dense ? 1 : 0); break;
+    case ST_FILTER: KB_LAUNCH(TB_FILTER, kb_bound_filter, 256); break;
+    case ST_SORT:
+        KB_LAUNCH(TB_SORT, kb_key_hist, 256);
+        KB_LAUNCH(TB_ONE, kb_scan, 1024, 1);
+        KB_LAUNCH(TB_SORT, kb_l1_scatter, 256);
+        break;
+    case ST_ASSIGN_DENSE:
+        KB_LAUNCH(TB_DENSE_F32 + 0, kb_dense_f32<8>, wthreads);
+        KB_LAUNCH(TB_DENSE_F32 + 1, kb_dense_f32<16>, wthreads);
+        KB_LAUNCH(TB_DENSE_F32 + 2, kb_dense_f32<32>, wthreads);
+        KB_LAUNCH(TB_DENSE_F32 + 3, kb_dense_f32<64>, wthreads);
+        KB_LAUNCH(TB_DENSE_F32 + 4, kb_dense_f32<128>, wthreads);
+        if (cfg.depth == 1) batch_blk64<true, 1>(B, s);
+        else batch_blk64<true, 3>(B, s);
+        break;
+    case ST_ASSIGN:
+        KB_LAUNCH(TB_GT, kb_group_test, WAVE * GT_WAVES);
+        KB_LAUNCH(TB_TILE_F32 + 0, kb_tile_f32<8>, wthreads);
+        KB_LAUNCH(TB_TILE_F32 + 1, kb_tile_f32<16>, wthreads);
+        KB_LAUNCH(TB_TILE_F32 + 2, kb_tile_f32<32>, wthreads);
+        KB_LAUNCH(TB_TILE_F32 + 3, kb_tile_f32<64>, wthreads);
+        KB_LAUNCH(TB_TILE_F32 + 4, kb_tile_f32<128>, wthreads);
+        if (cfg.depth == 1) batch_blk64<false, 1>(B, s);
+        else batch_blk64<false, 3>(B, s);
+        break;
+    case ST_RECHECK:
+        KB_LAUNCH(TB_RECHECK + 0, kb_recheck<1>, 256);
+        KB_LAUNCH(TB_RECHECK + 1, kb_recheck<2>, 256);
+        KB_LAUNCH(TB_RECHECK + 2, kb_recheck<4>, 256);
+        KB_LAUNCH(TB_RECHECK + 3, kb_recheck<8>, 256);
+        break;
+    case ST_UPDATE:
+        KB_LAUNCH(TB_HIST, kb_hist, 256);
+        KB_LAUNCH(TB_ONE, kb_scan, 1024, 0);
+        KB_LAUNCH(TB_SCATTER, kb_scatter, 256);
+        KB_LAUNCH(TB_SEGSUM + 0, kb_segsum<1>, 256);
+        KB_LAUNCH(TB_SEGSUM + 1, kb_segsum<2>, 256);
+        KB_LAUNCH(TB_SEGSUM + 2, kb_segsum<3>, 256);
+        KB_LAUNCH(TB_SEGSUM + 3, kb_segsum<4>, 256);
+        KB_LAUNCH(TB_SEGSUM + 4, kb_segsum<8>, 256);
+        KB_LAUNCH(TB_SEGSUM + 5, kb_segsum<16>, 256);
+        break;
+    case ST_CENTROIDS:
+        KB_LAUNCH(TB_CENT, kb_centroids<false>, 256, (const float *)nullptr);
+        KB_LAUNCH(TB_ONE, kb_drift, 1024, 0);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+#undef KB_LAUNCH
 
 hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out)
 {

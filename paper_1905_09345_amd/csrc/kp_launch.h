@@ -1,6 +1,7 @@
 // Host-side launchers of the kernels in kp_kernels.hip (internal to libkp).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <vector>
 #include "kp_device.h"
 
 namespace kp {
@@ -22,6 +23,35 @@ int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT]);
 hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, const LaunchCfg &cfg);
 // One K-means iteration (dense = every distance) of one problem.
 hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const LaunchCfg &cfg);
+// ---------------------------------------------------------------- batches
+// A ctx with several problems launches each stage once for all of them.
+// Table id (a launch shape, per template class where the kernel has one)
+// gives each problem a contiguous range of blocks; a problem outside the
+// class gets none.
+enum TabId {
+    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_HIST, TB_SCATTER,
+    TB_DENSE_F32,                     // + DMAX class (5)
+    TB_TILE_F32 = TB_DENSE_F32 + 5,   // + DMAX class (5)
+    TB_BLK64 = TB_TILE_F32 + 5,       // + KS class (6)
+    TB_RECHECK = TB_BLK64 + 6,        // + NV class (4)
+    TB_SEGSUM = TB_RECHECK + 4,       // + DCH class (6)
+    TB_COUNT = TB_SEGSUM + 6
+};
+struct Batch {
+    int count = 0;
+    const ProbDev *probs = nullptr;   // device copy of the problems
+    const int *tabs = nullptr;        // device: TB_COUNT tables of count + 1 block offsets
+    std::vector<int> htabs;           // host copy
+    int total(int id) const { return htabs[(size_t)id * (count + 1) + count]; }
+    const int *tab(int id) const { return tabs + (size_t)id * (count + 1); }
+};
+// Block offsets of every table for these problems (host side).
+void build_tables(Batch &B, const std::vector<ProbDev> &hp, const LaunchCfg &cfg);
+// The stages of one iteration of a batch, in order.
+int batch_stages(const std::vector<ProbDev> &hp, bool dense, Stage out[ST_COUNT]);
+// Launch one stage for every problem of the batch.
+hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dense, const LaunchCfg &cfg);
+
 // Current assignment as original centroid indices.
 hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out);
 // Current centroids in original order (either output may be null).

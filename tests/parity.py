@@ -90,3 +90,38 @@ def run_steplocked(X, C0, g, precision, iters, *, seed=0, tuning=None, sample=No
     finally:
         km.close()
     return report
+
+
+def run_steplocked_batch(problems, iters, *, tuning=None, check_every=1):
+    """Several problems in one ctx (batched launches), each checked step-locked
+    against the oracle as in run_steplocked.  problems: list of
+    (X, C0, g, precision).  Returns one report per problem."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+
+    dev = [(torch.from_numpy(np.ascontiguousarray(X)).cuda(), torch.from_numpy(np.ascontiguousarray(C0)).cuda(),
+            g, prec, 0) for X, C0, g, prec in problems]
+    km = KMeans(dev, tuning=tuning)
+    prev = [(C0.astype(np.float32), C0.astype(np.float64)) for _, C0, _, _ in problems]
+    scales = [float(np.sqrt((X.astype(np.float64) ** 2).sum(axis=1).mean())) for X, _, _, _ in problems]
+    reports = [dict(mismatch=[], allowed=[]) for _ in problems]
+    try:
+        for t in range(1, iters + 1):
+            km.iterate(1)
+            for i, (X, _, _, _) in enumerate(problems):
+                lab = km.assign(i).cpu().numpy()
+                c32, c64 = [a.cpu().numpy() for a in km.centroids(i)]
+                if t % check_every == 0 or t == 1 or t == iters:
+                    try:
+                        m, a = check_assignment(X, prev[i][0], lab)
+                        check_centroids(X, lab, prev[i][1], c32, c64, scales[i])
+                    except AssertionError as e:
+                        raise AssertionError("problem %d, iteration %d: %s" % (i, t, e))
+                    reports[i]["mismatch"].append(m)
+                    reports[i]["allowed"].append(a)
+                prev[i] = (c32, c64)
+        for i in range(len(problems)):
+            reports[i]["stats"] = km.stats(i)
+    finally:
+        km.close()
+    return reports

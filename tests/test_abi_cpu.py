@@ -46,7 +46,9 @@ def test_workspace_bytes_valid_and_monotone():
     b = kp.kp_workspace_bytes([_prob(n=2000)])
     c = kp.kp_workspace_bytes([_prob(precision=1)])
     assert 0 < a < b and a < c
-    assert kp.kp_workspace_bytes([_prob(), _prob(n=2000)]) == a + b
+    # several problems: their regions plus the batch header (descriptors and block tables)
+    two = kp.kp_workspace_bytes([_prob(), _prob(n=2000)])
+    assert a + b < two <= a + b + 64 * 1024
 
 
 @pytest.mark.parametrize("bad", [dict(n=0), dict(k=0), dict(k=2000), dict(g=0), dict(g=17), dict(d=0),

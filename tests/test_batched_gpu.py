@@ -1,0 +1,60 @@
+"""GPU parity of the batched form: several independent problems of uneven
+N, D, K and precision in one context, every stage launched once for all of
+them, each problem checked step-locked against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+from parity import run_steplocked_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(seed, n, d, k, prec):
+    rng = np.random.default_rng(seed)
+    X = datagen.gaussian_mixture(rng, n, d, k)
+    C0 = datagen.kmeanspp(rng, X, k, sample=min(n, 64 * k))
+    return X, C0, int(math.ceil(k / 10)), prec
+
+
+def test_mixed_batch():
+    """Uneven sizes, both precisions, ragged and padded dimensions."""
+    specs = [(1, 3_001, 16, 16, "bf16"), (2, 9_017, 32, 64, "bf16"), (3, 20_011, 64, 256, "bf16"),
+             (4, 4_099, 37, 20, "bf16"), (5, 7_001, 5, 12, "fp32"), (6, 12_007, 32, 64, "fp32"),
+             (7, 150, 16, 16, "bf16"), (8, 65, 8, 3, "fp32")]
+    print("CASE batch-mixed", len(specs), flush=True)
+    reps = run_steplocked_batch([_problem(*sp) for sp in specs], 8)
+    for r in reps:
+        assert len(r["stats"]) == 8 and r["stats"][0]["dense"] == 1
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_batch_of_small_problems(depth):
+    """Many small problems of the batched workload's shapes."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    rng = np.random.default_rng(42)
+    specs = []
+    for p in range(24):
+        specs.append((500 + p, int(rng.integers(300, 3000)), int(rng.choice([16, 32, 64])),
+                      int(rng.choice([16, 64, 256])), "bf16"))
+    print("CASE batch-small", len(specs), depth, flush=True)
+    run_steplocked_batch([_problem(*sp) for sp in specs], 6, tuning=kp_tuning(chunk_depth=depth), check_every=2)
+
+
+def test_batch_graph_and_timing():
+    """Batched iterations replayed from a captured graph, stages timed inside it."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning
+    probs = [_problem(900 + i, 2_000 + 500 * i, 32, 64, "bf16") for i in range(5)]
+    dev = [(torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda(), g, prec) for X, C0, g, prec in probs]
+    print("CASE batch-graph", flush=True)
+    km = KMeans(dev, tuning=kp_tuning(timing=1, use_graph=1))
+    km.iterate(4)
+    t = km.stage_times()
+    assert t["filtered_iter"]["launches"] == 3 and t["assign"]["launches"] == 3
+    for i in range(len(probs)):
+        assert len(km.stats(i)) == 4
+    km.close()
