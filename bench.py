@@ -52,6 +52,8 @@ def parse():
                     help="plain launches instead of graph replays")
     ap.add_argument("--depth", type=int, default=0, choices=[0, 1, 3],
                     help="centroid chunks in flight per workgroup (0: library default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip kp_autotune (untimed, before the contexts are made) and use the defaults")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device twice (reference for the HBM byte counters) and exit")
     return ap.parse_args()
@@ -138,7 +140,7 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(P.X).to(dev)
     C0d = torch.from_numpy(P.C0).to(dev)
-    tun = kp_tuning(timing=1, use_graph=-1 if args.plain else 1, chunk_depth=args.depth)
+    tun = tuned(args, KMeans, kp_tuning, [(Xd, C0d, P.g, prec, P.seed)])
     runs = []
     for i in range(args.warmup + args.steps):
         runs.append(KMeans([(Xd, C0d, P.g, prec, P.seed)], tuning=tun))
@@ -194,7 +196,7 @@ def main():
         "data": "synthetic (seeded mixture, see datagen)",
         "config": {"workload": P.meta["name"], "n": P.n, "d": P.d, "k": P.k, "g": P.g, "iterations": P.iters,
                    "precision": "bf16 MFMA + fp32 recheck + fp64 centroids" if prec == "bf16"
-                   else "fp32 direct + fp64 centroids"},
+                   else "fp32 direct + fp64 centroids", "tuning": TUNING},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp32_lloyd": baseline,
@@ -232,6 +234,24 @@ def traffic_of(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
+def tuned(args, KMeans, kp_tuning, spec):
+    """Launch tuning of the measured runs: kp_autotune's pick unless disabled
+    or fixed on the command line; timing on (stage events)."""
+    tun = kp_tuning(chunk_depth=args.depth)
+    if not args.no_autotune and not args.depth:
+        t0 = time.perf_counter()
+        tun = KMeans.autotune(spec, iters=3)
+        log("autotune: chunk_depth=%d blocks_per_cu=%d (%.1f s)" % (tun.chunk_depth, tun.blocks_per_cu,
+                                                                    time.perf_counter() - t0))
+    tun.timing = 1
+    tun.use_graph = -1 if args.plain else 1
+    TUNING.update(chunk_depth=tun.chunk_depth, blocks_per_cu=tun.blocks_per_cu, use_graph=tun.use_graph)
+    return tun
+
+
+TUNING = {}
+
+
 def main_batched(args, torch, datagen, KMeans, kp_tuning):
     """The batched workload: many independent problems in one context, every
     stage launched once for all of them, one graph replay per iteration."""
@@ -244,7 +264,7 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
     Xd = [torch.from_numpy(p.X).to(dev) for p in probs]
     Cd = [torch.from_numpy(p.C0).to(dev) for p in probs]
     spec = [(Xd[i], Cd[i], p.g, p.precision, p.seed) for i, p in enumerate(probs)]
-    tun = kp_tuning(timing=1, use_graph=-1 if args.plain else 1, chunk_depth=args.depth)
+    tun = tuned(args, KMeans, kp_tuning, spec)
     runs = [KMeans(spec, tuning=tun) for _ in range(args.warmup + args.steps)]
     torch.cuda.synchronize()
     log("contexts ready: %d (%.1f s)" % (len(runs), time.perf_counter() - t0))
@@ -314,7 +334,7 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
         "data": "synthetic (seeded mixtures, see datagen)",
         "config": {"workload": "C4 batched, %d problems, N~U{2000..200000}, D in {16,32,64}, K in {16,64,256}, "
                                "G=ceil(K/10)" % len(probs), "problems": len(probs), "sum_n": ntot,
-                   "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids"},
+                   "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids", "tuning": TUNING},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp32_lloyd": baseline,

@@ -160,6 +160,17 @@ int32_t kp_iterations(const kp_ctx *ctx);
  * no-op. */
 kp_status kp_destroy(kp_ctx *ctx);
 
+/* Autotuner of the launch shapes (the batched form picks its tiles and
+ * workgroups per problem from it).  Runs `iters` iterations (>= 2) of the
+ * problems from their initial centroids under each candidate tuning --
+ * centroid chunks in flight {1, 3} x workgroups per CU {8, 16, 32} -- in the
+ * caller's workspace (kp_workspace_bytes of the same problems), timing each
+ * run with HIP events on `stream`, and writes the fastest to *best_host
+ * (use_graph 1, timing 0).  Synchronises `stream`; leaves no ctx behind.
+ * The workspace contents are undefined afterwards. */
+kp_status kp_autotune(const kp_problem *problems_host, int32_t count, void *workspace_dev,
+                      size_t workspace_bytes, void *stream, int32_t iters, kp_tuning *best_host);
+
 /* Static description of a status code. */
 const char *kp_strerror(kp_status status);
 

@@ -10,6 +10,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/kp.h"
@@ -296,7 +297,7 @@ struct kp_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<kp::ProbDev> P;
     kp::Batch batch;                           // count > 1: batched launches
-    kp::LaunchCfg cfg{4, 2048, 1};
+    kp::LaunchCfg cfg{4, 4096, 1};
     int use_graph = 1;
     int iters = 0;
     bool poisoned = false;
@@ -772,6 +773,55 @@ kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out, int32_t cap, int32_t *
 }
 
 int32_t kp_iterations(const kp_ctx *ctx) { return ctx ? ctx->iters : -1; }
+
+kp_status kp_autotune(const kp_problem *problems, int32_t count, void *workspace, size_t ws_bytes, void *stream,
+                      int32_t iters, kp_tuning *best)
+{
+    if (!best || iters < 2) {
+        set_error("NULL best or iters=%d < 2", iters);
+        return KP_ERR_INVALID;
+    }
+    if (!validate(problems, count, nullptr)) return KP_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    kp_ctx *ctx = nullptr;   // for KP_HIP
+    KP_HIP(hipEventCreate(&e0));
+    std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g0(e0, hipEventDestroy);
+    KP_HIP(hipEventCreate(&e1));
+    std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(e1, hipEventDestroy);
+    static const int depths[2] = {1, 3}, bpcs[3] = {8, 16, 32};
+    float best_ms = -1.f;
+    kp_tuning cur{};
+    for (int di = 0; di < 2; ++di)
+        for (int bi = 0; bi < 3; ++bi) {
+            kp_tuning t{};
+            t.chunk_depth = depths[di];
+            t.blocks_per_cu = bpcs[bi];
+            t.use_graph = 1;
+            kp_ctx *c = nullptr;
+            kp_status st = kp_init(&c, problems, count, workspace, ws_bytes, stream, &t);
+            if (st != KP_OK) return st;
+            // the first call runs the dense iteration and captures the graph;
+            // the timed call replays filtered iterations only
+            st = kp_iterate(c, 1);
+            if (st == KP_OK && hipEventRecord(e0, s) != hipSuccess) st = KP_ERR_HIP;
+            if (st == KP_OK) st = kp_iterate(c, iters - 1);
+            if (st == KP_OK && hipEventRecord(e1, s) != hipSuccess) st = KP_ERR_HIP;
+            float ms = 0.f;
+            if (st == KP_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = KP_ERR_HIP;
+            const kp_status sd = kp_destroy(c);
+            if (st != KP_OK) return st;
+            if (sd != KP_OK) return sd;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                cur = t;
+            }
+        }
+    *best = cur;
+    g_last_error.clear();
+    return KP_OK;
+}
 
 kp_status kp_destroy(kp_ctx *ctx)
 {

@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
-           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_strerror", "kp_last_error")
+           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_strerror", "kp_last_error")
 
 
 class kp_problem(ctypes.Structure):
@@ -78,6 +78,8 @@ def lib():
         L.kp_iterations.restype = ctypes.c_int32
         L.kp_destroy.argtypes = [vp]
         L.kp_destroy.restype = ctypes.c_int
+        L.kp_autotune.argtypes = [P(kp_problem), ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_int32, P(kp_tuning)]
+        L.kp_autotune.restype = ctypes.c_int
         L.kp_strerror.argtypes = [ctypes.c_int]
         L.kp_strerror.restype = ctypes.c_char_p
         L.kp_last_error.argtypes = []
@@ -147,6 +149,15 @@ def kp_destroy(ctx):
     _check(lib().kp_destroy(ctypes.c_void_p(ctx)), "kp_destroy")
 
 
+def kp_autotune(problems, workspace_ptr, workspace_bytes, stream=0, iters=4):
+    """Returns the fastest kp_tuning for these problems (see kp.h)."""
+    arr, n = _probs(problems)
+    best = kp_tuning()
+    _check(lib().kp_autotune(arr, n, ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream),
+                             int(iters), ctypes.byref(best)), "kp_autotune")
+    return best
+
+
 def kp_strerror(status):
     return lib().kp_strerror(int(status)).decode()
 
@@ -196,6 +207,25 @@ class KMeans:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = kp_init(descs, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream, tuning)
+
+    @staticmethod
+    def autotune(problems, iters=4):
+        """Tuning for these problems from kp_autotune (same problem tuples as the constructor)."""
+        import torch
+        descs, keep = [], []
+        for pr in problems:
+            X, C0, g = pr[0], pr[1], int(pr[2])
+            prec = PRECISIONS[pr[3]] if len(pr) > 3 else KP_PREC_FP32
+            seed = int(pr[4]) if len(pr) > 4 else 0
+            keep += [X, C0]
+            descs.append(kp_problem(n=X.shape[0], d=X.shape[1], k=C0.shape[0], g=g, precision=prec,
+                                    points_dev=X.data_ptr(), init_centroids_dev=C0.data_ptr(), seed=seed))
+        nbytes = kp_workspace_bytes(descs)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=problems[0][0].device)
+        stream = torch.cuda.current_stream(problems[0][0].device).cuda_stream
+        best = kp_autotune(descs, ws.data_ptr(), nbytes, stream, iters)
+        del ws
+        return best
 
     def iterate(self, iters=1):
         kp_iterate(self.ctx, iters)

@@ -105,3 +105,12 @@ def test_strerror():
     for s in range(6):
         assert kp.kp_strerror(s)
     assert kp.kp_strerror(99) == "unknown status"
+
+
+def test_autotune_argument_errors():
+    lib = kp.lib()
+    arr, n = kp._probs([_prob()])
+    best = kp.kp_tuning()
+    assert lib.kp_autotune(arr, n, None, 0, None, 4, None) == kp.KP_ERR_INVALID      # no output
+    assert lib.kp_autotune(arr, n, None, 0, None, 1, ctypes.byref(best)) == kp.KP_ERR_INVALID   # iters < 2
+    assert lib.kp_autotune(arr, 0, None, 0, None, 4, ctypes.byref(best)) == kp.KP_ERR_INVALID   # no problems

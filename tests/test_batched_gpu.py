@@ -58,3 +58,15 @@ def test_batch_graph_and_timing():
     for i in range(len(probs)):
         assert len(km.stats(i)) == 4
     km.close()
+
+
+def test_autotune_then_run():
+    """kp_autotune picks one of its candidates; the batch then runs with it and matches the oracle."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    probs = [_problem(700 + i, 3_000 + 1_000 * i, 16 * (1 + i % 3), 64, "bf16") for i in range(6)]
+    dev = [(torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda(), g, prec) for X, C0, g, prec in probs]
+    print("CASE autotune", flush=True)
+    best = KMeans.autotune(dev, iters=3)
+    assert best.chunk_depth in (1, 3) and best.blocks_per_cu in (8, 16, 32) and best.use_graph == 1
+    run_steplocked_batch(probs, 5, tuning=best)
