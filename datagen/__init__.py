@@ -153,8 +153,13 @@ def kmeanspp(rng, X, k, *, sample=None):
     if k > m:
         raise ValueError("k-means++ needs at least k sample points")
     C = np.empty((k, S.shape[1]), dtype=np.float64)
+    sn = (S * S).sum(axis=1)
+
+    def d2(c):   # squared distances of the sample to one center (clamped at 0)
+        return np.maximum(sn - 2.0 * (S @ c) + c @ c, 0.0)
+
     C[0] = S[rng.integers(m)]
-    best = ((S - C[0]) ** 2).sum(axis=1)
+    best = d2(C[0])
     for j in range(1, k):
         tot = best.sum()
         if tot <= 0.0:
@@ -163,7 +168,7 @@ def kmeanspp(rng, X, k, *, sample=None):
             u = rng.random() * tot
             c = int(np.searchsorted(np.cumsum(best), u, side="right"))
             C[j] = S[min(c, m - 1)]
-        np.minimum(best, ((S - C[j]) ** 2).sum(axis=1), out=best)
+        np.minimum(best, d2(C[j]), out=best)
     return C.astype(np.float32)
 
 

@@ -43,6 +43,16 @@ def test_c3_shape_bf16():
     assert sum(s["rechecks"] for s in st) >= 0
 
 
+def test_c5_shape_bf16():
+    """The large workload's shape (D=256, K=4096, G=410, Student-t mixture with
+    Zipf sizes) at a reduced N: eight 32-wide steps per MFMA tile, seven
+    rounds of the group filter."""
+    P = datagen.make_config(5, n=40_000)
+    _print_case("c5-reduced", n=P.n)
+    r = run_steplocked(P.X, P.C0, P.g, "bf16", 4)
+    assert r["stats"][-1]["pairs"] < P.n * P.g
+
+
 @pytest.mark.parametrize("d", [16, 32, 64])
 def test_bf16_small_dims(d):
     rng = np.random.default_rng(d)
