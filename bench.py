@@ -179,6 +179,11 @@ def main():
     # the dominant kernel stage (the whole-replay entry is a sum of stages)
     dom = max((nm for nm in agg if nm != "filtered_iter"), key=lambda nm: agg[nm]["ms"])
     roofline = roofline_of(dom, agg[dom], P, st)
+    others = {}
+    for nm in ("assign_dense", "group_filter", "bound_filter"):
+        if nm in agg and nm != dom:
+            r = roofline_of(nm, agg[nm], P, st)
+            others[nm] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
     del runs
     torch.cuda.empty_cache()
 
@@ -198,6 +203,7 @@ def main():
                    "precision": "bf16 MFMA + fp32 recheck + fp64 centroids" if prec == "bf16"
                    else "fp32 direct + fp64 centroids", "tuning": TUNING},
         "roofline": roofline,
+        "stage_rooflines": others,
         "cpu_baseline": cpu,
         "plain_fp32_lloyd": baseline,
         "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
@@ -210,11 +216,20 @@ def main():
 
 def assign_bytes(P, s):
     """Algorithmic HBM bytes of one filtered assignment launch (BF16 mode): per
-    entry of L1 its FP32 row, its bound row, the sorted entry, the new state,
-    the update entries and the flag; per visited (point, group) pair the new
-    bound; per uncertain point its recheck record."""
-    per_point = 4 * P.d + 4 * P.g + 16 + 16 + 12 + 4
-    return s["point_filter_fail"] * per_point + s["pairs"] * 4 + s["rechecks"] * 16
+    entry of L1 its FP32 row, the sorted entry, its norm, its open-group mask
+    words and closed-group bound (from the group filter), the new state and the
+    update entries; per visited (point, group) pair the new bound; per
+    uncertain point its recheck record and list entry."""
+    per_point = 4 * P.d + 16 + 4 + 4 * ((P.g + 31) // 32) + 4 + 16 + 12
+    return s["point_filter_fail"] * per_point + s["pairs"] * 4 + s["rechecks"] * 20
+
+
+def gfilter_bytes(P, s):
+    """Algorithmic HBM bytes of one group-filter launch: per entry of L1 the
+    sorted entry, the point's bound row (g FP32, padded to 4), and the written
+    mask words and closed-group bound."""
+    gs = (P.g + 3) // 4 * 4
+    return s["point_filter_fail"] * (16 + 4 * gs + 4 * ((P.g + 31) // 32) + 4)
 
 
 def traffic_of(kernel, workload):
@@ -336,6 +351,7 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
                                "G=ceil(K/10)" % len(probs), "problems": len(probs), "sum_n": ntot,
                    "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids", "tuning": TUNING},
         "roofline": roofline,
+        "stage_rooflines": others,
         "cpu_baseline": cpu,
         "plain_fp32_lloyd": baseline,
         "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
@@ -352,10 +368,18 @@ def roofline_of(stage, a, P, st):
         filt = [s for s in st if not s["dense"]]
         byts = sum(assign_bytes(P, s) for s in filt) / max(len(filt), 1)
         ach = byts / (ms_per_launch * 1e-3) / 1e9
-        return dict(kernel="k_blk64 (filtered iteration: group filter + BF16x3 survivor distances)", bound="hbm",
+        return dict(kernel="k_blk64 (filtered iteration: BF16x3 distances of the open groups)", bound="hbm",
                     achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     traffic=traffic_of("k_blk64_filtered", wl),
-                    work_per_launch="%.4g B (per L1 entry 4d+4g+60 B, per pair 4 B, per recheck 16 B)" % byts,
+                    work_per_launch="%.4g B (per L1 entry 4d+52+4*ceil(g/32) B, per pair 4 B, per recheck 20 B)"
+                    % byts, ms_per_launch=ms_per_launch)
+    if stage == "group_filter":
+        filt = [s for s in st if not s["dense"]]
+        byts = sum(gfilter_bytes(P, s) for s in filt) / max(len(filt), 1)
+        ach = byts / (ms_per_launch * 1e-3) / 1e9
+        return dict(kernel="k_gfilter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=traffic_of("k_gfilter", wl),
+                    work_per_launch="%.4g B (per L1 entry 16+4*gs+4*ceil(g/32)+4 B)" % byts,
                     ms_per_launch=ms_per_launch)
     if stage == "assign_dense":
         flops = 2.0 * P.n * P.k * P.d

@@ -103,9 +103,9 @@ typedef struct {
 
 /* Accumulated GPU time of one stage (kp_stage_times). */
 typedef struct {
-    char name[24];                 /* "assign_dense", "bound_filter", "l1_sort", "assign",
-                                      "recheck", "update", "centroids", "begin",
-                                      "filtered_iter" */
+    char name[24];                 /* "assign_dense", "bound_filter", "l1_sort",
+                                      "group_filter" (BF16 mode), "assign", "recheck",
+                                      "update", "centroids", "begin", "filtered_iter" */
     double ms;                     /* total milliseconds between the stage's events */
     int64_t launches;              /* number of timed launches */
 } kp_stage_time;

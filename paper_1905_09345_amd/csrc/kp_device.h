@@ -35,6 +35,7 @@ constexpr int STATS_CAP = 1024;       // per-iteration stats ring
 constexpr int NCTR = 8;               // per-iteration counters
 constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
 constexpr int SINK_SLOTS = 1024;      // 64-byte slots taking the stores of lanes with nothing to write
+constexpr int GMAX_BF16 = 1024;       // largest g of the BF16 mode (group tables kept in LDS)
 
 // counters (unsigned long long) per problem
 enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6 };
@@ -75,6 +76,8 @@ struct ProbDev {
     int *L1s;                 // the same ids sorted by assigned slot
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int *L3;                  // positions of the points whose BF16 decision is uncertain
+    unsigned *vmask;          // per position: open groups of the group filter, ceil(g/32) words
+    float *minnc;             // per position: smallest bound of the closed groups (rounded down)
     int4 *tlist;              // per tile of sorted L1: (group, point mask lo, hi, 0), g entries per tile
     int *tcnt;                // entries used per tile
     float4 *ps4;              // per position: ub, min closed-group bound, U* of an uncertain point

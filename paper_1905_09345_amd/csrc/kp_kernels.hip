@@ -739,19 +739,21 @@ __device__ __forceinline__ Key2 key2_merge(Key2 a, Key2 b)
     r.k2 = min(max(a.k1, b.k1), min(a.k2, b.k2));
     return r;
 }
-__device__ __forceinline__ Key2 key2_xor(Key2 a, int mask)
+// Merge with the lane l ^ 16 (rows) or l ^ 32 (halves): with both operands
+// equal, v_permlane16_swap / v_permlane32_swap leave in every lane its own
+// value and its partner's, in an order that does not matter to the
+// symmetric merge.  All 64 lanes must be active.
+__device__ __forceinline__ Key2 key2_fold16(Key2 t)
 {
-    Key2 r;
-    r.k1 = (unsigned)__shfl_xor((int)a.k1, mask);
-    r.k2 = (unsigned)__shfl_xor((int)a.k2, mask);
-    return r;
+    const auto a = __builtin_amdgcn_permlane16_swap(t.k1, t.k1, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(t.k2, t.k2, false, false);
+    return key2_merge(Key2{a[0], b[0]}, Key2{a[1], b[1]});
 }
-__device__ __forceinline__ Key2 key2_swz16(Key2 a)   // lane l <-> lane l ^ 16 (within 32 lanes)
+__device__ __forceinline__ Key2 key2_fold32(Key2 t)
 {
-    Key2 r;
-    r.k1 = (unsigned)__builtin_amdgcn_ds_swizzle((int)a.k1, 0x401F);
-    r.k2 = (unsigned)__builtin_amdgcn_ds_swizzle((int)a.k2, 0x401F);
-    return r;
+    const auto a = __builtin_amdgcn_permlane32_swap(t.k1, t.k1, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(t.k2, t.k2, false, false);
+    return key2_merge(Key2{a[0], b[0]}, Key2{a[1], b[1]});
 }
 __device__ __forceinline__ float key_value(unsigned k) { return __uint_as_float(k & ~15u); }
 
@@ -770,8 +772,7 @@ __device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lh, con
     }
     Key2 p = {min(k[0], k[1]), max(k[0], k[1])}, q = {min(k[2], k[3]), max(k[2], k[3])};
     Key2 t = key2_merge(p, q);
-    t = key2_merge(t, key2_swz16(t));
-    return key2_merge(t, key2_xor(t, 32));
+    return key2_fold32(key2_fold16(t));
 }
 
 // Bounds on the true distance from an estimate v of its square with
@@ -1021,6 +1022,82 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void kb_group_test(const ProbDev *
 }
 
 
+// ======================================= group-level filter (BF16 mode)
+// One wave per 16 positions of the sorted L1, four per workgroup.  Each
+// point's group bounds are tested against its upper bound brought to this
+// iteration: lane (point p, quad q) reads groups g0 + 16 q .. +15 of p's bound
+// row as one 64-byte run.  The point's own group always stays open.  Writes,
+// per position, the open groups as a bit mask (ceil(g / 32) words) and the
+// smallest bound of the closed groups (rounded down).
+__device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, const int nblk_)
+{
+    __shared__ float gsu[GMAX_BF16];
+    for (int i = threadIdx.x; i < P.g; i += blockDim.x) gsu[i] = P.Sgu[i];
+    for (int i = P.g + threadIdx.x; i < ((P.g + 3) & ~3); i += blockDim.x) gsu[i] = 0.f;   // float4 tail
+    __syncthreads();
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
+    const long long count = list_len(P, CTR_L1);
+    const long long ntiles = (count + 15) / 16;
+    const int mw = (P.g + 31) / 32;
+    for (long long tl = (long long)bid_ * 4 + wv; tl < ntiles; tl += (long long)nblk_ * 4) {
+        const long long pos = tl * 16 + pt;
+        const bool in = pos < count;
+        int pid = 0, ga = -1;
+        float ubt = KP_INF;
+        if (in) {
+            const int4 e = P.L1x[pos];
+            pid = clamp_pid(P, e.x);
+            ubt = __int_as_float(e.z);
+            ga = min(max(e.w, 0), P.g - 1);
+        }
+        const float *lbrow = P.lb + (size_t)pid * P.gs;
+        float cm = KP_INF;
+        for (int g0 = 0; g0 < P.g; g0 += WAVE) {
+            const int gq = g0 + 16 * quad;
+            float v[16], sg[16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gi = gq + 4 * i;   // gs and the LDS table are padded to 4
+                const bool ok = in && gi < P.g;
+                const float4 v4 = ok ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 s4 = ok ? *(const float4 *)(gsu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[4 * i] = v4.x;
+                v[4 * i + 1] = v4.y;
+                v[4 * i + 2] = v4.z;
+                v[4 * i + 3] = v4.w;
+                sg[4 * i] = s4.x;
+                sg[4 * i + 1] = s4.y;
+                sg[4 * i + 2] = s4.z;
+                sg[4 * i + 3] = s4.w;
+            }
+            unsigned bits = 0u;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int g = gq + j;
+                const bool cand = in && g < P.g;
+                const bool open = cand && (g == ga || group_open(ubt, sg[j], v[j]));
+                bits |= open ? 1u << j : 0u;
+                cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
+            }
+            // word g0/32 + q/2: quad 2i gives its low half, quad 2i+1 its high half
+            const unsigned hi = (unsigned)__shfl_xor((int)bits, 16);
+            const int w = g0 / 32 + (quad >> 1);
+            if (in && (quad & 1) == 0 && w < mw) P.vmask[(size_t)pos * mw + w] = bits | (hi << 16);
+        }
+        cm = fminf(cm, __shfl_xor(cm, 16));
+        cm = fminf(cm, __shfl_xor(cm, 32));
+        if (in && quad == 0) P.minnc[pos] = f_dn(cm);
+    }
+}
+__global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter(P, (int)blockIdx.x, (int)gridDim.x); }
+__global__ __launch_bounds__(256) void kb_gfilter(const ProbDev *__restrict__ probs, const int *__restrict__ tab,
+                                                  int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_gfilter(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+
 // ================================================== distance kernels (phase 2)
 template <int DMAX>
 __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, const int nblk_)
@@ -1104,13 +1181,18 @@ struct ChunkStage {
     bf16x8 a[2 * KS][WAVE];
     float4 cn[4];
 };
-constexpr int GMAX_BF16 = 1024;      // largest g of the BF16 mode (group tables kept in LDS)
+// One visit of a tile: a group and the four waves' 16-bit point masks.
+struct Visit {
+    int g;
+    unsigned short m[4];
+};
 template <int KS>
 struct BlockLds {
     ChunkStage<KS> st[2];
-    unsigned short mask[4][WAVE];   // filter round: wave w's point mask of group g0 + t
+    Visit vis[GMAX_BF16];           // the tile's visits (filtered iterations)
+    unsigned short mask[4][WAVE];   // while listing: wave w's point mask of group g0 + t
     int gst[GMAX_BF16], gsz[GMAX_BF16];
-    float gsd[GMAX_BF16], gsu[GMAX_BF16];   // Sg rounded down / up
+    float gsd[GMAX_BF16];           // Sg rounded down
 };
 template <int KS>
 struct StageRegs {
@@ -1163,79 +1245,88 @@ __device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<
     return chunk_keys(hh, lh, hl, S.cn[lane >> 4], xnp);
 }
 
-// Chunks of the visits named by the set bits of vm (workgroup-uniform);
-// lane j holds visit j's first slot ts0 and size tns (>= 1).
+// Chunks of a tile's visits 0 .. nv-1 (workgroup-uniform); src(k, g, m, s0,
+// ns, sgd) gives visit k's group, this wave's point mask, first slot, size
+// (>= 1) and rounded-down drift sum.
 struct ChunkSeq {
-    unsigned long long rest;
-    int j, c0, s0, ns;
+    int k, c0, s0, ns;
     bool valid;
 };
-__device__ __forceinline__ void seq_take(ChunkSeq &q, int ts0, int tns)
+template <class Src>
+__device__ __forceinline__ void seq_take(ChunkSeq &q, Src &src)
 {
-    q.j = __ffsll((long long)q.rest) - 1;
-    q.rest &= q.rest - 1ull;
-    q.s0 = __builtin_amdgcn_readlane(ts0, q.j);
-    q.ns = __builtin_amdgcn_readlane(tns, q.j);
+    int g, s0, ns;
+    unsigned m;
+    float sgd;
+    src(q.k, g, m, s0, ns, sgd);
+    q.s0 = s0;
+    q.ns = ns;
     q.c0 = 0;
 }
-__device__ __forceinline__ void seq_begin(ChunkSeq &q, unsigned long long vm, int ts0, int tns)
+template <class Src>
+__device__ __forceinline__ void seq_begin(ChunkSeq &q, int nv, Src &src)
 {
-    q.rest = vm;
-    q.valid = vm != 0ull;
-    q.j = q.c0 = q.s0 = q.ns = 0;
-    if (q.valid) seq_take(q, ts0, tns);
+    q.k = 0;
+    q.c0 = q.s0 = q.ns = 0;
+    q.valid = nv > 0;
+    if (q.valid) seq_take(q, src);
 }
-__device__ __forceinline__ void seq_next(ChunkSeq &q, int ts0, int tns)
+template <class Src>
+__device__ __forceinline__ void seq_next(ChunkSeq &q, int nv, Src &src)
 {
     q.c0 += CHUNK;
     if (q.c0 >= q.ns) {
-        if (q.rest) seq_take(q, ts0, tns);
+        if (++q.k < nv) seq_take(q, src);
         else q.valid = false;
     }
 }
-
 // Advance a load cursor; past the last chunk it stays on it.
-__device__ __forceinline__ void seq_next_load(ChunkSeq &q, int ts0, int tns)
+template <class Src>
+__device__ __forceinline__ void seq_next_load(ChunkSeq &q, int nv, Src &src)
 {
-    if (q.c0 + CHUNK < q.ns) q.c0 += CHUNK;
-    else if (q.rest) seq_take(q, ts0, tns);
+    if (q.c0 + CHUNK < q.ns) {
+        q.c0 += CHUNK;
+    } else if (q.k + 1 < nv) {
+        ++q.k;
+        seq_take(q, src);
+    }
 }
 
-// The workgroup's visits named by vm: lane j holds group tg, this wave's
-// 16-bit point mask tmw, first slot ts0, size tns and the group's rounded-
-// down drift sum tsgd.  fold(g, m, slot0, nreal, first, sgd, key2) receives
-// each chunk's two smallest keys per point of this wave; a wave with no
-// point in the visit skips the chunk and calls skip() instead, which issues
-// the same memory operations.  Every thread of the workgroup calls it.
+// The workgroup's visits 0 .. nv-1 from src.  fold(g, m, slot0, nreal,
+// first, sgd, key2) receives each chunk's two smallest keys per point of this
+// wave; a wave with no point in the visit skips the chunk and calls skip()
+// instead, which issues the same memory operations.  Every thread of the
+// workgroup calls it.
 //
 // DEPTH chunks are in flight: chunk i is read from LDS while chunks
 // i+1 .. i+DEPTH-1 are loading into registers; after chunk i the loads of
 // chunk i+DEPTH are issued and chunk i+1 goes to LDS.  With DEPTH = 1 the
 // next chunk's loads are issued before the current chunk's work.
-template <int KS, int DEPTH, class Fold, class Skip>
-__device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, unsigned long long vm, int tg,
-                                             unsigned tmw, int ts0, int tns, float tsgd, const PtFrag<KS> &b,
-                                             float xnp, Fold fold, Skip skip)
+template <int KS, int DEPTH, class Src, class Fold, class Skip>
+__device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, int nv, Src src,
+                                             const PtFrag<KS> &b, float xnp, Fold fold, Skip skip)
 {
-    if (vm == 0ull) return;
+    if (nv <= 0) return;
     ChunkSeq cp, ld;
-    seq_begin(cp, vm, ts0, tns);
+    seq_begin(cp, nv, src);
     ld = cp;
     StageRegs<KS> R[DEPTH];
 #pragma unroll
     for (int k = 0; k < DEPTH; ++k) {
         stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
-        seq_next_load(ld, ts0, tns);
+        seq_next_load(ld, nv, src);
     }
     stage_store<KS>(L.st[0], R[0]);
     __syncthreads();
     int buf = 0;
     auto work = [&]() {
-        const unsigned m = (unsigned)__builtin_amdgcn_readlane((int)tmw, cp.j);
+        int g, s0, ns;
+        unsigned m;
+        float sgd;
+        src(cp.k, g, m, s0, ns, sgd);
         if (m) {
             const Key2 t = chunk_lds<KS>(L.st[buf], b, xnp);
-            fold(__builtin_amdgcn_readlane(tg, cp.j), m, cp.s0 + cp.c0, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0,
-                 __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tsgd), cp.j)), t);
+            fold(g, m, cp.s0 + cp.c0, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0, sgd, t);
         } else {
             skip();
         }
@@ -1245,16 +1336,16 @@ __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, 
         for (int k = 0; k < DEPTH; ++k) {
             if (DEPTH == 1) {
                 stage_load<KS>(P, ld.s0 + ld.c0, R[0]);
-                seq_next_load(ld, ts0, tns);
+                seq_next_load(ld, nv, src);
                 work();
             } else {
                 work();
                 stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
-                seq_next_load(ld, ts0, tns);
+                seq_next_load(ld, nv, src);
             }
             stage_store<KS>(L.st[buf ^ 1], R[(k + 1) % DEPTH]);
             __syncthreads();
-            seq_next(cp, ts0, tns);
+            seq_next(cp, nv, src);
             buf ^= 1;
             if (!cp.valid) return;
         }
@@ -1263,13 +1354,10 @@ __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, 
 
 // BF16 mode, one workgroup per tile of 64 positions.  DENSE (iteration 1):
 // the positions are the points and every group is visited.  Otherwise the
-// positions are entries of the sorted L1: while its row loads, each point's
-// upper bound is tightened to the FP32 distance to its assigned centroid;
-// then each wave tests its points' group bounds against the tightened
-// bounds (lanes over groups; the own group stays open) and the workgroup
-// visits every group open for some point of the tile.  Per point: the
-// decision under the error bound, or the flag that sends it to the FP32
-// recheck.
+// positions are entries of the sorted L1 and the workgroup visits every
+// group that the group filter left open for some point of the tile (the
+// points' own groups always are).  Per point: the decision under the error
+// bound, or the entry that sends it to the FP32 recheck.
 template <int KS, bool DENSE, int DEPTH>
 __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const int nblk_)
 {
@@ -1284,9 +1372,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         L.gst[i] = P.gstart[i];
         L.gsz[i] = P.gsize[i];
         L.gsd[i] = P.Sgd[i];
-        L.gsu[i] = P.Sgu[i];
     }
-    for (int i = P.g + threadIdx.x; i < ((P.g + 3) & ~3); i += blockDim.x) L.gsu[i] = 0.f;   // float4 tail
     __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
     // sorted entry of this lane's position in the next tile, loaded one tile ahead
@@ -1299,8 +1385,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const long long idx = tl * 64 + 16 * wv + pt;
         const bool in = idx < count;
         int pid = in && DENSE ? (int)idx : 0;
-        int a = -1, ga = -1;
-        float ubt = KP_INF;
+        int a = -1;
         if (!DENSE) {
             const int4 e = nxt;
             const long long inext = idx + 64ll * nblk_;
@@ -1308,31 +1393,33 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             if (in) {
                 pid = clamp_pid(P, e.x);
                 a = clamp_slot(P, e.y);
-                ubt = __int_as_float(e.z);
-                ga = min(max(e.w, 0), P.g - 1);
             }
         }
         const float xnp = in ? P.xn[pid] : 0.f;
         const double eta = mfma_eta3(xnp, bmax, P.ldb);
         const float eta_f = d2f_up(eta);
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
-        PtFrag<KS> b;
-        float ubn = KP_INF;
-        if (DENSE) {
-            load_points16<KS, false>(P, pid, in, nullptr, b);
-        } else {
-            // the upper bound tightened to the FP32 distance to the assigned centroid
-            float d2a = load_points16<KS, true>(P, pid, in, P.c32 + (size_t)(a < 0 ? 0 : a) * P.ldc, b);
-            d2a += __shfl_xor(d2a, 16);
-            d2a += __shfl_xor(d2a, 32);
-            ubn = in ? fminf(ubt, dist_hi(d2a, eps2_tile(KS))) : KP_INF;
+        // open-group words of the first two rounds and the closed-group bound,
+        // written by the group filter; issued together with the point rows
+        const int mw = (P.g + 31) / 32;
+        const unsigned *mrow = P.vmask + (size_t)(DENSE ? 0 : idx) * mw;
+        unsigned wr0 = 0u, wr1 = 0u;
+        float minnc = KP_INF;
+        if (!DENSE && in) {
+            if ((quad >> 1) < mw) wr0 = mrow[quad >> 1];
+            if (2 + (quad >> 1) < mw) wr1 = mrow[2 + (quad >> 1)];
+            minnc = P.minnc[idx];
         }
+        PtFrag<KS> b;
+        load_points16<KS, false>(P, pid, in, nullptr, b);
         Run r;
         run_init(r);
         float gmin = KP_INF;   // running minimum of the group being visited
+        unsigned t_pairs = 0u, t_dist = 0u;   // this tile's counts (< 2^32)
         auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
-            n_pairs += first ? (unsigned long long)__popc(m) : 0ull;
-            n_dist += (unsigned long long)__popc(m) * (unsigned long long)nreal;
+            const unsigned pm = (unsigned)__popc(m);
+            t_pairs += first ? pm : 0u;
+            t_dist += pm * (unsigned)nreal;
             const bool mine = (m >> pt) & 1u;
             const float m1 = key_value(kk.k1);
             const float gprev = first ? KP_INF : gmin;
@@ -1345,68 +1432,64 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             *dst = lbv;
         };
         auto skip = [&]() { *sink = 0.f; };
-        float minnc = KP_INF;
         if (DENSE) {
-            for (int g0 = 0; g0 < P.g; g0 += WAVE) {
-                const int g = g0 + lane;
-                const bool gv = g < P.g;
-                const int s0 = gv ? L.gst[g] : 0, ns = gv ? L.gsz[g] : 0;
-                const float sgd = gv ? L.gsd[g] : 0.f;
-                const unsigned long long vm = __ballot(gv && ns > 0);
-                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
-                block_visits<KS, DEPTH>(P, L, vm, g, inm, s0, ns, sgd, b, xnp, fold, skip);
-            }
+            // every group, in order
+            auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
+                g = k;
+                m = inm;
+                s0 = L.gst[k];
+                ns = L.gsz[k];
+                sgd = L.gsd[k];
+            };
+            n_visits += wv == 0 ? (unsigned long long)P.g : 0ull;
+            block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
         } else {
-            // group-level filter, 64 groups per round: lane (point p, quad q)
-            // tests groups g0 + 16 q .. +15 of point p (one 64-byte run of its
-            // bound row); lane t then holds the visit of group g0 + t
-            const float *lbrow = P.lb + (size_t)pid * P.gs;
+            // list the groups the group filter left open for some point of the
+            // tile, 64 groups per round: lane (point p, quad q) holds groups
+            // g0 + 16 q .. +15 of point p; lane t then holds group g0 + t
+            int nv = 0;
             for (int g0 = 0; g0 < P.g; g0 += WAVE) {
-                const int gq = g0 + 16 * quad;
-                float v[16], sg[16];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int gi = gq + 4 * i;   // gs and the LDS table are padded to 4
-                    const bool ok = in && gi < P.g;
-                    const float4 v4 = ok ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
-                    const float4 s4 = ok ? *(const float4 *)(L.gsu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
-                    v[4 * i] = v4.x;
-                    v[4 * i + 1] = v4.y;
-                    v[4 * i + 2] = v4.z;
-                    v[4 * i + 3] = v4.w;
-                    sg[4 * i] = s4.x;
-                    sg[4 * i + 1] = s4.y;
-                    sg[4 * i + 2] = s4.z;
-                    sg[4 * i + 3] = s4.w;
-                }
-                float cm = KP_INF;
+                const int w = g0 / 32 + (quad >> 1);
+                unsigned word = g0 == 0 ? wr0 : (g0 == WAVE ? wr1 : 0u);
+                if (g0 >= 2 * WAVE && in && w < mw) word = mrow[w];
+                const unsigned bits = (word >> (16 * (quad & 1))) & 0xFFFFu;
                 unsigned long long mine = 0ull;
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int g = gq + j;
-                    // the point's own group is always visited
-                    const bool cand = in && g < P.g;
-                    const bool open = cand && (g == ga || group_open(ubn, sg[j], v[j]));
-                    cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
-                    const unsigned long long bj = __ballot(open);
+                    const unsigned long long bj = __ballot((bits >> j) & 1u);
                     if ((lane & 15) == j) mine = bj;
                 }
-                cm = fminf(cm, __shfl_xor(cm, 16));
-                minnc = fminf(minnc, f_dn(fminf(cm, __shfl_xor(cm, 32))));
-                const unsigned tm = (unsigned)(mine >> (16 * quad)) & 0xFFFFu;
-                L.mask[wv][lane] = (unsigned short)tm;
+                L.mask[wv][lane] = (unsigned short)((mine >> (16 * quad)) & 0xFFFFu);
                 __syncthreads();
-                const unsigned any = (unsigned)L.mask[0][lane] | L.mask[1][lane] | L.mask[2][lane] | L.mask[3][lane];
-                __syncthreads();   // the masks are rewritten by the next round
-                const int tgr = g0 + lane;
-                const bool gv = tgr < P.g;
-                const int s0 = gv ? L.gst[tgr] : 0, ns = gv ? L.gsz[tgr] : 0;
-                const float sgd = gv ? L.gsd[tgr] : 0.f;
-                const unsigned long long vm = __ballot(gv && any != 0u && ns > 0);
-                n_visits += wv == 0 ? (unsigned long long)__popcll(vm) : 0ull;
-                block_visits<KS, DEPTH>(P, L, vm, tgr, tm, s0, ns, sgd, b, xnp, fold, skip);
+                const unsigned short m0 = L.mask[0][lane], m1 = L.mask[1][lane], m2 = L.mask[2][lane],
+                                     m3 = L.mask[3][lane];
+                const int g = g0 + lane;
+                const bool open = g < P.g && (m0 | m1 | m2 | m3) != 0 && L.gsz[min(g, P.g - 1)] > 0;
+                const unsigned long long om = __ballot(open);
+                if (wv == 0 && open) {
+                    Visit &v = L.vis[nv + __popcll(om & ((1ull << lane) - 1ull))];
+                    v.g = g;
+                    v.m[0] = m0;
+                    v.m[1] = m1;
+                    v.m[2] = m2;
+                    v.m[3] = m3;
+                }
+                nv += __popcll(om);
+                __syncthreads();   // the masks are rewritten by the next round; the list is complete after the last
             }
+            auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
+                const Visit &v = L.vis[k];
+                g = v.g;
+                m = v.m[wv];
+                s0 = L.gst[g];
+                ns = L.gsz[g];
+                sgd = L.gsd[g];
+            };
+            n_visits += wv == 0 ? (unsigned long long)nv : 0ull;
+            block_visits<KS, DEPTH>(P, L, nv, src, b, xnp, fold, skip);
         }
+        n_pairs += t_pairs;
+        n_dist += t_dist;
         bool moved = false, amb = false;
         const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
@@ -1984,8 +2067,8 @@ static void launch_centroid_rows(const ProbDev &P, hipStream_t s)
 
 const char *stage_name(Stage st)
 {
-    static const char *names[ST_COUNT] = {"begin", "bound_filter", "l1_sort", "assign_dense", "assign",
-                                          "recheck", "update", "centroids"};
+    static const char *names[ST_COUNT] = {"begin", "bound_filter", "l1_sort", "assign_dense", "group_filter",
+                                          "assign", "recheck", "update", "centroids"};
     return (st >= 0 && st < ST_COUNT) ? names[st] : "?";
 }
 
@@ -1998,6 +2081,7 @@ int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT])
     } else {
         out[n++] = ST_FILTER;
         out[n++] = ST_SORT;
+        if (P.prec) out[n++] = ST_GFILTER;
         out[n++] = ST_ASSIGN;
     }
     if (P.prec) out[n++] = ST_RECHECK;
@@ -2023,6 +2107,9 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
         break;
     }
     case ST_ASSIGN_DENSE: launch_dense(P, s, cfg); break;
+    case ST_GFILTER:
+        hipLaunchKernelGGL(k_gfilter, dim3(cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
+        break;
     case ST_ASSIGN: launch_survivors(P, s, cfg); break;
     case ST_RECHECK: {
         const int blocks = cap_grid((P.n + 31) / 32, cfg.grid_cap);
@@ -2095,6 +2182,7 @@ static int tab_blocks(int id, const ProbDev &P, const LaunchCfg &cfg, int cap)
     case TB_ONE: return 1;
     case TB_CENT: return cap_grid((P.kg + 3) / 4, 4096);
     case TB_GT: return f32 ? cap_grid(((n + 63) / 64 + GT_WAVES - 1) / GT_WAVES, cap) : 0;
+    case TB_GF: return f32 ? 0 : cap_grid(((n + 15) / 16 + 3) / 4, cap);
     case TB_HIST: return cap_grid((2 * n + 255) / 256, cap);
     case TB_SCATTER: return cap_grid((2 * n + 4095) / 4096, 1024);
     default: return 0;
@@ -2133,6 +2221,7 @@ int batch_stages(const std::vector<ProbDev> &hp, bool dense, Stage out[ST_COUNT]
     } else {
         out[n++] = ST_FILTER;
         out[n++] = ST_SORT;
+        if (any_bf16) out[n++] = ST_GFILTER;
         out[n++] = ST_ASSIGN;
     }
     if (any_bf16) out[n++] = ST_RECHECK;
@@ -2179,6 +2268,7 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
         if (cfg.depth == 1) batch_blk64<true, 1>(B, s);
         else batch_blk64<true, 3>(B, s);
         break;
+    case ST_GFILTER: KB_LAUNCH(TB_GF, kb_gfilter, 256); break;
     case ST_ASSIGN:
         KB_LAUNCH(TB_GT, kb_group_test, WAVE * GT_WAVES);
         KB_LAUNCH(TB_TILE_F32 + 0, kb_tile_f32<8>, wthreads);

@@ -15,7 +15,10 @@ struct LaunchCfg {
 // Per-point BF16 shadow and norms, initial centroid rows, drift rings at t=0.
 hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev);
 // Stages of one iteration, in launch order.
-enum Stage { ST_BEGIN = 0, ST_FILTER, ST_SORT, ST_ASSIGN_DENSE, ST_ASSIGN, ST_RECHECK, ST_UPDATE, ST_CENTROIDS, ST_COUNT };
+enum Stage {
+    ST_BEGIN = 0, ST_FILTER, ST_SORT, ST_ASSIGN_DENSE, ST_GFILTER, ST_ASSIGN, ST_RECHECK, ST_UPDATE, ST_CENTROIDS,
+    ST_COUNT
+};
 const char *stage_name(Stage st);
 // The stages of a dense (first) or filtered iteration of problem P, in order.
 int iteration_stages(const ProbDev &P, bool dense, Stage out[ST_COUNT]);
@@ -29,7 +32,7 @@ hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const L
 // gives each problem a contiguous range of blocks; a problem outside the
 // class gets none.
 enum TabId {
-    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_HIST, TB_SCATTER,
+    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_GF, TB_HIST, TB_SCATTER,
     TB_DENSE_F32,                     // + DMAX class (5)
     TB_TILE_F32 = TB_DENSE_F32 + 5,   // + DMAX class (5)
     TB_BLK64 = TB_TILE_F32 + 5,       // + KS class (6)
