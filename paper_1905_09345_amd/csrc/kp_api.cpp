@@ -38,7 +38,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, L3, vmask, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
         cursor1, ctr, stats, iter, scal, sink;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
@@ -90,11 +90,10 @@ Plan plan_problem(const kp_problem &p)
     o.L1s = take(n * 4);
     o.L1x = take(bf ? n * 16 : 0);
     o.L3 = take(bf ? n * 4 : 0);
-    o.vmask = take(bf ? n * (size_t)((g + 31) / 32) * 4 : 0);
     o.minnc = take(bf ? n * 4 : 0);
     const size_t ntiles = (n + 63) / 64;
-    o.tlist = take(bf ? 0 : ntiles * (size_t)g * 16);   // group-filter lists of the FP32 path
-    o.tcnt = take(bf ? 0 : ntiles * 4);
+    o.tlist = take(ntiles * (size_t)g * 16);   // per-tile visit lists of the group filter
+    o.tcnt = take(ntiles * 4);
     o.ps4 = take(n * 16);
     o.psf = take(n * 4);
     o.mvp = take(n * 4);
@@ -455,7 +454,6 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.L1s = (int *)(base + o.L1s);
         P.L1x = (int4 *)(base + o.L1x);
         P.L3 = (int *)(base + o.L3);
-        P.vmask = (unsigned *)(base + o.vmask);
         P.minnc = (float *)(base + o.minnc);
         P.tlist = (int4 *)(base + o.tlist);
         P.tcnt = (int *)(base + o.tcnt);

@@ -76,9 +76,9 @@ struct ProbDev {
     int *L1s;                 // the same ids sorted by assigned slot
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int *L3;                  // positions of the points whose BF16 decision is uncertain
-    unsigned *vmask;          // per position: open groups of the group filter, ceil(g/32) words
     float *minnc;             // per position: smallest bound of the closed groups (rounded down)
-    int4 *tlist;              // per tile of sorted L1: (group, point mask lo, hi, 0), g entries per tile
+    int4 *tlist;              // per tile of sorted L1, g entries: the group filter's visit list
+                              // (FP32: group, point mask lo, hi, 0; BF16: group, four 16-bit masks, 0)
     int *tcnt;                // entries used per tile
     float4 *ps4;              // per position: ub, min closed-group bound, U* of an uncertain point
     int *psf;                 // per position: bit 0 open (filter to distance kernel), bit 2 uncertain
@@ -197,16 +197,18 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
     return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
 // eta of one point for the BF16x3 estimate v = fl(fl(xn + cn) - 2 S) of
-// ||x - c||^2, where S = hh + (lh + hl) and hh = xh.ch, lh = xl.ch, hl = xh.cl
-// are accumulated separately in FP32 on the matrix cores (exact products).
+// ||x - c||^2, where S = hh + lo, hh = xh.ch accumulated in FP32 on the
+// matrix cores (exact products) and lo = xl.ch + xh.cl in a second FP32
+// accumulator.
 // Rounding to nearest with 8-bit significands gives x = xh + xl + rx with
 // |xl_i| <= 2^-8 (1 + 2^-8) |x_i| and |rx_i| <= 2^-16 |x_i|; the same for c.
 // With u = 2^-24, A >= ||x||, C >= ||c||:
 //   |xh.ch + xl.ch + xh.cl - x.c| <= |xl.cl| + |rx.c| + |xh.rc| + |xl.rc|
 //                                  <= 3.02 * 2^-16 A C
-//   sums of ldb products, gamma_ldb sum |products| each, doubled for the
+//   hh sums ldb products, lo 2 ldb products of size <= 2^-8 (1.01) |x_i c_i|:
+//   gamma_ldb (1.01) A C + gamma_2ldb 2^-7 (1.01) A C, doubled for the
 //   unspecified summation order inside the matrix cores: <= 2.1 (ldb + 2) u A C
-//   the two adds forming S: <= 2.05 u A C
+//   the add forming S (two are allowed for): <= 2.05 u A C
 // so |S - x.c| <= kappa A C.  xn and cn are FP64 norms rounded to FP32 (u each,
 // relative), xn + cn rounds once more, and the final fused multiply-add
 // rounds |xn + cn - 2S| <= 1.01 (A + C)^2 once:

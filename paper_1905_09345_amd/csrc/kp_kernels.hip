@@ -607,10 +607,11 @@ __device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense
 // ============================================== BF16 engine: MFMA per group
 // A FP32 vector is split as x = xh + xl + rx with xh = bf16(x) and
 // xl = bf16(x - xh) (x - xh is exact in FP32); the centroids the same way
-// (cb, cbl).  The dot product x.c is taken as xh.ch + xl.ch + xh.cl, each of
-// the three accumulated on the matrix cores (v_mfma_f32_16x16x32_bf16: exact
-// products, FP32 sums) in an accumulator of its own; mfma_eta3 bounds the
-// error of the resulting squared distance.
+// (cb, cbl).  The dot product x.c is taken as xh.ch + (xl.ch + xh.cl),
+// accumulated on the matrix cores (v_mfma_f32_16x16x32_bf16: exact products,
+// FP32 sums) in two accumulators, one for the leading products and one for
+// the two correction products; mfma_eta3 bounds the error of the resulting
+// squared distance.
 //
 // One wave works on a tile of 16 points.  Lane l holds point (l & 15) of the
 // tile and coordinates 32 ks + 8 (l >> 4) .. +7 of its split row: the B
@@ -757,17 +758,18 @@ __device__ __forceinline__ Key2 key2_fold32(Key2 t)
 }
 __device__ __forceinline__ float key_value(unsigned k) { return __uint_as_float(k & ~15u); }
 
-// Keys of the estimates v = ||x||^2 + ||c||^2 - 2 (hh + (lh + hl)) of lane
-// l's point against slots 4 (l >> 4) .. +3 of the chunk, reduced over the
-// four lane groups: every lane of point p returns p's two smallest keys.
-__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lh, const f32x4 &hl, float4 c4, float xnp)
+// Keys of the estimates v = ||x||^2 + ||c||^2 - 2 (hh + lo) of lane l's point
+// against slots 4 (l >> 4) .. +3 of the chunk (hh: leading products, lo: the
+// correction products), reduced over the four lane groups: every lane of
+// point p returns p's two smallest keys.
+__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp)
 {
     const float cnv[4] = {c4.x, c4.y, c4.z, c4.w};
     const unsigned base = 4u * (unsigned)(lane_id() >> 4);
     unsigned k[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float v = fmaxf(fmaf(-2.f, hh[r] + (lh[r] + hl[r]), xnp + cnv[r]), 0.f);
+        const float v = fmaxf(fmaf(-2.f, hh[r] + lo[r], xnp + cnv[r]), 0.f);
         k[r] = (__float_as_uint(v) & ~15u) | (base + (unsigned)r);
     }
     Key2 p = {min(k[0], k[1]), max(k[0], k[1])}, q = {min(k[2], k[3]), max(k[2], k[3])};
@@ -1023,24 +1025,29 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void kb_group_test(const ProbDev *
 
 
 // ======================================= group-level filter (BF16 mode)
-// One wave per 16 positions of the sorted L1, four per workgroup.  Each
-// point's group bounds are tested against its upper bound brought to this
-// iteration: lane (point p, quad q) reads groups g0 + 16 q .. +15 of p's bound
-// row as one 64-byte run.  The point's own group always stays open.  Writes,
-// per position, the open groups as a bit mask (ceil(g / 32) words) and the
-// smallest bound of the closed groups (rounded down).
+// One workgroup per tile of 64 sorted L1 positions -- the distance kernel's
+// tile -- with wave w on positions 16 w .. 16 w + 15.  Each point's group
+// bounds are tested against its upper bound brought to this iteration: lane
+// (point p, quad q) reads groups g0 + 16 q .. +15 of p's bound row as one
+// 64-byte run.  The point's own group always stays open.  Writes, per
+// position, the smallest bound of the closed groups (rounded down) and, per
+// tile, the visit list of the distance kernel: every group open for some
+// point of the tile, in group order, with the four waves' 16-bit point masks
+// (g, m0 | m1 << 16, m2 | m3 << 16, 0), and its length.
 __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ float gsu[GMAX_BF16];
+    __shared__ unsigned short msk[2][4][WAVE];   // round r: wave w's point mask of group g0 + t
     for (int i = threadIdx.x; i < P.g; i += blockDim.x) gsu[i] = P.Sgu[i];
     for (int i = P.g + threadIdx.x; i < ((P.g + 3) & ~3); i += blockDim.x) gsu[i] = 0.f;   // float4 tail
     __syncthreads();
-    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const long long count = list_len(P, CTR_L1);
-    const long long ntiles = (count + 15) / 16;
-    const int mw = (P.g + 31) / 32;
-    for (long long tl = (long long)bid_ * 4 + wv; tl < ntiles; tl += (long long)nblk_ * 4) {
-        const long long pos = tl * 16 + pt;
+    const long long ntiles = (count + 63) / 64;
+    int rb = 0;   // mask buffer, alternating over every round of the launch
+    for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
+        const long long pos = tl * 64 + 16 * wv + pt;
         const bool in = pos < count;
         int pid = 0, ga = -1;
         float ubt = KP_INF;
@@ -1051,8 +1058,10 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
             ga = min(max(e.w, 0), P.g - 1);
         }
         const float *lbrow = P.lb + (size_t)pid * P.gs;
+        int4 *vis = P.tlist + (size_t)tl * P.g;
         float cm = KP_INF;
-        for (int g0 = 0; g0 < P.g; g0 += WAVE) {
+        int nv = 0;
+        for (int g0 = 0; g0 < P.g; g0 += WAVE, rb ^= 1) {
             const int gq = g0 + 16 * quad;
             float v[16], sg[16];
 #pragma unroll
@@ -1079,14 +1088,30 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
                 bits |= open ? 1u << j : 0u;
                 cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
             }
-            // word g0/32 + q/2: quad 2i gives its low half, quad 2i+1 its high half
-            const unsigned hi = (unsigned)__shfl_xor((int)bits, 16);
-            const int w = g0 / 32 + (quad >> 1);
-            if (in && (quad & 1) == 0 && w < mw) P.vmask[(size_t)pos * mw + w] = bits | (hi << 16);
+            // transposed: lane t gets this wave's point mask of group g0 + t
+            unsigned long long mine = 0ull;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const unsigned long long bj = __ballot((bits >> j) & 1u);
+                if (pt == j) mine = bj;
+            }
+            msk[rb][wv][lane] = (unsigned short)((mine >> (16 * quad)) & 0xFFFFu);
+            // one barrier per round: a buffer is rewritten two rounds later,
+            // after every wave has passed the barrier of the round between
+            __syncthreads();
+            const unsigned m0 = msk[rb][0][lane], m1 = msk[rb][1][lane], m2 = msk[rb][2][lane],
+                           m3 = msk[rb][3][lane];
+            const bool open = g0 + lane < P.g && (m0 | m1 | m2 | m3) != 0u;
+            const unsigned long long om = __ballot(open);
+            if (wv == 0 && open)
+                vis[nv + __popcll(om & ((1ull << lane) - 1ull))] =
+                    make_int4(g0 + lane, (int)(m0 | (m1 << 16)), (int)(m2 | (m3 << 16)), 0);
+            nv += __popcll(om);
         }
         cm = fminf(cm, __shfl_xor(cm, 16));
         cm = fminf(cm, __shfl_xor(cm, 32));
         if (in && quad == 0) P.minnc[pos] = f_dn(cm);
+        if (wv == 0 && lane == 0) P.tcnt[tl] = nv;
     }
 }
 __global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter(P, (int)blockIdx.x, (int)gridDim.x); }
@@ -1190,7 +1215,6 @@ template <int KS>
 struct BlockLds {
     ChunkStage<KS> st[2];
     Visit vis[GMAX_BF16];           // the tile's visits (filtered iterations)
-    unsigned short mask[4][WAVE];   // while listing: wave w's point mask of group g0 + t
     int gst[GMAX_BF16], gsz[GMAX_BF16];
     float gsd[GMAX_BF16];           // Sg rounded down
 };
@@ -1234,15 +1258,15 @@ template <int KS>
 __device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp)
 {
     const int lane = lane_id();
-    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lh = {0.f, 0.f, 0.f, 0.f}, hl = {0.f, 0.f, 0.f, 0.f};
+    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lo = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 ah = S.a[ks][lane], al = S.a[KS + ks][lane];
         hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.h[ks], hh, 0, 0, 0);
-        lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.h[ks], lh, 0, 0, 0);
-        hl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], hl, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.h[ks], lo, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], lo, 0, 0, 0);
     }
-    return chunk_keys(hh, lh, hl, S.cn[lane >> 4], xnp);
+    return chunk_keys(hh, lo, S.cn[lane >> 4], xnp);
 }
 
 // Chunks of a tile's visits 0 .. nv-1 (workgroup-uniform); src(k, g, m, s0,
@@ -1376,10 +1400,10 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
     // sorted entry of this lane's position in the next tile, loaded one tile ahead
-    int4 nxt = make_int4(0, 0, 0, 0);
+    int2 nxt = make_int2(0, 0);   // point and slot of the entry (the first half of it)
     if (!DENSE) {
         const long long i0 = (long long)bid_ * 64 + 16 * wv + pt;
-        if (i0 < count) nxt = P.L1x[i0];
+        if (i0 < count) nxt = *(const int2 *)(P.L1x + i0);
     }
     for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
         const long long idx = tl * 64 + 16 * wv + pt;
@@ -1387,9 +1411,9 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         int pid = in && DENSE ? (int)idx : 0;
         int a = -1;
         if (!DENSE) {
-            const int4 e = nxt;
+            const int2 e = nxt;
             const long long inext = idx + 64ll * nblk_;
-            if (inext < count) nxt = P.L1x[inext];
+            if (inext < count) nxt = *(const int2 *)(P.L1x + inext);
             if (in) {
                 pid = clamp_pid(P, e.x);
                 a = clamp_slot(P, e.y);
@@ -1399,17 +1423,8 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const double eta = mfma_eta3(xnp, bmax, P.ldb);
         const float eta_f = d2f_up(eta);
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
-        // open-group words of the first two rounds and the closed-group bound,
-        // written by the group filter; issued together with the point rows
-        const int mw = (P.g + 31) / 32;
-        const unsigned *mrow = P.vmask + (size_t)(DENSE ? 0 : idx) * mw;
-        unsigned wr0 = 0u, wr1 = 0u;
-        float minnc = KP_INF;
-        if (!DENSE && in) {
-            if ((quad >> 1) < mw) wr0 = mrow[quad >> 1];
-            if (2 + (quad >> 1) < mw) wr1 = mrow[2 + (quad >> 1)];
-            minnc = P.minnc[idx];
-        }
+        // the closed-group bound, written by the group filter
+        const float minnc = (!DENSE && in) ? P.minnc[idx] : KP_INF;
         PtFrag<KS> b;
         load_points16<KS, false>(P, pid, in, nullptr, b);
         Run r;
@@ -1444,39 +1459,19 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             n_visits += wv == 0 ? (unsigned long long)P.g : 0ull;
             block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
         } else {
-            // list the groups the group filter left open for some point of the
-            // tile, 64 groups per round: lane (point p, quad q) holds groups
-            // g0 + 16 q .. +15 of point p; lane t then holds group g0 + t
-            int nv = 0;
-            for (int g0 = 0; g0 < P.g; g0 += WAVE) {
-                const int w = g0 / 32 + (quad >> 1);
-                unsigned word = g0 == 0 ? wr0 : (g0 == WAVE ? wr1 : 0u);
-                if (g0 >= 2 * WAVE && in && w < mw) word = mrow[w];
-                const unsigned bits = (word >> (16 * (quad & 1))) & 0xFFFFu;
-                unsigned long long mine = 0ull;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const unsigned long long bj = __ballot((bits >> j) & 1u);
-                    if ((lane & 15) == j) mine = bj;
-                }
-                L.mask[wv][lane] = (unsigned short)((mine >> (16 * quad)) & 0xFFFFu);
-                __syncthreads();
-                const unsigned short m0 = L.mask[0][lane], m1 = L.mask[1][lane], m2 = L.mask[2][lane],
-                                     m3 = L.mask[3][lane];
-                const int g = g0 + lane;
-                const bool open = g < P.g && (m0 | m1 | m2 | m3) != 0 && L.gsz[min(g, P.g - 1)] > 0;
-                const unsigned long long om = __ballot(open);
-                if (wv == 0 && open) {
-                    Visit &v = L.vis[nv + __popcll(om & ((1ull << lane) - 1ull))];
-                    v.g = g;
-                    v.m[0] = m0;
-                    v.m[1] = m1;
-                    v.m[2] = m2;
-                    v.m[3] = m3;
-                }
-                nv += __popcll(om);
-                __syncthreads();   // the masks are rewritten by the next round; the list is complete after the last
+            // the tile's visit list, written by the group filter
+            const int nv = min(max(P.tcnt[tl], 0), P.g);
+            const int4 *tv = P.tlist + (size_t)tl * P.g;
+            for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+                const int4 v = tv[k];
+                Visit &d = L.vis[k];
+                d.g = min(max(v.x, 0), P.g - 1);
+                d.m[0] = (unsigned short)((unsigned)v.y & 0xFFFFu);
+                d.m[1] = (unsigned short)((unsigned)v.y >> 16);
+                d.m[2] = (unsigned short)((unsigned)v.z & 0xFFFFu);
+                d.m[3] = (unsigned short)((unsigned)v.z >> 16);
             }
+            __syncthreads();
             auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
                 const Visit &v = L.vis[k];
                 g = v.g;
