@@ -658,12 +658,13 @@ __device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &h, bf16x8 &l
 // squared distance to that centroid row (c32, padded with zeros to ldc):
 // the lane's 8 KS coordinates summed in order with fused multiply-adds; the
 // four lanes of a point are combined by the caller (eps2_tile bounds it).
-template <int KS, bool OWN>
-__device__ __forceinline__ float load_points16(const ProbDev &P, int pid, bool ok, const float *crow, PtFrag<KS> &b)
+// This lane's 8 KS coordinates of point pid (FP32, zero beyond d and for
+// absent points): coordinates 32 ks + 8 (l >> 4) .. +7 for ks < KS.
+template <int KS>
+__device__ __forceinline__ void load_rows16(const ProbDev &P, int pid, bool ok, float (&v)[KS][8])
 {
     const int quad = lane_id() >> 4;
     const float *xr = P.X + (size_t)pid * P.d;
-    float v[KS][8], c[KS][8];
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     if ((P.d & 3) == 0 && ((uintptr_t)P.X & 15) == 0) {
 #pragma unroll
@@ -689,6 +690,20 @@ __device__ __forceinline__ float load_points16(const ProbDev &P, int pid, bool o
                 v[ks][j] = (ok && k < P.d) ? xr[k] : 0.f;
             }
     }
+}
+
+// The tile's B operand from the FP32 rows; zero beyond d and for absent
+// points.  With crow (OWN): also this lane's part of the FP32 direct-form
+// squared distance to that centroid row (c32, padded with zeros to ldc):
+// the lane's 8 KS coordinates summed in order with fused multiply-adds; the
+// four lanes of a point are combined by the caller (eps2_tile bounds it).
+template <int KS, bool OWN>
+__device__ __forceinline__ float load_points16(const ProbDev &P, int pid, bool ok, const float *crow, PtFrag<KS> &b)
+{
+    const int quad = lane_id() >> 4;
+    float v[KS][8], c[KS][8];
+    load_rows16<KS>(P, pid, ok, v);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     float d2 = 0.f;
     if (OWN) {
 #pragma unroll
@@ -1399,34 +1414,54 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     }
     __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
-    // sorted entry of this lane's position in the next tile, loaded one tile ahead
-    int2 nxt = make_int2(0, 0);   // point and slot of the entry (the first half of it)
+    // sorted entry of this lane's position in the tile after the one being
+    // fetched, loaded one tile ahead
+    int2 nxt = make_int2(0, 0);   // point and slot of the entry (its first half)
     if (!DENSE) {
         const long long i0 = (long long)bid_ * 64 + 16 * wv + pt;
         if (i0 < count) nxt = *(const int2 *)(P.L1x + i0);
     }
+    // A tile's inputs, fetched while the previous tile is finished: this
+    // lane's point, old slot, norm, closed-group bound and FP32 coordinates,
+    // and (filtered) the length of the tile's visit list and this thread's
+    // entry of it.
+    int f_pid = 0, f_a = -1, f_nv = 0;
+    float f_xn = 0.f, f_minnc = KP_INF;
+    float f_v[KS][8];
+    int4 f_ent = make_int4(0, 0, 0, 0);
+    auto fetch = [&](long long tf) {
+        const long long ix = tf * 64 + 16 * wv + pt;
+        const bool ok = ix < count;
+        f_pid = ok && DENSE ? (int)ix : 0;
+        f_a = -1;
+        if (!DENSE) {
+            const int2 e = nxt;
+            const long long inext = ix + 64ll * nblk_;
+            if (inext < count) nxt = *(const int2 *)(P.L1x + inext);
+            if (ok) {
+                f_pid = clamp_pid(P, e.x);
+                f_a = clamp_slot(P, e.y);
+            }
+        }
+        f_xn = ok ? P.xn[f_pid] : 0.f;
+        f_minnc = (!DENSE && ok) ? P.minnc[ix] : KP_INF;
+        load_rows16<KS>(P, f_pid, ok, f_v);
+        if (!DENSE && tf < ntiles) {
+            f_nv = P.tcnt[tf];
+            if ((int)threadIdx.x < P.g) f_ent = P.tlist[(size_t)tf * P.g + threadIdx.x];
+        }
+    };
+    if (bid_ < ntiles) fetch(bid_);
     for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
         const long long idx = tl * 64 + 16 * wv + pt;
         const bool in = idx < count;
-        int pid = in && DENSE ? (int)idx : 0;
-        int a = -1;
-        if (!DENSE) {
-            const int2 e = nxt;
-            const long long inext = idx + 64ll * nblk_;
-            if (inext < count) nxt = *(const int2 *)(P.L1x + inext);
-            if (in) {
-                pid = clamp_pid(P, e.x);
-                a = clamp_slot(P, e.y);
-            }
-        }
-        const float xnp = in ? P.xn[pid] : 0.f;
-        const double eta = mfma_eta3(xnp, bmax, P.ldb);
-        const float eta_f = d2f_up(eta);
+        const int pid = f_pid, a = f_a;
+        const float xnp = f_xn, minnc = f_minnc;
+        const float eta_f = d2f_up(mfma_eta3(xnp, bmax, P.ldb));
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
-        // the closed-group bound, written by the group filter
-        const float minnc = (!DENSE && in) ? P.minnc[idx] : KP_INF;
         PtFrag<KS> b;
-        load_points16<KS, false>(P, pid, in, nullptr, b);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) split8(f_v[ks], b.h[ks], b.l[ks]);
         Run r;
         run_init(r);
         float gmin = KP_INF;   // running minimum of the group being visited
@@ -1459,11 +1494,12 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             n_visits += wv == 0 ? (unsigned long long)P.g : 0ull;
             block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
         } else {
-            // the tile's visit list, written by the group filter
-            const int nv = min(max(P.tcnt[tl], 0), P.g);
+            // the tile's visit list, written by the group filter (the first
+            // entries fetched with the tile's inputs)
+            const int nv = min(max(f_nv, 0), P.g);
             const int4 *tv = P.tlist + (size_t)tl * P.g;
             for (int k = threadIdx.x; k < nv; k += blockDim.x) {
-                const int4 v = tv[k];
+                const int4 v = k == (int)threadIdx.x ? f_ent : tv[k];
                 Visit &d = L.vis[k];
                 d.g = min(max(v.x, 0), P.g - 1);
                 d.m[0] = (unsigned short)((unsigned)v.y & 0xFFFFu);
@@ -1485,11 +1521,14 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         }
         n_pairs += t_pairs;
         n_dist += t_dist;
+        // the next tile's loads are in flight while this one is finished
+        fetch(tl + nblk_);
         bool moved = false, amb = false;
         const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
             int win = -1;
             float umin = KP_INF;
+            const double eta = mfma_eta3(xnp, bmax, P.ldb);   // recomputed: not kept across the visits
             decide_bf16(P, pid, DENSE, a, -1, false, KP_INF, KP_INF, KP_INF, minnc, r, eta, 0.0, 0.0, sdd, moved,
                         amb, win, umin);
             P.mv_pt[pos] = pid;
@@ -1509,8 +1548,11 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
     }
 }
+// Three workgroups per CU (three waves per SIMD) are asked of the register
+// allocation up to KS = 4; wider rows get two (three would spill).  The
+// batched form keeps the default (its problem lookup would spill).
 template <int KS, bool DENSE, int DEPTH>
-__global__ __launch_bounds__(256) void k_blk64(ProbDev P)
+__global__ __launch_bounds__(256, KS <= 4 ? 3 : 2) void k_blk64(ProbDev P)
 {
     b_blk64<KS, DENSE, DEPTH>(P, (int)blockIdx.x, (int)gridDim.x);
 }
