@@ -52,6 +52,8 @@ def parse():
                     help="plain launches instead of graph replays")
     ap.add_argument("--depth", type=int, default=0, choices=[0, 1, 3],
                     help="centroid chunks in flight per workgroup (0: library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="workgroups per CU of the grid-stride launches (0: library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip kp_autotune (untimed, before the contexts are made) and use the defaults")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -252,8 +254,8 @@ def traffic_of(kernel, workload):
 def tuned(args, KMeans, kp_tuning, spec):
     """Launch tuning of the measured runs: kp_autotune's pick unless disabled
     or fixed on the command line; timing on (stage events)."""
-    tun = kp_tuning(chunk_depth=args.depth)
-    if not args.no_autotune and not args.depth:
+    tun = kp_tuning(chunk_depth=args.depth, blocks_per_cu=args.blocks_per_cu)
+    if not args.no_autotune and not args.depth and not args.blocks_per_cu:
         t0 = time.perf_counter()
         tun = KMeans.autotune(spec, iters=3)
         log("autotune: chunk_depth=%d blocks_per_cu=%d (%.1f s)" % (tun.chunk_depth, tun.blocks_per_cu,
