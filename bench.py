@@ -320,6 +320,17 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
     else:
         roofline = dict(kernel=dom, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                         ms_per_launch=agg[dom]["ms"] / max(agg[dom]["launches"], 1e-9))
+    others = {}
+    if "group_filter" in agg and dom != "group_filter" and agg["group_filter"]["launches"] > 0:
+        byts = 0.0
+        for i, p in enumerate(probs):
+            filt = [s for s in km.stats(i) if not s["dense"]]
+            if p.precision == "bf16":
+                byts += sum(gfilter_bytes(p, s) for s in filt) / max(len(filt), 1)
+        ms = agg["group_filter"]["ms"] / agg["group_filter"]["launches"]
+        ach = byts / (ms * 1e-3) / 1e9
+        others["group_filter"] = dict(kernel="kb_gfilter (all problems)", bound="hbm", achieved=ach,
+                                      peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
     del runs, km
     torch.cuda.empty_cache()
     baseline = None
