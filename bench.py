@@ -93,6 +93,46 @@ def plain_fp32_lloyd(torch, Xd, C0d, iters, warmup=1, chunk=1 << 19):
     return (time.perf_counter() - t0) / iters
 
 
+def serving(torch, km, Xd, nq=1_000_000, reps=5):
+    """kp_predict throughput with the context's trained centroids: nq queries
+    = training rows plus N(0, 0.05^2) noise (seeded), so they follow the same
+    mixture; plain torch FP32 GEMM + argmin on the same queries as the
+    comparator.  Queries are resident in HBM; HIP events around the calls."""
+    nq = min(nq, Xd.shape[0])
+    g = torch.Generator(device=Xd.device).manual_seed(4242)
+    Q = (Xd[:nq] + 0.05 * torch.randn(Xd[:nq].shape, generator=g, device=Xd.device)).contiguous()
+    out = km.predict(Q)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        km.predict(Q, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    c32 = km.centroids(0)[0]
+    torch.backends.cuda.matmul.allow_tf32 = False
+    cn = (c32 * c32).sum(1)
+    ct = c32.t().contiguous()
+    chunk = 1 << 19
+
+    def plain():
+        return torch.cat([torch.argmin(cn[None, :] - 2.0 * (Q[i:i + chunk] @ ct), dim=1)
+                          for i in range(0, nq, chunk)])
+    ref = plain()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        plain()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_plain = ev0.elapsed_time(ev1) / reps
+    agree = float((ref.to(torch.int32) == out).float().mean().item())
+    return dict(queries=nq, ms=ms, value=nq / (ms * 1e-3), unit="queries/s", plain_fp32_ms=ms_plain,
+                speedup_vs_plain_fp32=ms_plain / ms, agreement_with_plain_fp32=agree,
+                queries_recipe="training rows + N(0, 0.05^2) noise, seeded")
+
+
 def cpu_baseline(P, target_s):
     """The FP64 oracle (one Lloyd iteration) on a bounded sample of the workload."""
     import oracle
@@ -181,6 +221,9 @@ def main():
     # the dominant kernel stage (the whole-replay entry is a sum of stages)
     dom = max((nm for nm in agg if nm != "filtered_iter"), key=lambda nm: agg[nm]["ms"])
     roofline = roofline_of(dom, agg[dom], P, st)
+    serve = serving(torch, runs[-1], Xd)
+    log("serving: %d queries in %.3f ms (%.3g queries/s), plain FP32 argmin %.3f ms" % (
+        serve["queries"], serve["ms"], serve["value"], serve["plain_fp32_ms"]))
     others = {}
     for nm in ("assign_dense", "group_filter", "bound_filter"):
         if nm in agg and nm != dom:
@@ -206,6 +249,7 @@ def main():
                    else "fp32 direct + fp64 centroids", "tuning": TUNING},
         "roofline": roofline,
         "stage_rooflines": others,
+        "serving": serve,
         "cpu_baseline": cpu,
         "plain_fp32_lloyd": baseline,
         "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,

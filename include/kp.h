@@ -155,6 +155,27 @@ kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out_host, int32_t cap, int3
  * iterations).  Returns -1 for NULL. */
 int32_t kp_iterations(const kp_ctx *ctx);
 
+/* Serving: bytes of device scratch kp_predict needs for nq query points
+ * (0 with kp_last_error set for a NULL ctx, a bad problem index or nq outside
+ * 0..2^31-1). */
+size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq);
+
+/* Serving: queue the assignment of nq new points (queries_dev: nq*d FP32,
+ * row-major, 16-byte aligned; read until the queued work completes) to the
+ * current centroids of problem `problem` -- the assignment step of the
+ * iteration (Section 1) applied to points outside the training set, with its
+ * decision rule: labels_dev[i] receives the original index of the nearest
+ * centroid, ties to the lowest index.  BF16 problems decide on the BF16x3
+ * estimate under its error bound and recompute the uncertain points in FP32
+ * direct form over every centroid; FP32 problems use the FP32 direct form.
+ * Before the first iteration the initial centroids are used.  Nothing of the
+ * problem's state changes.  scratch_dev: caller-owned device memory of
+ * kp_predict_scratch_bytes(), 256-byte aligned, overwritten.  Ordered on the
+ * ctx's stream like kp_assign.  nq = 0 is a no-op; KP_ERR_INVALID for a bad
+ * problem index, NULL or misaligned pointers or short scratch. */
+kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries_dev, int64_t nq, int32_t *labels_dev,
+                     void *scratch_dev, size_t scratch_bytes);
+
 /* Synchronise and release the ctx's host resources, stream and graph.  The
  * workspace and points are the caller's to free afterwards.  NULL is a
  * no-op. */

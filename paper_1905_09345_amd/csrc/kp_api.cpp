@@ -776,6 +776,46 @@ kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out, int32_t cap, int32_t *
 
 int32_t kp_iterations(const kp_ctx *ctx) { return ctx ? ctx->iters : -1; }
 
+size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq)
+{
+    if (!ctx || problem < 0 || problem >= ctx->count || nq < 0 || nq > 0x7FFFFFFFll) {
+        set_error("NULL ctx, bad problem index %d or nq=%lld outside 0..2^31-1", problem, (long long)nq);
+        return 0;
+    }
+    return kp::SERVE_HEADER + ((size_t)nq * 4 + 255) / 256 * 256;
+}
+
+kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, int32_t *labels,
+                     void *scratch, size_t scratch_bytes)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count) {
+        set_error("bad problem index %d", problem);
+        return KP_ERR_INVALID;
+    }
+    if (nq < 0 || nq > 0x7FFFFFFFll) {
+        set_error("nq=%lld outside 0..2^31-1", (long long)nq);
+        return KP_ERR_INVALID;
+    }
+    if (nq == 0) return KP_OK;
+    if (!queries || !labels || !scratch) {
+        set_error("NULL queries, labels or scratch");
+        return KP_ERR_INVALID;
+    }
+    if (((uintptr_t)queries & 15u) != 0 || ((uintptr_t)scratch & 255u) != 0) {
+        set_error("queries must be 16-byte and scratch 256-byte aligned");
+        return KP_ERR_INVALID;
+    }
+    const size_t need = kp_predict_scratch_bytes(ctx, problem, nq);
+    if (scratch_bytes < need) {
+        set_error("scratch of %zu bytes, %zu needed", scratch_bytes, need);
+        return KP_ERR_INVALID;
+    }
+    KP_HIP(kp::launch_serve(ctx->P[problem], ctx->user, ctx->cfg, queries, (long long)nq, labels, scratch));
+    return KP_OK;
+}
+
 kp_status kp_autotune(const kp_problem *problems, int32_t count, void *workspace, size_t ws_bytes, void *stream,
                       int32_t iters, kp_tuning *best)
 {

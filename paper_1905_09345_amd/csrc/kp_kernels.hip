@@ -1980,6 +1980,149 @@ __global__ __launch_bounds__(256) void kb_segsum(const ProbDev *__restrict__ pro
 }
 
 
+// ================================================================ serving
+// New query points assigned to a problem's current centroids with the
+// iteration's decision rule -- the assignment step of Section 1 applied to
+// points outside the training set.  BF16 mode: every group is visited as in
+// the dense iteration, on tiles of 64 queries, and a query whose nearest
+// centroid is certain under the error bound is labelled at once; the others
+// are listed for an FP32 direct-form pass over every centroid.  FP32 mode:
+// every query takes that pass.  Nothing of the problem's state is written.
+
+// ||x||^2 of this lane's point from its 8 KS coordinates: FP64 squares summed
+// over the four lanes of the point, rounded to FP32 once.
+template <int KS>
+__device__ __forceinline__ float norm_rows16(const float (&v)[KS][8])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s = fma((double)v[ks][j], (double)v[ks][j], s);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return (float)s;
+}
+
+__global__ void k_serve_begin(unsigned long long *ucnt) { *ucnt = 0ull; }
+
+template <int KS, int DEPTH>
+__device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restrict__ Q, long long nq,
+                                        int *__restrict__ labels, int *__restrict__ unc,
+                                        unsigned long long *__restrict__ ucnt, const int bid_, const int nblk_)
+{
+    __shared__ BlockLds<KS> L;
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
+    const float bmax = P.scal[0];
+    for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
+        L.gst[i] = P.gstart[i];
+        L.gsz[i] = P.gsize[i];
+        L.gsd[i] = 0.f;
+    }
+    __syncthreads();
+    ProbDev Pq = P;   // the query rows in place of the training points
+    Pq.X = Q;
+    const long long ntiles = (nq + 63) / 64;
+    for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
+        const long long q = tl * 64 + 16 * wv + pt;
+        const bool in = q < nq;
+        float v[KS][8];
+        load_rows16<KS>(Pq, in ? (int)q : 0, in, v);
+        const float xnp = norm_rows16<KS>(v);
+        PtFrag<KS> b;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
+        const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's queries
+        Run r;
+        run_init(r);
+        float gmin = KP_INF;
+        auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
+            const float m1 = key_value(kk.k1);
+            const float gprev = first ? KP_INF : gmin;
+            gmin = fminf(gprev, m1);
+            run_fold_part(r, true, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev);
+        };
+        auto skip = [&]() {};
+        auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
+            g = k;
+            m = inm;
+            s0 = L.gst[k];
+            ns = L.gsz[k];
+            sgd = L.gsd[k];
+        };
+        block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
+        bool amb = false;
+        if (in && quad == 0) {
+            // certain iff the best estimate's upper bound is below every
+            // other estimate's lower bound
+            const double eta = mfma_eta3(xnp, bmax, P.ldb);
+            const float Ub = mfma_hi(r.bd, eta, 0.0), Ls = mfma_lo(r.sec, eta, 0.0);
+            if (Ub < Ls && r.bs >= 0) labels[q] = P.perm[clamp_slot(P, r.bs)];
+            else amb = true;
+        }
+        const long long e = wave_append(ucnt, amb);
+        if (e >= 0) unc[e] = (int)q;
+    }
+}
+template <int KS, int DEPTH>
+__global__ __launch_bounds__(256) void k_serve(ProbDev P, const float *Q, long long nq, int *labels, int *unc,
+                                               unsigned long long *ucnt)
+{
+    b_serve<KS, DEPTH>(P, Q, nq, labels, unc, ucnt, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// FP32 direct form over every centroid, eight lanes per query (as the
+// recheck), for the listed queries (unc != nullptr) or for all of them.
+// Lowest original index on exact ties.
+template <int NV>
+__global__ __launch_bounds__(256) void k_serve_fp32(ProbDev P, const float *__restrict__ Q, long long nq,
+                                                    const int *__restrict__ unc,
+                                                    const unsigned long long *__restrict__ ucnt,
+                                                    int *__restrict__ labels)
+{
+    const int lane = lane_id();
+    const int t = lane & (RT - 1);
+    const int team = threadIdx.x / RT;
+    const long long cnt = unc ? (long long)min(*ucnt, (unsigned long long)nq) : nq;
+    const long long nteams = (long long)gridDim.x * (blockDim.x / RT);
+    const long long trips = (cnt + nteams - 1) / nteams;   // the same for every lane of the grid
+    for (long long it = 0; it < trips; ++it) {
+        const long long e = it * nteams + (long long)blockIdx.x * (blockDim.x / RT) + team;
+        const bool live = e < cnt;
+        if (__ballot(live) == 0ull) continue;
+        const long long q = live ? (unc ? (long long)min(max(unc[e], 0), (int)(nq - 1)) : e) : 0;
+        float4 x[NV];
+        const float *xrow = Q + (size_t)q * P.d;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int i = 4 * t + 32 * j;
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (live && i + u < P.d) ? xrow[i + u] : 0.f;
+            x[j] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        float bd = KP_INF;
+        int bo = 0x7FFFFFFF;
+        constexpr int BATCH = NV <= 4 ? 4 : 2;   // rows in flight together
+        for (int s0 = 0; s0 < P.kg; s0 += BATCH) {
+            float4 c4[BATCH][NV];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u)
+                team_load<NV>(c4[u], P.c32 + (size_t)min(s0 + u, P.kg - 1) * P.ldc, P.ldc, t);
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const float dv = team_dist<NV>(x, c4[u]);
+                const int o = s0 + u < P.kg ? P.perm[s0 + u] : -1;   // -1: padding slot
+                if (o >= 0 && (dv < bd || (dv == bd && o < bo))) {
+                    bd = dv;
+                    bo = o;
+                }
+            }
+        }
+        if (live && t == 0) labels[q] = bo;
+    }
+}
+
 // ================================================================ outputs
 __global__ void k_labels(ProbDev P, int *out)
 {
@@ -2346,6 +2489,43 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
 hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out)
 {
     hipLaunchKernelGGL(k_labels, dim3(cap_grid((P.n + 255) / 256, 4096)), dim3(256), 0, s, P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,
+                        int *labels, void *scratch)
+{
+    auto *ucnt = (unsigned long long *)scratch;
+    int *unc = (int *)((char *)scratch + SERVE_HEADER);
+    const int nv = P.d <= 32 ? 1 : P.d <= 64 ? 2 : P.d <= 128 ? 4 : 8;
+    const int grid2 = cap_grid((nq + 31) / 32, cfg.grid_cap);
+    const unsigned long long *cnt_in = nullptr;
+    const int *list = nullptr;
+    if (P.prec) {
+        hipLaunchKernelGGL(k_serve_begin, dim3(1), dim3(1), 0, s, ucnt);
+        const int grid = cap_grid((nq + 63) / 64, cfg.grid_cap);
+#define KP_SERVE(KS)                                                                                       \
+    if (cfg.depth == 1) hipLaunchKernelGGL((k_serve<KS, 1>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, unc, ucnt); \
+    else hipLaunchKernelGGL((k_serve<KS, 3>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, unc, ucnt)
+        switch (P.ldb / 32) {
+        case 1: KP_SERVE(1); break;
+        case 2: KP_SERVE(2); break;
+        case 3: KP_SERVE(3); break;
+        case 4: KP_SERVE(4); break;
+        case 6: KP_SERVE(6); break;
+        case 8: KP_SERVE(8); break;
+        default: break;   // excluded when the plan is made
+        }
+#undef KP_SERVE
+        cnt_in = ucnt;
+        list = unc;
+    }
+    switch (nv) {
+    case 1: hipLaunchKernelGGL(k_serve_fp32<1>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+    case 2: hipLaunchKernelGGL(k_serve_fp32<2>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+    case 4: hipLaunchKernelGGL(k_serve_fp32<4>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+    default: hipLaunchKernelGGL(k_serve_fp32<8>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+    }
     return hipGetLastError();
 }
 

@@ -59,5 +59,10 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
 hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out);
 // Current centroids in original order (either output may be null).
 hipError_t launch_centroids_out(const ProbDev &P, hipStream_t s, float *c32, double *c64);
+// Serving: labels of nq query rows against the problem's current centroids.
+// scratch: SERVE_HEADER bytes (uncertain-query counter) + 4 nq bytes (list).
+constexpr size_t SERVE_HEADER = 256;
+hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,
+                        int *labels, void *scratch);
 
 }  // namespace kp

@@ -19,7 +19,8 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
-           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_strerror", "kp_last_error")
+           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_predict_scratch_bytes", "kp_predict",
+           "kp_strerror", "kp_last_error")
 
 
 class kp_problem(ctypes.Structure):
@@ -80,6 +81,10 @@ def lib():
         L.kp_destroy.restype = ctypes.c_int
         L.kp_autotune.argtypes = [P(kp_problem), ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_int32, P(kp_tuning)]
         L.kp_autotune.restype = ctypes.c_int
+        L.kp_predict_scratch_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
+        L.kp_predict_scratch_bytes.restype = ctypes.c_size_t
+        L.kp_predict.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t]
+        L.kp_predict.restype = ctypes.c_int
         L.kp_strerror.argtypes = [ctypes.c_int]
         L.kp_strerror.restype = ctypes.c_char_p
         L.kp_last_error.argtypes = []
@@ -117,6 +122,16 @@ def kp_iterate(ctx, iters):
 
 def kp_assign(ctx, problem, labels_ptr):
     _check(lib().kp_assign(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(labels_ptr)), "kp_assign")
+
+
+def kp_predict_scratch_bytes(ctx, problem, nq):
+    return int(lib().kp_predict_scratch_bytes(ctypes.c_void_p(ctx), int(problem), int(nq)))
+
+
+def kp_predict(ctx, problem, queries_ptr, nq, labels_ptr, scratch_ptr, scratch_bytes):
+    _check(lib().kp_predict(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(queries_ptr), int(nq),
+                            ctypes.c_void_p(labels_ptr), ctypes.c_void_p(scratch_ptr), int(scratch_bytes)),
+           "kp_predict")
 
 
 def kp_centroids(ctx, problem, c32_ptr=None, c64_ptr=None):
@@ -239,6 +254,24 @@ class KMeans:
         if out is None:
             out = self._torch.empty(p.n, dtype=self._torch.int32, device=self.device)
         kp_assign(self.ctx, problem, out.data_ptr())
+        return out
+
+    def predict(self, queries, problem=0, out=None):
+        """Labels of new points (n_q x d FP32 on the ctx's device) against the
+        problem's current centroids (kp_predict); scratch from torch."""
+        p = self.problems[problem]
+        q = queries.contiguous()
+        if q.dtype != self._torch.float32 or q.dim() != 2 or q.shape[1] != p.d or q.device != self.device:
+            raise ValueError("queries must be an (n, %d) float32 tensor on %s" % (p.d, self.device))
+        nq = q.shape[0]
+        if out is None:
+            out = self._torch.empty(nq, dtype=self._torch.int32, device=self.device)
+        nbytes = kp_predict_scratch_bytes(self.ctx, problem, nq)
+        scratch = self._torch.empty(nbytes + 256, dtype=self._torch.uint8, device=self.device)
+        base = (scratch.data_ptr() + 255) // 256 * 256
+        kp_predict(self.ctx, problem, q.data_ptr(), nq, out.data_ptr(), base, nbytes)
+        # the queued work reads both; held until the next call or close
+        self._serve_keep = (q, scratch)
         return out
 
     def centroids(self, problem=0):

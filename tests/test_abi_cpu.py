@@ -99,6 +99,9 @@ def test_null_ctx_calls():
     assert L.kp_stage_times(None, None, 0, ctypes.byref(n)) == kp.KP_ERR_INVALID
     assert L.kp_destroy(None) == kp.KP_OK
     assert L.kp_iterations(None) == -1
+    assert L.kp_predict(None, 0, None, 10, None, None, 0) == kp.KP_ERR_INVALID
+    assert L.kp_predict_scratch_bytes(None, 0, 10) == 0
+    assert b"ctx" in L.kp_last_error()
 
 
 def test_strerror():
