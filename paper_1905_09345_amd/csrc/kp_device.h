@@ -38,7 +38,8 @@ constexpr int SINK_SLOTS = 1024;      // 64-byte slots taking the stores of lane
 constexpr int GMAX_BF16 = 1024;       // largest g of the BF16 mode (group tables kept in LDS)
 
 // counters (unsigned long long) per problem
-enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6 };
+enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6,
+       CTR_MV = 7 /* entries of the moved list */ };
 
 struct __attribute__((aligned(16))) PointState {
     int a;        // slot of the assigned centroid

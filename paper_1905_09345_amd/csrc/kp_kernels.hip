@@ -914,13 +914,14 @@ __device__ __forceinline__ void b_dense_f32(const ProbDev &P, const int bid_, co
             if (act) *(float4 *)(lbrow + g4) = make_float4(outv[0], outv[1], outv[2], outv[3]);
         }
         bool moved = false;
-        if (act) {
-            moved = finish_f32(P, pid, true, -1, -1, false, KP_INF, KP_INF, KP_INF, r, eps2, sdd);
-            P.mv_pt[pid] = pid;
-            P.mv_old[pid] = -1;
-            P.mv_new[pid] = moved ? P.st[pid].a : -1;
-        }
+        if (act) moved = finish_f32(P, pid, true, -1, -1, false, KP_INF, KP_INF, KP_INF, r, eps2, sdd);
         n_moved += (unsigned long long)__popcll(__ballot(moved));
+        const long long em = wave_append(&P.ctr[CTR_MV], moved);
+        if (em >= 0) {
+            P.mv_pt[em] = pid;
+            P.mv_old[em] = -1;
+            P.mv_new[em] = P.st[pid].a;
+        }
     }
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
     if (bid_ == 0 && threadIdx.x == 0) {
@@ -1185,12 +1186,13 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
         }
         bool moved = false;
         if (act) moved = finish_f32(P, pid, false, a, ga, a_sep, d2a, lbe_a, minnc, r, eps2, sdd);
-        if (in) {
-            P.mv_pt[idx] = pid;
-            P.mv_old[idx] = a;
-            P.mv_new[idx] = moved ? P.st[pid].a : -1;
-        }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
+        const long long em = wave_append(&P.ctr[CTR_MV], moved);
+        if (em >= 0) {
+            P.mv_pt[em] = pid;
+            P.mv_old[em] = a;
+            P.mv_new[em] = P.st[pid].a;
+        }
     }
     if (lane == 0 && n_dist) atomicAdd(&P.ctr[CTR_DIST], n_dist);
     if (lane == 0 && n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
@@ -1524,19 +1526,23 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         // the next tile's loads are in flight while this one is finished
         fetch(tl + nblk_);
         bool moved = false, amb = false;
+        int win = -1;
         const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
-            int win = -1;
             float umin = KP_INF;
             const double eta = mfma_eta3(xnp, bmax, P.ldb);   // recomputed: not kept across the visits
             decide_bf16(P, pid, DENSE, a, -1, false, KP_INF, KP_INF, KP_INF, minnc, r, eta, 0.0, 0.0, sdd, moved,
                         amb, win, umin);
-            P.mv_pt[pos] = pid;
-            P.mv_old[pos] = a;
-            P.mv_new[pos] = moved ? win : -1;
             if (amb) P.ps4[pos] = make_float4(0.f, 0.f, umin, 0.f);
         }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
+        // moved points: compact list for the centroid update
+        const long long em = wave_append(&P.ctr[CTR_MV], moved);
+        if (em >= 0) {
+            P.mv_pt[em] = pid;
+            P.mv_old[em] = a;
+            P.mv_new[em] = win;
+        }
         // uncertain points: compact list of positions for the FP32 recheck
         const long long q3 = wave_append(&P.ctr[CTR_L3], amb);
         if (q3 >= 0) P.L3[q3] = (int)pos;
@@ -1641,6 +1647,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
     const float sdd = P.Sdud[1];
     const bool dense = P.ctr[CTR_DENSE] != 0;
     const long long n3 = list_len(P, CTR_L3);   // uncertain positions, listed by the distance kernel
+    const long long mv0 = list_len(P, CTR_MV);  // update entries the distance kernel wrote before these
     const long long nteams = (long long)nblk_ * (blockDim.x / RT);
     const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
     unsigned long long n_moved = 0;
@@ -1790,10 +1797,15 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             nsv.p = store_lb(lbp, sdd);
             nsv.ga = gbest;
             P.st[pid] = nsv;
-            P.mv_pt[e] = pid;
-            P.mv_old[e] = olda;
-            P.mv_new[e] = bs != olda ? bs : -1;
             n_moved += bs != olda ? 1ull : 0ull;
+        }
+        // the centroid update's entry of this point, after the entries the
+        // distance kernel listed (-1: did not move)
+        if (t == 0) {
+            const long long em = mv0 + e3;
+            P.mv_pt[em] = pid;
+            P.mv_old[em] = olda;
+            P.mv_new[em] = bs != olda ? bs : -1;
         }
     }
     // one atomic per lane that decided points (lane 0 of each team)
@@ -1814,10 +1826,17 @@ __global__ __launch_bounds__(256) void kb_recheck(const ProbDev *__restrict__ pr
 
 
 // ========================================================= centroid update
-// Entries over the M positions of the iteration: e < M adds point mv_pt[e]
-// to slot mv_new[e]; M <= e < 2M subtracts point mv_pt[e-M] from slot
-// mv_old[e-M].  Positions that did not move (mv_new = -1) and points that had
-// no slot before (mv_old = -1) contribute nothing.
+// Entries of the centroid update: the points the distance kernels decided
+// and moved (a compact list), then one entry per rechecked point (mv_new = -1
+// when it did not move) -- M in all.  e < M adds point mv_pt[e] to slot
+// mv_new[e]; M <= e < 2M subtracts point mv_pt[e-M] from slot mv_old[e-M].
+// Points that had no slot before (mv_old = -1, the dense iteration)
+// contribute no subtraction.
+__device__ __forceinline__ long long update_len(const ProbDev &P)
+{
+    const long long m = list_len(P, CTR_MV) + list_len(P, CTR_L3);
+    return m < (long long)P.n ? m : (long long)P.n;
+}
 __device__ __forceinline__ int entry_key(const ProbDev &P, long long e, long long M)
 {
     const long long q = e < M ? e : e - M;
@@ -1830,7 +1849,7 @@ __device__ __forceinline__ int entry_key(const ProbDev &P, long long e, long lon
 __device__ __forceinline__ void b_hist(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
-    const long long M = positions(P);
+    const long long M = update_len(P);
     const long long E = 2 * M;
     const bool lds = P.kg <= HIST_LDS;
     if (lds)
@@ -1864,7 +1883,7 @@ __device__ __forceinline__ void b_scatter(const ProbDev &P, const int bid_, cons
 {
     __shared__ int h[HIST_LDS];
     __shared__ int base[HIST_LDS];
-    const long long M = positions(P);
+    const long long M = update_len(P);
     const long long E = 2 * M;
     const bool lds = P.kg <= HIST_LDS;
     const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
@@ -1919,21 +1938,39 @@ template <int DCH>
 __device__ __forceinline__ void b_segsum(const ProbDev &P, const int bid_, const int nblk_)
 {
     const int lane = lane_id();
-    const long long M = positions(P);
+    const long long M = update_len(P);
     const long long used = (long long)P.cursor[P.kg - 1];   // end of the last bin = entries sorted
     const long long E = used < 2 * M ? used : 2 * M;
-    const long long nchunks = (E + WAVE - 1) / WAVE;
+    constexpr int SEG = DCH <= 2 ? 16 : (DCH <= 4 ? 8 : 2);   // sorted entries per wave and pass: their rows load together
+    const long long nchunks = (E + SEG - 1) / SEG;
     const long long nw = (long long)nblk_ * (blockDim.x / WAVE);
     for (long long c = (long long)bid_ * (blockDim.x / WAVE) + threadIdx.x / WAVE; c < nchunks; c += nw) {
-        const long long p0 = c * WAVE, p1 = (p0 + WAVE < E) ? p0 + WAVE : E;
+        const long long p0 = c * SEG;
+        const int cnt = (int)((p0 + SEG < E) ? SEG : E - p0);
+        // lane i < cnt holds entry p0 + i: its slot and (signed) point
+        const int ekey = lane < cnt ? clamp_slot(P, P.srt_key[p0 + lane]) : 0;
+        const int ept = lane < cnt ? P.srt_pt[p0 + lane] : 0;
+        float xv[SEG][DCH];
+#pragma unroll
+        for (int i = 0; i < SEG; ++i) {
+            const int v = __builtin_amdgcn_readlane(ept, i);
+            const float *xr = P.X + (size_t)clamp_pid(P, v & 0x7FFFFFFF) * P.d;
+#pragma unroll
+            for (int j = 0; j < DCH; ++j) {
+                const int dim = lane + WAVE * j;
+                xv[i][j] = (i < cnt && dim < P.d) ? xr[dim] : 0.f;
+            }
+        }
         double acc[DCH];
 #pragma unroll
         for (int j = 0; j < DCH; ++j) acc[j] = 0.0;
         int cacc = 0;
-        int cur = clamp_slot(P, P.srt_key[p0]);
-        for (long long p = p0; p < p1; ++p) {
-            const int key = clamp_slot(P, P.srt_key[p]);
-            const int v = P.srt_pt[p];
+        int cur = __builtin_amdgcn_readlane(ekey, 0);
+#pragma unroll
+        for (int i = 0; i < SEG; ++i) {
+            if (i >= cnt) break;
+            const int key = __builtin_amdgcn_readlane(ekey, i);
+            const bool neg = __builtin_amdgcn_readlane(ept, i) < 0;
             if (key != cur) {
 #pragma unroll
                 for (int j = 0; j < DCH; ++j) {
@@ -1945,16 +1982,10 @@ __device__ __forceinline__ void b_segsum(const ProbDev &P, const int bid_, const
                 cacc = 0;
                 cur = key;
             }
-            const int pid = clamp_pid(P, v & 0x7FFFFFFF);
-            const bool neg = v < 0;
-            const float *xr = P.X + (size_t)pid * P.d;
 #pragma unroll
             for (int j = 0; j < DCH; ++j) {
-                const int dim = lane + WAVE * j;
-                if (dim < P.d) {
-                    const double xv = (double)xr[dim];
-                    acc[j] += neg ? -xv : xv;
-                }
+                const double x = (double)xv[i][j];
+                acc[j] += neg ? -x : x;
             }
             cacc += neg ? -1 : 1;
         }
