@@ -42,6 +42,7 @@ struct Plan {
         cursor1, ctr, stats, iter, scal, sink;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
+    size_t nk1max;   // keys of the L1 order for kgmax slots
 };
 
 Plan plan_problem(const kp_problem &p)
@@ -51,6 +52,9 @@ Plan plan_problem(const kp_problem &p)
     const int d = p.d, g = p.g;
     const bool bf = p.precision == KP_PREC_BF16_RECHECK;
     o.kgmax = p.k + (kp::CHUNK_SLOTS - 1) * g;
+    // L1 ordered by slot, then by a bucket of the nearest other group: at most
+    // max(slots, HIST_LDS) keys whatever the final slot count
+    o.nk1max = (size_t)(o.kgmax > kp::HIST_LDS ? o.kgmax : kp::HIST_LDS);
     o.ldc = (d + 3) / 4 * 4;
     o.ldb = (d + 31) / 32 * 32;
     if (o.ldb == 160) o.ldb = 192;   // BF16 tiles take 1, 2, 3, 4, 6 or 8 steps of 32
@@ -103,8 +107,8 @@ Plan plan_problem(const kp_problem &p)
     o.srtk = take(2 * n * 4);
     o.hist = take((kgm + 1) * 4);
     o.cursor = take((kgm + 1) * 4);
-    o.hist1 = take((kgm + 1) * 4);
-    o.cursor1 = take((kgm + 1) * 4);
+    o.hist1 = take((o.nk1max + 1) * 4);
+    o.cursor1 = take((o.nk1max + 1) * 4);
     o.ctr = take(kp::NCTR * 8);
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
@@ -426,6 +430,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.gs = o.gs;
         P.prec = p.precision;
         P.maxgs = G.maxgs;
+        P.nk1 = G.kg * kp::l1_buckets(p.n, G.kg, G.g);
         P.X = p.points_dev;
         P.xn = (float *)(base + o.xn);
         P.st = (kp::PointState *)(base + o.st);

@@ -34,6 +34,19 @@ constexpr int CHUNK = 16;             // centroid slots per MFMA tile / group pa
 constexpr int STATS_CAP = 1024;       // per-iteration stats ring
 constexpr int NCTR = 8;               // per-iteration counters
 constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
+// Buckets of the nearest other group in the L1 order of a problem with n
+// points, kg slots and g groups: as many as keep kg * buckets within the LDS
+// histogram and about four tiles of 64 points per bucket, at most g + 1
+// (1: order by slot only).
+__host__ __device__ inline int l1_buckets(long long n, int kg, int g)
+{
+    if (kg <= 0) return 1;
+    long long b = HIST_LDS / kg;
+    const long long fill = n / (256ll * kg);
+    if (fill < b) b = fill;
+    if (g + 1 < b) b = g + 1;
+    return b < 1 ? 1 : (int)b;
+}
 constexpr int SINK_SLOTS = 1024;      // 64-byte slots taking the stores of lanes with nothing to write
 constexpr int GMAX_BF16 = 1024;       // largest g of the BF16 mode (group tables kept in LDS)
 
@@ -57,6 +70,7 @@ struct ProbDev {
     int ldc, ldb, gs;         // leading dims: c32 (roundup 4), bf16 (roundup 32), lb row
     int prec;                 // 0 fp32 direct, 1 bf16 + recheck
     int maxgs;                // largest group size (real members)
+    int nk1;                  // keys of the L1 order: kg * buckets of the nearest other group (<= HIST_LDS), or kg
     const float *X;
     float *xn;
     PointState *st;
@@ -74,7 +88,7 @@ struct ProbDev {
     float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
     int *L1;                  // point ids failing the point-level filter (filter order)
-    int *L1s;                 // the same ids sorted by assigned slot
+    int *L1s;                 // the same ids sorted by assigned slot (and nearest other group, bucketed)
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int *L3;                  // positions of the points whose BF16 decision is uncertain
     float *minnc;             // per position: smallest bound of the closed groups (rounded down)
@@ -86,7 +100,7 @@ struct ProbDev {
     int *mv_pt, *mv_old, *mv_new;   // per position: point, old slot, new slot (-1: did not move)
     int *srt_pt, *srt_key;    // update entries sorted by centroid slot (sign in bit 31 of srt_pt)
     int *hist, *cursor;       // kg + 1: centroid update sort
-    int *hist1, *cursor1;     // kg + 1: L1 sort
+    int *hist1, *cursor1;     // nk1 + 1: L1 sort
     unsigned long long *ctr;  // NCTR counters of the running iteration
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations

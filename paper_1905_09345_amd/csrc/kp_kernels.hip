@@ -246,10 +246,8 @@ __device__ __forceinline__ void b_begin(const ProbDev &P, const int bid_, const 
 {
     const int tid = bid_ * blockDim.x + threadIdx.x;
     if (tid < NCTR) P.ctr[tid] = (tid == CTR_DENSE) ? (unsigned long long)dense : 0ull;
-    for (int s = tid; s <= P.kg; s += nblk_ * blockDim.x) {
-        P.hist[s] = 0;
-        P.hist1[s] = 0;
-    }
+    for (int s = tid; s <= P.kg; s += nblk_ * blockDim.x) P.hist[s] = 0;
+    for (int s = tid; s <= P.nk1; s += nblk_ * blockDim.x) P.hist1[s] = 0;
 }
 __global__ void k_begin(ProbDev P, int dense)
 {
@@ -324,23 +322,36 @@ __global__ __launch_bounds__(256) void kb_bound_filter(const ProbDev *__restrict
 
 // ======================================================= L1 sort by slot
 // key of L1 entry e: the slot its point is assigned to.
+// Key of an L1 entry: its slot, then one of nk1 / kg buckets of the nearest
+// other group of its last decision (the group modulo the bucket count), so
+// that a tile's points tend to share their neighbouring groups as well as
+// their own.  The key space stays within the LDS histogram.
+__device__ __forceinline__ int l1_key(const ProbDev &P, int a, int gaf)
+{
+    const int nb = P.nk1 / P.kg;
+    if (nb <= 1) return a;
+    const int o = min((gaf >> 16) & 0xFFFF, P.g);   // 0xFFFF (none) -> group g
+    return a * nb + o % nb;
+}
+
 __device__ __forceinline__ void b_key_hist(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int h[HIST_LDS];
     const long long n1 = list_len(P, CTR_L1);
-    const bool lds = P.kg <= HIST_LDS;
+    const bool lds = P.nk1 <= HIST_LDS;
     if (lds)
-        for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
+        for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (long long e = (long long)bid_ * blockDim.x + threadIdx.x; e < n1;
          e += (long long)nblk_ * blockDim.x) {
-        const int key = clamp_slot(P, P.st[clamp_pid(P, P.L1[e])].a);
+        const PointState st = P.st[clamp_pid(P, P.L1[e])];
+        const int key = l1_key(P, clamp_slot(P, st.a), st.ga);
         if (lds) atomicAdd(&h[key], 1);
         else atomicAdd(&P.hist1[key], 1);
     }
     __syncthreads();
     if (lds)
-        for (int i = threadIdx.x; i < P.kg; i += blockDim.x)
+        for (int i = threadIdx.x; i < P.nk1; i += blockDim.x)
             if (h[i]) atomicAdd(&P.hist1[i], h[i]);
 }
 __global__ __launch_bounds__(256) void k_key_hist(ProbDev P)
@@ -383,7 +394,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int *hist, int *cursor, int
 __global__ __launch_bounds__(1024) void kb_scan(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count, int which)
 {
     const ProbDev P = probs[batch_problem(tab, count)];
-    if (which) b_scan(P.hist1, P.cursor1, P.kg);
+    if (which) b_scan(P.hist1, P.cursor1, P.nk1);
     else b_scan(P.hist, P.cursor, P.kg);
 }
 
@@ -394,23 +405,26 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
     __shared__ int base[HIST_LDS];
     const long long E = list_len(P, CTR_L1);
     const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
-    if (P.kg > HIST_LDS) {
+    if (P.nk1 > HIST_LDS) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
             const int pid = clamp_pid(P, P.L1[e]);
             const PointState st = P.st[pid];
-            const int key = clamp_slot(P, st.a);
+            const int a = clamp_slot(P, st.a), key = l1_key(P, a, st.ga);
             const int pos = atomicAdd(&P.cursor1[key], 1);
             P.L1s[pos] = pid;
-            if (P.prec) P.L1x[pos] = make_int4(pid, key, __float_as_int(ub_now(st.u, P.Scu[key])), st.ga);
+            if (P.prec) P.L1x[pos] = make_int4(pid, a, __float_as_int(ub_now(st.u, P.Scu[a])), st.ga & 0xFFFF);
         }
         return;
     }
     if (b0 >= b1) return;   // uniform per block
-    for (int i = threadIdx.x; i < P.kg; i += blockDim.x) h[i] = 0;
+    for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) atomicAdd(&h[clamp_slot(P, P.st[clamp_pid(P, P.L1[e])].a)], 1);
+    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        const PointState st = P.st[clamp_pid(P, P.L1[e])];
+        atomicAdd(&h[l1_key(P, clamp_slot(P, st.a), st.ga)], 1);
+    }
     __syncthreads();
-    for (int i = threadIdx.x; i < P.kg; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) {
         base[i] = h[i] ? atomicAdd(&P.cursor1[i], h[i]) : 0;
         h[i] = 0;
     }
@@ -418,10 +432,10 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
     for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
         const int pid = clamp_pid(P, P.L1[e]);
         const PointState st = P.st[pid];
-        const int key = clamp_slot(P, st.a);
+        const int a = clamp_slot(P, st.a), key = l1_key(P, a, st.ga);
         const int pos = base[key] + atomicAdd(&h[key], 1);
         P.L1s[pos] = pid;
-        if (P.prec) P.L1x[pos] = make_int4(pid, key, __float_as_int(ub_now(st.u, P.Scu[key])), st.ga);
+        if (P.prec) P.L1x[pos] = make_int4(pid, a, __float_as_int(ub_now(st.u, P.Scu[a])), st.ga & 0xFFFF);
     }
 }
 __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
@@ -531,24 +545,39 @@ __device__ __forceinline__ bool before(const ProbDev &P, float v, int sa, float 
 
 // ====================================================== per-point decisions
 // Running best of one point over the groups examined: best value, its slot
-// and group, the second value of the best's group and the overall second.
+// and group, the second value of the best's group and the overall second;
+// ov / og: the smallest value of any other group and that group (the point's
+// nearest other group, kept for the order of the next iteration's L1).
 struct Run {
-    float bd, sec, bm2;
-    int bs, bg;
+    float bd, sec, bm2, ov;
+    int bs, bg, og;
 };
 __device__ __forceinline__ void run_init(Run &r)
 {
     r.bd = KP_INF;
     r.sec = KP_INF;
     r.bm2 = KP_INF;
+    r.ov = KP_INF;
     r.bs = -1;
     r.bg = -1;
+    r.og = -1;
+}
+// The state's group field: the assigned centroid's group in the low 16 bits,
+// the nearest other group (0xFFFF: none) in the high 16.
+__device__ __forceinline__ int pack_ga(int ga, int og)
+{
+    const unsigned o = (og >= 0 && og != ga) ? (unsigned)og & 0xFFFFu : 0xFFFFu;
+    return (int)(((unsigned)ga & 0xFFFFu) | (o << 16));
 }
 __device__ __forceinline__ void run_fold(const ProbDev &P, Run &r, const Best3 &gb, int g)
 {
     // A group result of +inf carries no slot (a skipped MFMA block): never a best.
     if (!(gb.m1 < KP_INF)) return;
     if (before(P, gb.m1, gb.s1, r.bd, r.bs)) {
+        if (g != r.bg) {   // the old best's group is now the nearest other one
+            r.ov = r.bd;
+            r.og = r.bg;
+        }
         r.sec = fminf(r.bd, gb.m2);
         r.bd = gb.m1;
         r.bs = gb.s1;
@@ -556,6 +585,10 @@ __device__ __forceinline__ void run_fold(const ProbDev &P, Run &r, const Best3 &
         r.bm2 = gb.m2;
     } else {
         r.sec = fminf(r.sec, gb.m1);
+        if (g != r.bg && gb.m1 < r.ov) {
+            r.ov = gb.m1;
+            r.og = g;
+        }
     }
 }
 
@@ -599,7 +632,7 @@ __device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense
     ns.a = win;
     ns.u = store_u(dist_hi(r.bd, eps2), P.Scd[win]);
     ns.p = store_lb(lbp, sdd);
-    ns.ga = P.slot_group[win];
+    ns.ga = pack_ga(P.slot_group[win], win == r.bs ? r.og : -1);
     P.st[pid] = ns;
     return win != (dense ? -1 : a);
 }
@@ -812,11 +845,21 @@ __device__ __forceinline__ float est_hi(float v, float eta_f)
 // running best, when `on`.  gprev: minimum over the group's earlier chunks
 // (+inf for its first).  A tie of estimates can never be decided under the
 // error bound, so ties keep the earlier result.
-__device__ __forceinline__ void run_fold_part(Run &r, bool on, float m1, int s1, float m2, int g, float gprev)
+__device__ __forceinline__ void run_fold_part(Run &r, bool on, float m1, int s1, float m2, int g, float gprev,
+                                              bool track_og)
 {
     const bool nb = on && m1 < r.bd;
     const float sec = nb ? fminf(r.bd, m2) : fminf(r.sec, m1);
     const float bm2 = nb ? fminf(m2, gprev) : (g == r.bg ? fminf(r.bm2, m1) : r.bm2);
+    if (track_og) {   // wave-uniform
+        // nearest other group: the old best's group when a new group leads,
+        // else this group when it comes closer than the current one
+        const float gm = fminf(gprev, m1);
+        const bool oo = nb && g != r.bg;
+        const bool on2 = on && !nb && g != r.bg && gm < r.ov;
+        r.ov = oo ? r.bd : (on2 ? gm : r.ov);
+        r.og = oo ? r.bg : (on2 ? g : r.og);
+    }
     r.sec = on ? sec : r.sec;
     r.bm2 = on ? bm2 : r.bm2;
     r.bd = nb ? m1 : r.bd;
@@ -857,7 +900,7 @@ __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dens
     if (amb) return;
     PointState nsv;
     nsv.a = win;
-    nsv.ga = P.slot_group[win];
+    nsv.ga = pack_ga(P.slot_group[win], win == r.bs ? r.og : -1);
     float ubn, lbp;
     if (a_sep && win == a) {
         ubn = ubt;
@@ -1406,6 +1449,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const float bmax = P.scal[0];
     const float sdd = P.Sdud[1];
+    const bool track_og = P.nk1 > P.kg;   // the L1 order uses the nearest other group
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
@@ -1476,7 +1520,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             const float m1 = key_value(kk.k1);
             const float gprev = first ? KP_INF : gmin;
             gmin = fminf(gprev, m1);
-            run_fold_part(r, mine, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev);
+            run_fold_part(r, mine, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev, track_og);
             const float lbv = dn_nonneg(est_lo(gmin, eta_f) + sgd);   // offset form, rounded down
             // one unconditional store per chunk: lanes without a bound to
             // write send it to the workgroup's sink slot
@@ -1648,6 +1692,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
     const bool dense = P.ctr[CTR_DENSE] != 0;
     const long long n3 = list_len(P, CTR_L3);   // uncertain positions, listed by the distance kernel
     const long long mv0 = list_len(P, CTR_MV);  // update entries the distance kernel wrote before these
+    const int last_pos = (int)(positions(P) - 1);  // counters read once: other waves update their line
     const long long nteams = (long long)nblk_ * (blockDim.x / RT);
     const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
     unsigned long long n_moved = 0;
@@ -1655,7 +1700,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         const long long e3 = it * nteams + (long long)bid_ * (blockDim.x / RT) + team;
         const bool live = e3 < n3;
         if (__ballot(live) == 0ull) continue;   // past the end of the list for this wave's eight teams
-        const long long e = live ? (long long)max(min(P.L3[e3], (int)(positions(P) - 1)), 0) : 0;
+        const long long e = live ? (long long)max(min(P.L3[e3], last_pos), 0) : 0;
         const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
         const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
         const float umin = live ? P.ps4[e].z : 0.f;
@@ -1702,8 +1747,8 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float bd = KP_INF;
-        int bs = -1;
+        float bd = KP_INF, ov = KP_INF;
+        int bs = -1, bgr = -1, og = -1;
         for (int i = 0; i < nscan_w; ++i) {
             const bool on = i < nscan;
             const int g = on ? (overflow ? i : rg[team][i]) : 0;
@@ -1737,8 +1782,16 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
                     rm2[team][i] = m2;
                 }
                 if (before(P, m1, s1, bd, bs)) {
+                    if (g != bgr) {
+                        ov = bd;
+                        og = bgr;
+                    }
                     bd = m1;
                     bs = s1;
+                    bgr = g;
+                } else if (g != bgr && m1 < ov) {
+                    ov = m1;
+                    og = g;
                 }
             }
         }
@@ -1795,7 +1848,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             nsv.a = bs;
             nsv.u = store_u(dist_hi(bd, eps2), P.Scd[bs]);
             nsv.p = store_lb(lbp, sdd);
-            nsv.ga = gbest;
+            nsv.ga = pack_ga(gbest, og);
             P.st[pid] = nsv;
             n_moved += bs != olda ? 1ull : 0ull;
         }
@@ -2071,7 +2124,7 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
             const float m1 = key_value(kk.k1);
             const float gprev = first ? KP_INF : gmin;
             gmin = fminf(gprev, m1);
-            run_fold_part(r, true, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev);
+            run_fold_part(r, true, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev, false);
         };
         auto skip = [&]() {};
         auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
@@ -2305,7 +2358,7 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
 {
     switch (st) {
     case ST_BEGIN:
-        hipLaunchKernelGGL(k_begin, dim3(cap_grid((P.kg + 256) / 256, 64)), dim3(256), 0, s, P, dense ? 1 : 0);
+        hipLaunchKernelGGL(k_begin, dim3(cap_grid(((long long)P.nk1 + 256) / 256, 1024)), dim3(256), 0, s, P, dense ? 1 : 0);
         break;
     case ST_FILTER:
         hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 4095) / 4096, cfg.grid_cap)), dim3(256), 0, s, P);
@@ -2313,7 +2366,7 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
     case ST_SORT: {
         const int blocks = cap_grid((P.n + 16383) / 16384, 1024);
         hipLaunchKernelGGL(k_key_hist, dim3(blocks), dim3(256), 0, s, P);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist1, P.cursor1, P.kg);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist1, P.cursor1, P.nk1);
         hipLaunchKernelGGL(k_l1_scatter, dim3(blocks), dim3(256), 0, s, P);
         break;
     }
@@ -2387,7 +2440,7 @@ static int tab_blocks(int id, const ProbDev &P, const LaunchCfg &cfg, int cap)
     if (id >= TB_SEGSUM && id < TB_COUNT)
         return dch_class(P.d) == id - TB_SEGSUM ? cap_grid((2 * n + 255) / 256, cap) : 0;
     switch (id) {
-    case TB_BEGIN: return cap_grid((P.kg + 256) / 256, 64);
+    case TB_BEGIN: return cap_grid(((long long)P.nk1 + 256) / 256, 1024);
     case TB_FILTER: return cap_grid((n + 4095) / 4096, cap);
     case TB_SORT: return cap_grid((n + 16383) / 16384, 1024);
     case TB_ONE: return 1;
