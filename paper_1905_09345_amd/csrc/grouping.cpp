@@ -4,9 +4,11 @@
 // centroids) (paper, Section 1: "Group-level Filter").  The paper does not
 // say how groups are formed; here they are the clusters of a small FP64
 // K-means over the k initial centroids: k-means++ seeding from the problem's
-// seed, five Lloyd iterations, and every empty group filled with the member
-// of the largest group that lies farthest from that group's center.  The
-// grouping only changes how much work the filter saves, never the result.
+// seed, five Lloyd iterations, every empty group filled with the member of
+// the largest group that lies farthest from that group's center, and group
+// sizes capped at the smallest multiple of 16 (one matrix-core chunk) that
+// holds k / g.  The grouping only changes how much work the filter saves,
+// never the result.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -120,6 +122,38 @@ Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed)
             cnt[big]--;
             cnt[empty] = 1;
             for (int i = 0; i < d; ++i) ctr[(size_t)empty * d + i] = C[(size_t)far * d + i];
+        }
+        // cap the group sizes at the smallest multiple of the chunk that holds
+        // k / g members: a group above it gives up its members farthest from
+        // its center, each to the group with room whose center is nearest.
+        // Every group then fills its chunks, and no visit pays for a chunk
+        // holding one or two centroids.
+        const int cap = CHUNK_SLOTS * ((k + g * CHUNK_SLOTS - 1) / (g * CHUNK_SLOTS));
+        for (int q = 0; q < g; ++q) {
+            if (cnt[q] <= cap) continue;
+            std::vector<std::pair<double, int>> mem;
+            for (int j = 0; j < k; ++j)
+                if (lab[j] == q) mem.push_back({sq(C + (size_t)j * d, &ctr[(size_t)q * d], d), j});
+            std::sort(mem.begin(), mem.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+                return x.first > y.first || (x.first == y.first && x.second < y.second);
+            });
+            for (size_t e = 0; e < mem.size() && cnt[q] > cap; ++e) {
+                const int j = mem[e].second;
+                int to = -1;
+                double tv = std::numeric_limits<double>::infinity();
+                for (int r = 0; r < g; ++r) {
+                    if (r == q || cnt[r] >= cap) continue;
+                    const double v = sq(C + (size_t)j * d, &ctr[(size_t)r * d], d);
+                    if (v < tv) {
+                        tv = v;
+                        to = r;
+                    }
+                }
+                if (to < 0) break;   // unreachable: g * cap >= k
+                lab[j] = to;
+                cnt[q]--;
+                cnt[to]++;
+            }
         }
     }
     Grouping out;
