@@ -53,8 +53,8 @@ Plan plan_problem(const kp_problem &p)
     const bool bf = p.precision == KP_PREC_BF16_RECHECK;
     o.kgmax = p.k + (kp::CHUNK_SLOTS - 1) * g;
     // L1 ordered by slot, then by a bucket of the nearest other group: at most
-    // max(slots, HIST_LDS) keys whatever the final slot count
-    o.nk1max = (size_t)(o.kgmax > kp::HIST_LDS ? o.kgmax : kp::HIST_LDS);
+    // max(slots, L1_HIST) keys whatever the final slot count
+    o.nk1max = (size_t)(o.kgmax > kp::L1_HIST ? o.kgmax : kp::L1_HIST);
     o.ldc = (d + 3) / 4 * 4;
     o.ldb = (d + 31) / 32 * 32;
     if (o.ldb == 160) o.ldb = 192;   // BF16 tiles take 1, 2, 3, 4, 6 or 8 steps of 32

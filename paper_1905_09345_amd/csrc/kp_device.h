@@ -34,6 +34,7 @@ constexpr int CHUNK = 16;             // centroid slots per MFMA tile / group pa
 constexpr int STATS_CAP = 1024;       // per-iteration stats ring
 constexpr int NCTR = 8;               // per-iteration counters
 constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
+constexpr int L1_HIST = 16384;        // largest key count of the L1 order histogrammed in LDS
 // Buckets of the nearest other group in the L1 order of a problem with n
 // points, kg slots and g groups: as many as keep kg * buckets within the LDS
 // histogram and about four tiles of 64 points per bucket, at most g + 1
@@ -41,7 +42,7 @@ constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
 __host__ __device__ inline int l1_buckets(long long n, int kg, int g)
 {
     if (kg <= 0) return 1;
-    long long b = HIST_LDS / kg;
+    long long b = L1_HIST / kg;
     const long long fill = n / (256ll * kg);
     if (fill < b) b = fill;
     if (g + 1 < b) b = g + 1;

@@ -336,9 +336,9 @@ __device__ __forceinline__ int l1_key(const ProbDev &P, int a, int gaf)
 
 __device__ __forceinline__ void b_key_hist(const ProbDev &P, const int bid_, const int nblk_)
 {
-    __shared__ int h[HIST_LDS];
+    __shared__ int h[L1_HIST];
     const long long n1 = list_len(P, CTR_L1);
-    const bool lds = P.nk1 <= HIST_LDS;
+    const bool lds = P.nk1 <= L1_HIST;
     if (lds)
         for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = 0;
     __syncthreads();
@@ -401,11 +401,10 @@ __global__ __launch_bounds__(1024) void kb_scan(const ProbDev *__restrict__ prob
 
 __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, const int nblk_)
 {
-    __shared__ int h[HIST_LDS];
-    __shared__ int base[HIST_LDS];
+    __shared__ int h[L1_HIST];   // this workgroup's count per key, then its next position per key
     const long long E = list_len(P, CTR_L1);
     const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
-    if (P.nk1 > HIST_LDS) {
+    if (P.nk1 > L1_HIST) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
             const int pid = clamp_pid(P, P.L1[e]);
             const PointState st = P.st[pid];
@@ -424,16 +423,13 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
         atomicAdd(&h[l1_key(P, clamp_slot(P, st.a), st.ga)], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) {
-        base[i] = h[i] ? atomicAdd(&P.cursor1[i], h[i]) : 0;
-        h[i] = 0;
-    }
+    for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = h[i] ? atomicAdd(&P.cursor1[i], h[i]) : 0;
     __syncthreads();
     for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
         const int pid = clamp_pid(P, P.L1[e]);
         const PointState st = P.st[pid];
         const int a = clamp_slot(P, st.a), key = l1_key(P, a, st.ga);
-        const int pos = base[key] + atomicAdd(&h[key], 1);
+        const int pos = atomicAdd(&h[key], 1);
         P.L1s[pos] = pid;
         if (P.prec) P.L1x[pos] = make_int4(pid, a, __float_as_int(ub_now(st.u, P.Scu[a])), st.ga & 0xFFFF);
     }
