@@ -90,7 +90,7 @@ Plan plan_problem(const kp_problem &p)
     o.Sgu = take((size_t)g * 4);
     o.Sgd = take((size_t)g * 4);
     o.Sdud = take(8);
-    o.L1 = take(n * 4);
+    o.L1 = take(n * 16);
     o.L1s = take(n * 4);
     o.L1x = take(bf ? n * 16 : 0);
     o.L3 = take(bf ? n * 4 : 0);
@@ -455,7 +455,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Sgu = (float *)(base + o.Sgu);
         P.Sgd = (float *)(base + o.Sgd);
         P.Sdud = (float *)(base + o.Sdud);
-        P.L1 = (int *)(base + o.L1);
+        P.L1 = (int4 *)(base + o.L1);
         P.L1s = (int *)(base + o.L1s);
         P.L1x = (int4 *)(base + o.L1x);
         P.L3 = (int *)(base + o.L3);

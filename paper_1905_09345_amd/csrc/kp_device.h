@@ -88,7 +88,7 @@ struct ProbDev {
     float *Scu, *Scd;         // FP32 copies of Sc rounded up / down
     float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
-    int *L1;                  // point ids failing the point-level filter (filter order)
+    int4 *L1;                 // points failing the point-level filter (filter order): {point, slot, ub now, group field}
     int *L1s;                 // the same ids sorted by assigned slot (and nearest other group, bucketed)
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int *L3;                  // positions of the points whose BF16 decision is uncertain

@@ -278,14 +278,22 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
     const int64_t chunk = 256 * BF_PER_THREAD;
     for (int64_t b0 = (int64_t)bid_ * chunk; b0 < P.n; b0 += (int64_t)nblk_ * chunk) {
         unsigned long long masks[BF_PER_THREAD];
+        int ka[BF_PER_THREAD], kgf[BF_PER_THREAD];   // the kept points' slot and group field
+        float ku[BF_PER_THREAD];                     // and upper bound brought to this iteration
         int mine = 0;
 #pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
             bool keep = false;
+            ka[r] = 0;
+            kgf[r] = 0;
+            ku[r] = 0.f;
             if (i < P.n) {
                 const PointState s = P.st[i];
-                keep = !(ub_now(s.u, P.Scu[clamp_slot(P, s.a)]) < lb_now(s.p, sdu));
+                ka[r] = clamp_slot(P, s.a);
+                kgf[r] = s.ga;
+                ku[r] = ub_now(s.u, P.Scu[ka[r]]);
+                keep = !(ku[r] < lb_now(s.p, sdu));
             }
             masks[r] = __ballot(keep);
             mine += __popcll(masks[r]);
@@ -302,7 +310,9 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
         const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
-            if ((masks[r] >> lane) & 1ull) P.L1[pos + __popcll(masks[r] & below)] = (int)(b0 + (int64_t)r * 256 + tid);
+            if ((masks[r] >> lane) & 1ull)
+                P.L1[pos + __popcll(masks[r] & below)] =
+                    make_int4((int)(b0 + (int64_t)r * 256 + tid), ka[r], __float_as_int(ku[r]), kgf[r]);
             pos += (unsigned long long)__popcll(masks[r]);
         }
         __syncthreads();
@@ -344,8 +354,8 @@ __device__ __forceinline__ void b_key_hist(const ProbDev &P, const int bid_, con
     __syncthreads();
     for (long long e = (long long)bid_ * blockDim.x + threadIdx.x; e < n1;
          e += (long long)nblk_ * blockDim.x) {
-        const PointState st = P.st[clamp_pid(P, P.L1[e])];
-        const int key = l1_key(P, clamp_slot(P, st.a), st.ga);
+        const int4 u = P.L1[e];
+        const int key = l1_key(P, clamp_slot(P, u.y), u.w);
         if (lds) atomicAdd(&h[key], 1);
         else atomicAdd(&P.hist1[key], 1);
     }
@@ -406,12 +416,11 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
     const long long b0 = E * bid_ / nblk_, b1 = E * (bid_ + 1) / nblk_;
     if (P.nk1 > L1_HIST) {
         for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-            const int pid = clamp_pid(P, P.L1[e]);
-            const PointState st = P.st[pid];
-            const int a = clamp_slot(P, st.a), key = l1_key(P, a, st.ga);
+            const int4 u = P.L1[e];
+            const int pid = clamp_pid(P, u.x), a = clamp_slot(P, u.y), key = l1_key(P, a, u.w);
             const int pos = atomicAdd(&P.cursor1[key], 1);
             P.L1s[pos] = pid;
-            if (P.prec) P.L1x[pos] = make_int4(pid, a, __float_as_int(ub_now(st.u, P.Scu[a])), st.ga & 0xFFFF);
+            if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);
         }
         return;
     }
@@ -419,19 +428,18 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
     for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-        const PointState st = P.st[clamp_pid(P, P.L1[e])];
-        atomicAdd(&h[l1_key(P, clamp_slot(P, st.a), st.ga)], 1);
+        const int4 u = P.L1[e];
+        atomicAdd(&h[l1_key(P, clamp_slot(P, u.y), u.w)], 1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < P.nk1; i += blockDim.x) h[i] = h[i] ? atomicAdd(&P.cursor1[i], h[i]) : 0;
     __syncthreads();
     for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-        const int pid = clamp_pid(P, P.L1[e]);
-        const PointState st = P.st[pid];
-        const int a = clamp_slot(P, st.a), key = l1_key(P, a, st.ga);
+        const int4 u = P.L1[e];
+        const int pid = clamp_pid(P, u.x), a = clamp_slot(P, u.y), key = l1_key(P, a, u.w);
         const int pos = atomicAdd(&h[key], 1);
         P.L1s[pos] = pid;
-        if (P.prec) P.L1x[pos] = make_int4(pid, a, __float_as_int(ub_now(st.u, P.Scu[a])), st.ga & 0xFFFF);
+        if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);
     }
 }
 __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
