@@ -873,54 +873,26 @@ __device__ __forceinline__ void run_fold_part(Run &r, bool on, float m1, int s1,
 
 // BF16 decision under the error bound; writes the point's state and bound
 // fix-ups when the decision is certain, else reports it as uncertain with
-// U* (an upper bound on its true nearest distance).
-__device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, int ga, bool a_sep,
-                                            float ubt, float d2a, float lbe_a, float minnc, const Run &r,
-                                            double eta, double rho, double eps2, float sdd, bool &moved,
-                                            bool &amb, int &win, float &umin)
+// U* (an upper bound on its true nearest distance).  The bounds on a
+// distance come from its estimate with est_lo / est_hi (eta_f: the point's
+// eta rounded up to FP32).
+__device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, float minnc, const Run &r,
+                                            float eta_f, float sdd, bool &moved, bool &amb, int &win, float &umin)
 {
-    float *lbrow = P.lb + (size_t)pid * P.gs;
-    const float Lb = mfma_lo(r.bd, eta, rho), Ub = mfma_hi(r.bd, eta, rho);
-    const float Ls = mfma_lo(r.sec, eta, rho);
-    float La = KP_INF;
-    amb = false;
-    if (a_sep) {
-        La = dist_lo(d2a, eps2, rho);
-        if (ubt < Lb) {
-            win = a;   // the old centroid is certainly nearest
-        } else if (Ub < La && Ub < Ls) {
-            win = r.bs;
-        } else {
-            amb = true;
-            umin = fminf(Ub, ubt);
-        }
-    } else if (Ub < Ls) {
-        win = r.bs;
-    } else {
-        amb = true;
-        umin = Ub;
-    }
+    const float Ub = est_hi(r.bd, eta_f), Ls = est_lo(r.sec, eta_f);
+    amb = !(Ub < Ls);   // certain iff the best is below every other estimate
     moved = false;
-    if (amb) return;
+    if (amb) {
+        umin = Ub;
+        return;
+    }
+    win = r.bs;
     PointState nsv;
     nsv.a = win;
-    nsv.ga = pack_ga(P.slot_group[win], win == r.bs ? r.og : -1);
-    float ubn, lbp;
-    if (a_sep && win == a) {
-        ubn = ubt;
-        lbp = fminf(minnc, Lb);
-    } else {
-        lbrow[r.bg] = store_lb(mfma_lo(r.bm2, eta, rho), P.Sgd[r.bg]);
-        ubn = Ub;
-        lbp = fminf(minnc, Ls);
-        if (a_sep) {
-            const float va = fminf(lbe_a, La);
-            lbrow[ga] = store_lb(va, P.Sgd[ga]);
-            lbp = fminf(lbp, va);
-        }
-    }
-    nsv.u = store_u(ubn, P.Scd[win]);
-    nsv.p = store_lb(lbp, sdd);
+    nsv.ga = pack_ga(P.slot_group[win], r.og);
+    P.lb[(size_t)pid * P.gs + r.bg] = store_lb(est_lo(r.bm2, eta_f), P.Sgd[r.bg]);
+    nsv.u = store_u(Ub, P.Scd[win]);
+    nsv.p = store_lb(fminf(minnc, Ls), sdd);
     P.st[pid] = nsv;
     moved = win != (dense ? -1 : a);
 }
@@ -1578,9 +1550,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
             float umin = KP_INF;
-            const double eta = mfma_eta3(xnp, bmax, P.ldb);   // recomputed: not kept across the visits
-            decide_bf16(P, pid, DENSE, a, -1, false, KP_INF, KP_INF, KP_INF, minnc, r, eta, 0.0, 0.0, sdd, moved,
-                        amb, win, umin);
+            decide_bf16(P, pid, DENSE, a, minnc, r, eta_f, sdd, moved, amb, win, umin);
             if (amb) P.ps4[pos] = make_float4(0.f, 0.f, umin, 0.f);
         }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
@@ -2143,8 +2113,8 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         if (in && quad == 0) {
             // certain iff the best estimate's upper bound is below every
             // other estimate's lower bound
-            const double eta = mfma_eta3(xnp, bmax, P.ldb);
-            const float Ub = mfma_hi(r.bd, eta, 0.0), Ls = mfma_lo(r.sec, eta, 0.0);
+            const float eta_f = d2f_up(mfma_eta3(xnp, bmax, P.ldb));
+            const float Ub = est_hi(r.bd, eta_f), Ls = est_lo(r.sec, eta_f);
             if (Ub < Ls && r.bs >= 0) labels[q] = P.perm[clamp_slot(P, r.bs)];
             else amb = true;
         }
