@@ -1551,7 +1551,8 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         if (in && quad == 0) {
             float umin = KP_INF;
             decide_bf16(P, pid, DENSE, a, minnc, r, eta_f, sdd, moved, amb, win, umin);
-            if (amb) P.ps4[pos] = make_float4(0.f, 0.f, umin, 0.f);
+            // the recheck's inputs: the BF16 best slot and U*
+            if (amb) P.ps4[pos] = make_float4(__int_as_float(r.bs), 0.f, umin, 0.f);
         }
         n_moved += (unsigned long long)__popcll(__ballot(moved));
         // moved points: compact list for the centroid update
@@ -1677,7 +1678,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         const long long e = live ? (long long)max(min(P.L3[e3], last_pos), 0) : 0;
         const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
         const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
-        const float umin = live ? P.ps4[e].z : 0.f;
+        const float4 pin = live ? P.ps4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
         const bool a_sep = false;
         float4 x[NV];
         const float *xrow = P.X + (size_t)pid * P.d;
@@ -1689,6 +1690,12 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             for (int q = 0; q < 4; ++q) v[q] = (live && i + q < P.d) ? xrow[i + q] : 0.f;
             x[j] = make_float4(v[0], v[1], v[2], v[3]);
         }
+        // candidate threshold: the smaller of U* and an upper bound on the
+        // FP32 direct-form distance to the BF16 pass's best centroid (either
+        // bounds the nearest distance from above; the second has no BF16
+        // error in it)
+        const int bslot = clamp_slot(P, __float_as_int(pin.x));
+        const float umin = fminf(pin.z, dist_hi(team_d2<NV>(x, P.c32 + (size_t)bslot * P.ldc, P.ldc, t), eps2));
         float *lbrow = P.lb + (size_t)pid * P.gs;
         // groups that may hold the nearest centroid
         float minnr = KP_INF;
