@@ -38,8 +38,8 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, stats, iter, scal, sink;
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, gcn, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+        cursor1, ctr, stats, iter, sink;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
     size_t nk1max;   // keys of the L1 order for kgmax slots
@@ -89,6 +89,7 @@ Plan plan_problem(const kp_problem &p)
     o.Scd = take(kgm * 4);
     o.Sgu = take((size_t)g * 4);
     o.Sgd = take((size_t)g * 4);
+    o.gcn = take((size_t)g * 4);
     o.Sdud = take(8);
     o.L1 = take(n * 16);
     o.L1s = take(n * 4);
@@ -112,7 +113,6 @@ Plan plan_problem(const kp_problem &p)
     o.ctr = take(kp::NCTR * 8);
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
-    o.scal = take(16);
     o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
     o.bytes = off;
     return o;
@@ -454,6 +454,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Scd = (float *)(base + o.Scd);
         P.Sgu = (float *)(base + o.Sgu);
         P.Sgd = (float *)(base + o.Sgd);
+        P.gcn = (float *)(base + o.gcn);
         P.Sdud = (float *)(base + o.Sdud);
         P.L1 = (int4 *)(base + o.L1);
         P.L1s = (int *)(base + o.L1s);
@@ -476,7 +477,6 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.ctr = (unsigned long long *)(base + o.ctr);
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
-        P.scal = (float *)(base + o.scal);
         P.sink = (float *)(base + o.sink);
         KP_HIP(hipMemcpyAsync((void *)P.perm, G.perm.data(), G.perm.size() * 4, hipMemcpyHostToDevice, ctx->user));
         KP_HIP(hipMemcpyAsync((void *)P.slot_group, G.slot_group.data(), G.slot_group.size() * 4,

@@ -87,6 +87,7 @@ struct ProbDev {
     double *Sc, *Sg, *Sd;     // cumulative drifts (kg, g, 1), FP64
     float *Scu, *Scd;         // FP32 copies of Sc rounded up / down
     float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
+    float *gcn;               // per group: an upper bound on its members' FP32 norms ||c||
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
     int4 *L1;                 // points failing the point-level filter (filter order): {point, slot, ub now, group field}
     int *L1s;                 // the same ids sorted by assigned slot (and nearest other group, bucketed)
@@ -105,7 +106,6 @@ struct ProbDev {
     unsigned long long *ctr;  // NCTR counters of the running iteration
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
-    float *scal;              // [0] max ||c32|| (rounded up)
     float *sink;              // SINK_SLOTS x 16 floats, written and never read
 };
 
@@ -212,7 +212,7 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
     const double r = s - rho;
     return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
-// eta of one point for the BF16x3 estimate v = fl(fl(xn + cn) - 2 S) of
+// eta of a (point, centroid) pair for the BF16x3 estimate v = fl(fl(xn + cn) - 2 S) of
 // ||x - c||^2, where S = hh + lo, hh = xh.ch accumulated in FP32 on the
 // matrix cores (exact products) and lo = xl.ch + xh.cl in a second FP32
 // accumulator.
@@ -230,16 +230,36 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 // rounds |xn + cn - 2S| <= 1.01 (A + C)^2 once:
 //   |v - ||x - c||^2| <= 3.02 u (A^2 + C^2) + (2 kappa + 2.02 u) A C.
 // The estimates are then compared with their low 4 significand bits
-// cleared (at most 2^-19 v <= 2^-19 * 1.01 (A + C)^2 less), which the last
-// term adds.  The true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
-__device__ __forceinline__ double mfma_eta3(float xn, float bmax, int ldb)
+// cleared (at most 2^-19 v <= 2^-19 * 1.01 (A + C)^2 less), which a third
+// term adds.  With it expanded,
+//   eta = a (A^2 + C^2) + b A C,  a = 3.02 u + 1.01 2^-19,
+//                                 b = 2 kappa + 2.02 u + 2.02 2^-19,
+// and the true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
+// A is per point, C per chunk of centroids: the bound on the norms of the
+// chunk's group.  eta is evaluated in FP32 with a and b scaled by
+// (1 + 2^-20) (1 + 2^-16), which covers the seven roundings of the evaluation
+// (each <= u relative, on sums and products of non-negative terms), and
+// rounded up.
+struct Eta3 {
+    float a, b;
+};
+__device__ __forceinline__ Eta3 mfma_eta3_coef(int ldb)
 {
     const double u = 5.9604644775390625e-08;
-    const double A = sqrt((double)xn) * (1.0 + 0x1p-22), C = (double)bmax;
     const double kappa = 3.02 * 0x1p-16 + 2.1 * (double)(ldb + 2) * u + 2.05 * u;
-    const double q = 1.01 * 0x1p-19 * (A + C) * (A + C);
-    return (3.02 * u * (A * A + C * C) + (2.0 * kappa + 2.02 * u) * A * C + q) * (1.0 + 0x1p-20);
+    const double s = (1.0 + 0x1p-20) * (1.0 + 0x1p-16);
+    Eta3 k;
+    k.a = d2f_up((3.02 * u + 1.01 * 0x1p-19) * s);
+    k.b = d2f_up((2.0 * kappa + 2.02 * u + 2.02 * 0x1p-19) * s);
+    return k;
 }
+// A >= ||x|| from the point's squared norm rounded to FP32, once per point.
+__device__ __forceinline__ float mfma_eta3_a(float xn) { return d2f_up(sqrt((double)xn) * (1.0 + 0x1p-22)); }
+// eta = fma(pt.x, grp.x, pt.y + grp.y) for a point with bound A and a chunk
+// whose group has bound C (both FP32, rounded up): pt = (b A, a A^2), grp =
+// (C, a C^2).
+__device__ __forceinline__ float2 mfma_eta3_pt(const Eta3 &k, float A) { return make_float2(k.b * A, k.a * (A * A)); }
+__device__ __forceinline__ float2 mfma_eta3_grp(const Eta3 &k, float C) { return make_float2(C, k.a * (C * C)); }
 
 // --------------------------------------------------- tuple merge (d^2, slot, second)
 struct Best3 {

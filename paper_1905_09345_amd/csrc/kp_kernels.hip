@@ -167,43 +167,40 @@ __global__ __launch_bounds__(256) void kb_centroids(const ProbDev *__restrict__ 
 // ================================================================== drifts
 // Single workgroup.  After the update of iteration t: per-group maximum
 // drift, the global maximum, the cumulative sums (FP64, each increment
-// rounded up) and their FP32 copies, the error-bound scalars and the
+// rounded up) and their FP32 copies, the groups' norm bounds and the
 // iteration's statistics.  first = 1 at init.
 __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const int nblk_, int first)
 {
     __shared__ double red[1024];
-    __shared__ float redf[2][1024];
     const int tid = threadIdx.x;
     const double up = 1.0 + 0x1p-50;
     double gmax = 0.0;
     for (int g = tid; g < P.g; g += blockDim.x) {
         double m = 0.0;
+        float cm = 0.f;
         const int s0 = P.gstart[g], ns = P.gsize[g];
-        for (int r = 0; r < ns; ++r) m = fmax(m, P.delta[s0 + r]);
+        for (int r = 0; r < ns; ++r) {
+            m = fmax(m, P.delta[s0 + r]);
+            if (P.perm[s0 + r] >= 0) cm = fmaxf(cm, P.cn[s0 + r]);
+        }
+        // the largest member norm (cn: FP64 squared norm rounded to FP32)
+        P.gcn[g] = d2f_up(sqrt((double)cm) * (1.0 + 0x1p-22));
         const double sg = first ? 0.0 : (P.Sg[g] + m) * up;
         P.Sg[g] = sg;
         P.Sgu[g] = d2f_up(sg);
         P.Sgd[g] = d2f_dn(sg);
         gmax = fmax(gmax, m);
     }
-    float bmax = 0.f, rmax = 0.f;
     for (int s = tid; s < P.kg; s += blockDim.x) {
         const double sc = first ? 0.0 : (P.Sc[s] + P.delta[s]) * up;
         P.Sc[s] = sc;
         P.Scu[s] = d2f_up(sc);
         P.Scd[s] = d2f_dn(sc);
-        if (P.perm[s] >= 0) bmax = fmaxf(bmax, P.cn[s]);
     }
     red[tid] = gmax;
-    redf[0][tid] = bmax;
-    redf[1][tid] = rmax;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (tid < o) {
-            red[tid] = fmax(red[tid], red[tid + o]);
-            redf[0][tid] = fmaxf(redf[0][tid], redf[0][tid + o]);
-            redf[1][tid] = fmaxf(redf[1][tid], redf[1][tid + o]);
-        }
+        if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
         __syncthreads();
     }
     if (tid == 0) {
@@ -211,8 +208,6 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
         P.Sd[0] = sd;
         P.Sdud[0] = d2f_up(sd);
         P.Sdud[1] = d2f_dn(sd);
-        P.scal[0] = d2f_up(sqrt((double)redf[0][0]) * (1.0 + 0x1p-46));
-        P.scal[1] = 0.f;
         if (!first) {
             const int t = *P.iter + 1;
             long long *rec = P.stats + (size_t)((t - 1) % STATS_CAP) * 16;
@@ -833,11 +828,12 @@ __device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lo, flo
 // |v - d^2| <= eta (eta_f: eta rounded up to FP32).  v_sqrt_f32 is within
 // 1 ulp of the square root (normal inputs); two steps cover it, and one step
 // each covers the rounding of v -/+ eta.  Tiny arguments give the bound 0.
-__device__ __forceinline__ float est_lo(float v, float eta_f)
+__device__ __forceinline__ float sq_lo(float v, float eta_f) { return dn_nonneg(v - eta_f); }
+__device__ __forceinline__ float root_lo(float t)
 {
-    const float t = dn_nonneg(v - eta_f);
     return t > 0x1p-100f ? __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(t)) - 2u) : 0.f;
 }
+__device__ __forceinline__ float est_lo(float v, float eta_f) { return root_lo(sq_lo(v, eta_f)); }
 __device__ __forceinline__ float est_hi(float v, float eta_f)
 {
     const float t = up_nonneg(v + eta_f);
@@ -845,41 +841,67 @@ __device__ __forceinline__ float est_hi(float v, float eta_f)
     return __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(fmaxf(t, 0x1p-100f))) + 2u);
 }
 
-// Fold one chunk's result (m1 at slot s1, second m2) of group g into the
-// running best, when `on`.  gprev: minimum over the group's earlier chunks
-// (+inf for its first).  A tie of estimates can never be decided under the
-// error bound, so ties keep the earlier result.
-__device__ __forceinline__ void run_fold_part(Run &r, bool on, float m1, int s1, float m2, int g, float gprev,
-                                              bool track_og)
+// Running best of a point over BF16x3 chunk estimates, whose error bound
+// eta differs per chunk (it grows with the norms of the chunk's group).  The
+// best is chosen by estimate (bd at slot bs in group bg, with its chunk's
+// eta eb); every other estimate v enters as dn(v - eta), the square of its
+// lower bound before the root (sq_lo; root_lo is monotone, so minima carry
+// over): sec over all of them, bm2 over the best's group, ov (nearest other
+// group, for the L1 order only) over the other groups.
+struct RunB {
+    float bd, bdl, eb, sec, bm2, ov;
+    int bs, bg, og;
+};
+__device__ __forceinline__ void runb_init(RunB &r)
+{
+    r.bd = KP_INF;
+    r.bdl = KP_INF;
+    r.eb = 0.f;
+    r.sec = KP_INF;
+    r.bm2 = KP_INF;
+    r.ov = KP_INF;
+    r.bs = -1;
+    r.bg = -1;
+    r.og = -1;
+}
+// Fold one chunk of group g, when `on`: smallest estimate m1 at slot s1 with
+// squared lower bound l1, squared lower bound l2 of the chunk's second
+// estimate, the chunk's eta e, and gprev the squared lower bound of the
+// group's earlier chunks (+inf for its first).  A tie of estimates can never
+// be decided under the error bound, so ties keep the earlier result.
+__device__ __forceinline__ void runb_fold(RunB &r, bool on, float m1, float l1, int s1, float l2, float e, int g,
+                                          float gprev, bool track_og)
 {
     const bool nb = on && m1 < r.bd;
-    const float sec = nb ? fminf(r.bd, m2) : fminf(r.sec, m1);
-    const float bm2 = nb ? fminf(m2, gprev) : (g == r.bg ? fminf(r.bm2, m1) : r.bm2);
+    // the old best (and everything below it) becomes an other estimate
+    const float sec = nb ? fminf(fminf(r.bdl, r.sec), l2) : fminf(r.sec, l1);
+    const float bm2 = nb ? fminf(l2, gprev) : (g == r.bg ? fminf(r.bm2, l1) : r.bm2);
     if (track_og) {   // wave-uniform
         // nearest other group: the old best's group when a new group leads,
         // else this group when it comes closer than the current one
-        const float gm = fminf(gprev, m1);
+        const float gm = fminf(gprev, l1);
         const bool oo = nb && g != r.bg;
         const bool on2 = on && !nb && g != r.bg && gm < r.ov;
-        r.ov = oo ? r.bd : (on2 ? gm : r.ov);
+        r.ov = oo ? r.bdl : (on2 ? gm : r.ov);
         r.og = oo ? r.bg : (on2 ? g : r.og);
     }
     r.sec = on ? sec : r.sec;
     r.bm2 = on ? bm2 : r.bm2;
     r.bd = nb ? m1 : r.bd;
+    r.bdl = nb ? l1 : r.bdl;
+    r.eb = nb ? e : r.eb;
     r.bs = nb ? s1 : r.bs;
     r.bg = nb ? g : r.bg;
 }
 
 // BF16 decision under the error bound; writes the point's state and bound
 // fix-ups when the decision is certain, else reports it as uncertain with
-// U* (an upper bound on its true nearest distance).  The bounds on a
-// distance come from its estimate with est_lo / est_hi (eta_f: the point's
-// eta rounded up to FP32).
-__device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, float minnc, const Run &r,
-                                            float eta_f, float sdd, bool &moved, bool &amb, int &win, float &umin)
+// U* (an upper bound on its true nearest distance).  The upper bound on the
+// best distance comes from its estimate with est_hi under its chunk's eta.
+__device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, float minnc, const RunB &r,
+                                            float sdd, bool &moved, bool &amb, int &win, float &umin)
 {
-    const float Ub = est_hi(r.bd, eta_f), Ls = est_lo(r.sec, eta_f);
+    const float Ub = est_hi(r.bd, r.eb), Ls = root_lo(r.sec);
     amb = !(Ub < Ls);   // certain iff the best is below every other estimate
     moved = false;
     if (amb) {
@@ -890,7 +912,7 @@ __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dens
     PointState nsv;
     nsv.a = win;
     nsv.ga = pack_ga(P.slot_group[win], r.og);
-    P.lb[(size_t)pid * P.gs + r.bg] = store_lb(est_lo(r.bm2, eta_f), P.Sgd[r.bg]);
+    P.lb[(size_t)pid * P.gs + r.bg] = store_lb(root_lo(r.bm2), P.Sgd[r.bg]);
     nsv.u = store_u(Ub, P.Scd[win]);
     nsv.p = store_lb(fminf(minnc, Ls), sdd);
     P.st[pid] = nsv;
@@ -1253,6 +1275,7 @@ struct BlockLds {
     Visit vis[GMAX_BF16];           // the tile's visits (filtered iterations)
     int gst[GMAX_BF16], gsz[GMAX_BF16];
     float gsd[GMAX_BF16];           // Sg rounded down
+    float2 gcn[GMAX_BF16];          // (C, a C^2): C bounds the members' norms
 };
 template <int KS>
 struct StageRegs {
@@ -1423,7 +1446,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
 {
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
-    const float bmax = P.scal[0];
+    const Eta3 ek = mfma_eta3_coef(P.ldb);
     const float sdd = P.Sdud[1];
     const bool track_og = P.nk1 > P.kg;   // the L1 order uses the nearest other group
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
@@ -1433,6 +1456,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         L.gst[i] = P.gstart[i];
         L.gsz[i] = P.gsize[i];
         L.gsd[i] = P.Sgd[i];
+        L.gcn[i] = mfma_eta3_grp(ek, P.gcn[i]);
     }
     __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
@@ -1479,25 +1503,28 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const bool in = idx < count;
         const int pid = f_pid, a = f_a;
         const float xnp = f_xn, minnc = f_minnc;
-        const float eta_f = d2f_up(mfma_eta3(xnp, bmax, P.ldb));
+        const float2 eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
         PtFrag<KS> b;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) split8(f_v[ks], b.h[ks], b.l[ks]);
-        Run r;
-        run_init(r);
-        float gmin = KP_INF;   // running minimum of the group being visited
+        RunB r;
+        runb_init(r);
+        float gmin = KP_INF;   // squared lower bound of the group being visited, so far
         unsigned t_pairs = 0u, t_dist = 0u;   // this tile's counts (< 2^32)
         auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
             const unsigned pm = (unsigned)__popc(m);
             t_pairs += first ? pm : 0u;
             t_dist += pm * (unsigned)nreal;
             const bool mine = (m >> pt) & 1u;
+            const float2 gc = L.gcn[g];
+            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);   // the chunk's eta
             const float m1 = key_value(kk.k1);
+            const float l1 = sq_lo(m1, e), l2 = sq_lo(key_value(kk.k2), e);
             const float gprev = first ? KP_INF : gmin;
-            gmin = fminf(gprev, m1);
-            run_fold_part(r, mine, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev, track_og);
-            const float lbv = dn_nonneg(est_lo(gmin, eta_f) + sgd);   // offset form, rounded down
+            gmin = fminf(gprev, l1);
+            runb_fold(r, mine, m1, l1, slot0 + (int)(kk.k1 & 15u), l2, e, g, gprev, track_og);
+            const float lbv = dn_nonneg(root_lo(gmin) + sgd);   // offset form, rounded down
             // one unconditional store per chunk: lanes without a bound to
             // write send it to the workgroup's sink slot
             float *dst = (mine && quad == 0) ? P.lb + (size_t)pid * P.gs + g : sink;
@@ -1550,7 +1577,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const long long pos = DENSE ? (long long)pid : idx;
         if (in && quad == 0) {
             float umin = KP_INF;
-            decide_bf16(P, pid, DENSE, a, minnc, r, eta_f, sdd, moved, amb, win, umin);
+            decide_bf16(P, pid, DENSE, a, minnc, r, sdd, moved, amb, win, umin);
             // the recheck's inputs: the BF16 best slot and U*
             if (amb) P.ps4[pos] = make_float4(__int_as_float(r.bs), 0.f, umin, 0.f);
         }
@@ -2078,11 +2105,12 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
 {
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
-    const float bmax = P.scal[0];
+    const Eta3 ek = mfma_eta3_coef(P.ldb);
     for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
         L.gst[i] = P.gstart[i];
         L.gsz[i] = P.gsize[i];
         L.gsd[i] = 0.f;
+        L.gcn[i] = mfma_eta3_grp(ek, P.gcn[i]);
     }
     __syncthreads();
     ProbDev Pq = P;   // the query rows in place of the training points
@@ -2098,14 +2126,18 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's queries
-        Run r;
-        run_init(r);
+        const float2 eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
+        RunB r;
+        runb_init(r);
         float gmin = KP_INF;
         auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
+            const float2 gc = L.gcn[g];
+            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);
             const float m1 = key_value(kk.k1);
+            const float l1 = sq_lo(m1, e), l2 = sq_lo(key_value(kk.k2), e);
             const float gprev = first ? KP_INF : gmin;
-            gmin = fminf(gprev, m1);
-            run_fold_part(r, true, m1, slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), g, gprev, false);
+            gmin = fminf(gprev, l1);
+            runb_fold(r, true, m1, l1, slot0 + (int)(kk.k1 & 15u), l2, e, g, gprev, false);
         };
         auto skip = [&]() {};
         auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
@@ -2120,8 +2152,7 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         if (in && quad == 0) {
             // certain iff the best estimate's upper bound is below every
             // other estimate's lower bound
-            const float eta_f = d2f_up(mfma_eta3(xnp, bmax, P.ldb));
-            const float Ub = est_hi(r.bd, eta_f), Ls = est_lo(r.sec, eta_f);
+            const float Ub = est_hi(r.bd, r.eb), Ls = root_lo(r.sec);
             if (Ub < Ls && r.bs >= 0) labels[q] = P.perm[clamp_slot(P, r.bs)];
             else amb = true;
         }
