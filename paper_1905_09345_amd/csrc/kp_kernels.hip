@@ -1618,15 +1618,17 @@ __global__ __launch_bounds__(256) void kb_blk64(const ProbDev *__restrict__ prob
 
 
 // ================================================================ recheck
-// Eight lanes per uncertain point (32 points per workgroup).  Candidates:
-// every group whose lower bound is <= U*, an upper bound on the point's true
-// nearest distance, plus the old centroid when it was tracked separately;
-// every other centroid is provably farther than the nearest one.  Their
-// distances are recomputed in FP32 direct form on the FP32 point, which the
-// team holds in registers: lane t owns coordinates 4t + 32j .. 4t + 32j + 3,
-// sums its d/8 terms in coordinate order, then a three-level tree combines
-// the lanes (relative error below eps2_direct).  The point is decided on
-// those values (lowest original index on exact ties).
+// Eight lanes (a team) per uncertain point, 32 points per workgroup.
+// Candidates: every group whose lower bound is <= U*, an upper bound on the
+// point's true nearest distance; every other centroid is provably farther
+// than the nearest one.  Their distances are recomputed in FP32 direct form
+// on the FP32 point, which the team holds in registers: lane t owns
+// coordinates 4t + 32j .. 4t + 32j + 3, sums its d/8 terms in coordinate
+// order, then a three-level tree combines the lanes (relative error below
+// eps2_direct).  The point is decided on those values (lowest original index
+// on exact ties).  The candidate rows come straight from L2: staging the
+// union of a workgroup's candidate groups in LDS was measured slower (its
+// barriers serialise the teams, and most teams idle in most groups).
 constexpr int RT = 8;                 // lanes per point
 constexpr int RMAX = 64;              // candidate groups kept in LDS per point
 
@@ -1684,8 +1686,10 @@ __device__ __forceinline__ float team_d2(const float4 (&x)[NV], const float *__r
 template <int NV>
 __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, const int nblk_)
 {
-    __shared__ int rg[256 / RT][RMAX];
-    __shared__ float rm1[256 / RT][RMAX], rm2[256 / RT][RMAX];
+    constexpr int TPB = 256 / RT;   // teams per workgroup
+    __shared__ int rg[TPB][RMAX];
+    __shared__ float rm1[TPB][RMAX], rm2[TPB][RMAX];
+    __shared__ float sgu[GMAX_BF16];
     const int lane = lane_id();
     const int t = lane & (RT - 1);
     const int team = threadIdx.x / RT;
@@ -1695,27 +1699,39 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
     const long long n3 = list_len(P, CTR_L3);   // uncertain positions, listed by the distance kernel
     const long long mv0 = list_len(P, CTR_MV);  // update entries the distance kernel wrote before these
     const int last_pos = (int)(positions(P) - 1);  // counters read once: other waves update their line
-    const long long nteams = (long long)nblk_ * (blockDim.x / RT);
+    const long long nteams = (long long)nblk_ * TPB;
     const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
+    for (int g = threadIdx.x; g < P.g; g += blockDim.x) sgu[g] = P.Sgu[g];
+    __syncthreads();
+    const unsigned long long tlanes = 0xFFull << (lane & ~(RT - 1));   // this team's lanes
+    const unsigned long long below = tlanes & ((1ull << lane) - 1ull);  // ... below this lane
     unsigned long long n_moved = 0;
     for (long long it = 0; it < trips; ++it) {
-        const long long e3 = it * nteams + (long long)bid_ * (blockDim.x / RT) + team;
+        const long long e0 = it * nteams + (long long)bid_ * TPB;
+        const long long e3 = e0 + team;
         const bool live = e3 < n3;
         if (__ballot(live) == 0ull) continue;   // past the end of the list for this wave's eight teams
         const long long e = live ? (long long)max(min(P.L3[e3], last_pos), 0) : 0;
         const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
         const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
         const float4 pin = live ? P.ps4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const bool a_sep = false;
         float4 x[NV];
         const float *xrow = P.X + (size_t)pid * P.d;
+        if ((P.d & 3) == 0 && ((uintptr_t)P.X & 15) == 0) {   // rows of whole, aligned float4
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int i = 4 * t + 32 * j;
-            float v[4];
+            for (int j = 0; j < NV; ++j) {
+                const int i = 4 * t + 32 * j;
+                x[j] = (live && i < P.d) ? *(const float4 *)(xrow + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (live && i + q < P.d) ? xrow[i + q] : 0.f;
-            x[j] = make_float4(v[0], v[1], v[2], v[3]);
+            for (int j = 0; j < NV; ++j) {
+                const int i = 4 * t + 32 * j;
+                float v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (live && i + q < P.d) ? xrow[i + q] : 0.f;
+                x[j] = make_float4(v[0], v[1], v[2], v[3]);
+            }
         }
         // candidate threshold: the smaller of U* and an upper bound on the
         // FP32 direct-form distance to the BF16 pass's best centroid (either
@@ -1724,28 +1740,51 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         const int bslot = clamp_slot(P, __float_as_int(pin.x));
         const float umin = fminf(pin.z, dist_hi(team_d2<NV>(x, P.c32 + (size_t)bslot * P.ldc, P.ldc, t), eps2));
         float *lbrow = P.lb + (size_t)pid * P.gs;
-        // groups that may hold the nearest centroid
+        // groups that may hold the nearest centroid, in ascending order: the
+        // team reads the bounds in blocks of 32 groups, lane t groups
+        // 32 j + 4 t .. 32 j + 4 t + 3 as one float4, SB blocks in flight
         float minnr = KP_INF;
         int nR = 0;
         const int ng = live ? P.g : 0;
-        const int gpad = (P.g + RT - 1) / RT * RT;
-        for (int g0 = 0; g0 < gpad; g0 += RT) {
-            const int g = g0 + t;
-            bool inR = false;
-            if (g < ng) {
-                const float lbe = lb_now(lbrow[g], P.Sgu[g]);
-                inR = lbe <= umin;
-                if (!inR) minnr = fminf(minnr, lbe);
+        const int nb32 = (P.g + 31) / 32;
+        constexpr int SB = 4;
+        for (int j0 = 0; j0 < nb32; j0 += SB) {
+            float4 lv[SB];
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int gq = 32 * (j0 + b) + 4 * t;   // the row is padded to a multiple of 4
+                lv[b] = gq < ng ? *(const float4 *)(lbrow + gq) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            // (the loads of later steps do not depend on this one, so the
-            // compiler keeps several in flight)
-            const unsigned long long m = __ballot(inR);
-            const unsigned mt = (unsigned)((m >> (lane & ~(RT - 1))) & ((1u << RT) - 1u));
-            if (inR) {
-                const int pos = nR + __popc(mt & ((1u << t) - 1u));
-                if (pos < RMAX) rg[team][pos] = g;
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int gq = 32 * (j0 + b) + 4 * t;
+                const float lq[4] = {lv[b].x, lv[b].y, lv[b].z, lv[b].w};
+                bool in4[4];
+                int nbelow = 0, nteam = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int g = gq + q;
+                    bool inR = false;
+                    if (g < ng) {
+                        const float lbe = lb_now(lq[q], sgu[g]);
+                        inR = lbe <= umin;
+                        if (!inR) minnr = fminf(minnr, lbe);
+                    }
+                    in4[q] = inR;
+                    const unsigned long long m = __ballot(inR);
+                    nbelow += __popcll(m & below);
+                    nteam += __popcll(m & tlanes);
+                }
+                int pos = nR + nbelow;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (in4[q]) {
+                        if (pos < RMAX) rg[team][pos] = gq + q;
+                        ++pos;
+                    }
+                }
+                nR += nteam;
             }
-            nR += __popc(mt);
         }
         minnr = team_min(minnr);
         // more than RMAX candidate groups: examine every group (rare)
@@ -1803,20 +1842,12 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
                 }
             }
         }
-        const float d2a = team_d2<NV>(x, P.c32 + (size_t)(a_sep ? olda : 0) * P.ldc, P.ldc, t);
-        if (a_sep && before(P, d2a, olda, bd, bs)) {
-            bd = d2a;
-            bs = olda;
-        }
-        if (bs < 0) bs = olda >= 0 ? olda : 0;   // unreachable: the provisional winner's group is in R
+        if (bs < 0) bs = olda >= 0 ? olda : 0;   // unreachable: the provisional winner's group is a candidate
         const int gbest = P.slot_group[bs];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // lower bounds of the examined groups
         float minr = KP_INF;
         if (!overflow) {
-            for (int i = t; i < nscan; i += RT) {
+            for (int i = t; i < nR; i += RT) {
                 const int g = rg[team][i];
                 const float lbv = dist_lo(g == gbest ? rm2[team][i] : rm1[team][i], eps2);
                 lbrow[g] = store_lb(lbv, P.Sgd[g]);
@@ -1824,8 +1855,9 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             }
         } else {
             // second pass: the minimum of every group except the winner
-            for (int i = 0; i < nscan_w; ++i) {
-                const bool on = i < nscan;
+            const int nw2 = wave_max_i(overflow ? ng : 0);
+            for (int i = 0; i < nw2; ++i) {
+                const bool on = overflow && i < ng;
                 const int g = on ? i : 0;
                 const int s0 = P.gstart[g], ns = on ? P.gsize[g] : 0;
                 const int ns_w = wave_max_i(ns);
@@ -1844,13 +1876,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         }
         minr = team_min(minr);
         if (!live) continue;
-        float lbp = fminf(minnr, minr);
-        if (a_sep && bs != olda) {
-            const int ga = P.slot_group[olda];
-            const float va = fminf(lb_now(lbrow[ga], P.Sgu[ga]), dist_lo(d2a, eps2));
-            if (t == 0) lbrow[ga] = store_lb(va, P.Sgd[ga]);
-            lbp = fminf(lbp, va);
-        }
+        const float lbp = fminf(minnr, minr);
         if (t == 0) {
             PointState nsv;
             nsv.a = bs;
@@ -1859,10 +1885,8 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             nsv.ga = pack_ga(gbest, og);
             P.st[pid] = nsv;
             n_moved += bs != olda ? 1ull : 0ull;
-        }
-        // the centroid update's entry of this point, after the entries the
-        // distance kernel listed (-1: did not move)
-        if (t == 0) {
+            // the centroid update's entry of this point, after the entries
+            // the distance kernel listed (-1: did not move)
             const long long em = mv0 + e3;
             P.mv_pt[em] = pid;
             P.mv_old[em] = olda;
