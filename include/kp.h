@@ -85,7 +85,9 @@ typedef struct {
                                       replays) and around every replay
                                       (kp_stage_times); 0: none */
     int32_t chunk_depth;           /* BF16 mode: centroid chunks in flight per
-                                      workgroup, 1 or 3 (default 1) */
+                                      workgroup in the filtered distance pass,
+                                      1 or 3 (default 1; the dense first pass
+                                      always keeps 3) */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */

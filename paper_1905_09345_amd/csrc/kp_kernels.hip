@@ -2295,13 +2295,11 @@ static void launch_blk64_ks(const ProbDev &P, hipStream_t s, int grid)
 static void launch_blk64(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, bool dense)
 {
     const int grid = cap_grid((P.n + 63) / 64, cfg.grid_cap);
-    if (cfg.depth == 1) {
-        if (dense) launch_blk64_ks<true, 1>(P, s, grid);
-        else launch_blk64_ks<false, 1>(P, s, grid);
-    } else {
-        if (dense) launch_blk64_ks<true, 3>(P, s, grid);
-        else launch_blk64_ks<false, 3>(P, s, grid);
-    }
+    // the dense pass (every chunk for every tile) keeps three chunks in
+    // flight; the filtered pass takes the tuned depth
+    if (dense) launch_blk64_ks<true, 3>(P, s, grid);
+    else if (cfg.depth == 1) launch_blk64_ks<false, 1>(P, s, grid);
+    else launch_blk64_ks<false, 3>(P, s, grid);
 }
 
 static void launch_dense(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
@@ -2565,8 +2563,7 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
         KB_LAUNCH(TB_DENSE_F32 + 2, kb_dense_f32<32>, wthreads);
         KB_LAUNCH(TB_DENSE_F32 + 3, kb_dense_f32<64>, wthreads);
         KB_LAUNCH(TB_DENSE_F32 + 4, kb_dense_f32<128>, wthreads);
-        if (cfg.depth == 1) batch_blk64<true, 1>(B, s);
-        else batch_blk64<true, 3>(B, s);
+        batch_blk64<true, 3>(B, s);   // the dense pass keeps three chunks in flight
         break;
     case ST_GFILTER: KB_LAUNCH(TB_GF, kb_gfilter, 256); break;
     case ST_ASSIGN:
