@@ -54,6 +54,8 @@ def parse():
                     help="centroid chunks in flight per workgroup (0: library default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="workgroups per CU of the grid-stride launches (0: library default)")
+    ap.add_argument("--bound-codes", type=int, default=0, choices=[0, 1, 2],
+                    help="BF16 mode: 1 = FP32 group bounds, 2 = FP16 codes (0: library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip kp_autotune (untimed, before the contexts are made) and use the defaults")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -298,15 +300,16 @@ def traffic_of(kernel, workload):
 def tuned(args, KMeans, kp_tuning, spec):
     """Launch tuning of the measured runs: kp_autotune's pick unless disabled
     or fixed on the command line; timing on (stage events)."""
-    tun = kp_tuning(chunk_depth=args.depth, blocks_per_cu=args.blocks_per_cu)
-    if not args.no_autotune and not args.depth and not args.blocks_per_cu:
+    tun = kp_tuning(chunk_depth=args.depth, blocks_per_cu=args.blocks_per_cu, bound_codes=args.bound_codes)
+    if not args.no_autotune and not args.depth and not args.blocks_per_cu and not args.bound_codes:
         t0 = time.perf_counter()
         tun = KMeans.autotune(spec, iters=3)
-        log("autotune: chunk_depth=%d blocks_per_cu=%d (%.1f s)" % (tun.chunk_depth, tun.blocks_per_cu,
-                                                                    time.perf_counter() - t0))
+        log("autotune: chunk_depth=%d blocks_per_cu=%d bound_codes=%d (%.1f s)" % (
+            tun.chunk_depth, tun.blocks_per_cu, tun.bound_codes, time.perf_counter() - t0))
     tun.timing = 1
     tun.use_graph = -1 if args.plain else 1
-    TUNING.update(chunk_depth=tun.chunk_depth, blocks_per_cu=tun.blocks_per_cu, use_graph=tun.use_graph)
+    TUNING.update(chunk_depth=tun.chunk_depth, blocks_per_cu=tun.blocks_per_cu, use_graph=tun.use_graph,
+                  bound_codes=tun.bound_codes)
     return tun
 
 

@@ -88,6 +88,11 @@ typedef struct {
                                       workgroup in the filtered distance pass,
                                       1 or 3 (default 1; the dense first pass
                                       always keeps 3) */
+    int32_t bound_codes;           /* BF16 mode: per-(point, group) lower
+                                      bounds stored as 1 = FP32 (default) or
+                                      2 = FP16 codes rounded down (half the
+                                      bound bytes, bounds up to 2^-10 looser;
+                                      kp_workspace_bytes shrinks accordingly) */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */
@@ -186,7 +191,8 @@ kp_status kp_destroy(kp_ctx *ctx);
 /* Autotuner of the launch shapes (the batched form picks its tiles and
  * workgroups per problem from it).  Runs `iters` iterations (>= 2) of the
  * problems from their initial centroids under each candidate tuning --
- * centroid chunks in flight {1, 3} x workgroups per CU {8, 16, 32} -- in the
+ * bound storage {FP32, FP16} (BF16 problems) x centroid chunks in flight
+ * {1, 3} x workgroups per CU {8, 16, 32} -- in the
  * caller's workspace (kp_workspace_bytes of the same problems), timing each
  * run with HIP events on `stream`, and writes the fastest to *best_host
  * (use_graph 1, timing 0).  Synchronises `stream`; leaves no ctx behind.

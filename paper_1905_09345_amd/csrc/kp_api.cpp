@@ -39,13 +39,13 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
     size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, gcn, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, stats, iter, sink;
+        cursor1, ctr, stats, iter, sink, lbsc;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
     size_t nk1max;   // keys of the L1 order for kgmax slots
 };
 
-Plan plan_problem(const kp_problem &p)
+Plan plan_problem(const kp_problem &p, bool lb16)
 {
     Plan o;
     const size_t n = (size_t)p.n;
@@ -59,7 +59,7 @@ Plan plan_problem(const kp_problem &p)
     o.ldb = (d + 31) / 32 * 32;
     if (o.ldb == 160) o.ldb = 192;   // BF16 tiles take 1, 2, 3, 4, 6 or 8 steps of 32
     if (o.ldb == 224) o.ldb = 256;
-    o.gs = (g + 3) / 4 * 4;
+    o.gs = bf ? (g + 7) / 8 * 8 : (g + 3) / 4 * 4;   // bound row stride (16-byte rows)
     const size_t kgm = (size_t)o.kgmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -69,7 +69,7 @@ Plan plan_problem(const kp_problem &p)
     };
     o.xn = take(bf ? n * 4 : 0);
     o.st = take(n * sizeof(kp::PointState));
-    o.lb = take(n * (size_t)o.gs * 4);
+    o.lb = take(n * (size_t)o.gs * (bf && lb16 ? 2 : 4));   // FP16 codes or FP32
     o.c32 = take(kgm * o.ldc * 4);
     o.cb = take(bf ? kgm * o.ldb * 2 : 0);
     o.cbl = take(bf ? kgm * o.ldb * 2 : 0);
@@ -114,6 +114,7 @@ Plan plan_problem(const kp_problem &p)
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
     o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
+    o.lbsc = take(16);
     o.bytes = off;
     return o;
 }
@@ -139,6 +140,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
         }
         if (t->chunk_depth != 0 && t->chunk_depth != 1 && t->chunk_depth != 3) {
             set_error("chunk_depth=%d not 0, 1 or 3", t->chunk_depth);
+            return false;
+        }
+        if (t->bound_codes < 0 || t->bound_codes > 2) {
+            set_error("bound_codes=%d outside 0..2", t->bound_codes);
             return false;
         }
         if (t->use_graph < -1 || t->use_graph > 1) {
@@ -302,7 +307,7 @@ struct kp_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<kp::ProbDev> P;
     kp::Batch batch;                           // count > 1: batched launches
-    kp::LaunchCfg cfg{4, 4096, 1};
+    kp::LaunchCfg cfg{4, 4096, 1, false};
     int use_graph = 1;
     int iters = 0;
     bool poisoned = false;
@@ -349,7 +354,8 @@ size_t kp_workspace_bytes(const kp_problem *problems, int32_t count, const kp_tu
 {
     if (!validate(problems, count, tuning)) return 0;
     size_t total = 0;
-    for (int i = 0; i < count; ++i) total += plan_problem(problems[i]).bytes;
+    const bool lb16 = tuning && tuning->bound_codes == 2;
+    for (int i = 0; i < count; ++i) total += plan_problem(problems[i], lb16).bytes;
     return total + batch_header_bytes(count);
 }
 
@@ -378,8 +384,9 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
     }
     std::vector<Plan> plans;
     size_t need = 0;
+    const bool lb16 = tuning && tuning->bound_codes == 2;
     for (int i = 0; i < count; ++i) {
-        plans.push_back(plan_problem(problems[i]));
+        plans.push_back(plan_problem(problems[i], lb16));
         need += plans.back().bytes;
     }
     const size_t problem_bytes = need;
@@ -400,6 +407,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         if (tuning->waves_per_block) ctx->cfg.waves = tuning->waves_per_block;
         if (tuning->blocks_per_cu) ctx->cfg.grid_cap = 256 * tuning->blocks_per_cu;
         if (tuning->chunk_depth) ctx->cfg.depth = tuning->chunk_depth;
+        ctx->cfg.lb16 = tuning->bound_codes == 2;
         if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
         ctx->timing = tuning->timing;
     }
@@ -429,12 +437,15 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.ldb = o.ldb;
         P.gs = o.gs;
         P.prec = p.precision;
+        P.lb16 = (p.precision == KP_PREC_BF16_RECHECK && lb16) ? 1 : 0;
         P.maxgs = G.maxgs;
         P.nk1 = G.kg * kp::l1_buckets(p.n, G.kg, G.g);
         P.X = p.points_dev;
         P.xn = (float *)(base + o.xn);
         P.st = (kp::PointState *)(base + o.st);
         P.lb = (float *)(base + o.lb);
+        P.lbh = (uint16_t *)(base + o.lb);
+        P.lbsc = (float *)(base + o.lbsc);
         P.c32 = (float *)(base + o.c32);
         P.cb = (uint16_t *)(base + o.cb);
         P.cbl = (uint16_t *)(base + o.cbl);
@@ -837,11 +848,15 @@ kp_status kp_autotune(const kp_problem *problems, int32_t count, void *workspace
     KP_HIP(hipEventCreate(&e1));
     std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(e1, hipEventDestroy);
     static const int depths[2] = {1, 3}, bpcs[3] = {8, 16, 32};
+    bool any_bf = false;
+    for (int i = 0; i < count; ++i) any_bf = any_bf || problems[i].precision == KP_PREC_BF16_RECHECK;
     float best_ms = -1.f;
     kp_tuning cur{};
-    for (int di = 0; di < 2; ++di)
+    for (int ci = 1; ci <= (any_bf ? 2 : 1); ++ci)
+        for (int di = 0; di < 2; ++di)
         for (int bi = 0; bi < 3; ++bi) {
             kp_tuning t{};
+            t.bound_codes = ci;
             t.chunk_depth = depths[di];
             t.blocks_per_cu = bpcs[bi];
             t.use_graph = 1;

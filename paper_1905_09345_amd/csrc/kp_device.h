@@ -5,7 +5,8 @@
 //   xn     n       FP32  ||X_i||^2 (BF16 mode; the BF16 split of a point is
 //                        formed on the fly in LDS, ldb = roundup(d, 32))
 //   st     n       16 B  PointState: assigned slot and two bounds
-//   lb     n x gs  FP32  group-level lower bounds, gs = roundup(g, 4)
+//   lb     n x gs  group-level lower bounds: FP32, gs = roundup(g, 4) (FP32 mode);
+//                 FP32 or FP16 codes, gs = roundup(g, 8) (BF16 mode)
 //   centroids in "slot" order: the members of group q occupy slots
 //   gstart[q] .. gstart[q] + gsize[q] - 1 in ascending original index, and the
 //   group is padded with empty slots to a multiple of 16 so that every
@@ -75,7 +76,10 @@ struct ProbDev {
     const float *X;
     float *xn;
     PointState *st;
-    float *lb;
+    float *lb;                // FP32 mode: lower bounds per (point, group), row stride gs
+    uint16_t *lbh;            // BF16 mode with lb16: the same as FP16 codes (lb16_enc), row stride gs
+    int lb16;                 // BF16 mode: 1 = bounds stored as FP16 codes, 0 = FP32
+    float *lbsc;              // BF16 mode: [0] 2^e and [1] 2^-e of the FP16 codes, [2] bits of max ||x||^2
     float *c32;
     uint16_t *cb, *cbl;       // BF16 split of c32: cb = bf16(c), cbl = bf16(c - cb)
     float *cn;                // ||c32||^2 (BF16 mode; +inf for padding)
@@ -167,6 +171,27 @@ __device__ __forceinline__ bool group_open(float ub, float sgu, float v)
 {
     const float s = ub + sgu;
     return !(__uint_as_float(__float_as_uint(s) + 1u) < v);
+}
+
+// ------------------------------------------------- FP16 lower-bound codes
+// BF16 mode can store each offset-form lower bound v as an FP16 code: the
+// FP16 number at or below max(v, 0) * 2^-e, with 2^e a power-of-two scale
+// chosen from the data at init so that distances land near 2^10.  Half the
+// bytes of FP32 in the bound rows that the group filter and the recheck
+// stream, at up to 2^-10 (relative) looser bounds.  The code truncates the
+// FP32 significand (toward zero), flushes values below the FP16 normal
+// range to 0 and saturates values above it at the largest finite FP16;
+// decoding is exact.  A decoded code therefore never exceeds the bound it
+// came from (raising a negative bound to 0 is valid: distances are >= 0).
+__device__ __forceinline__ uint16_t lb16_enc(float v, float inv)
+{
+    const float w = fmaxf(v * inv, 0.f);   // NaN gives 0; the product is exact above FP32 subnormals
+    const int c = (int)(__float_as_uint(w) >> 13) - (112 << 10);   // exponent rebias 127 -> 15
+    return (uint16_t)min(max(c, 0), 0x7BFF);
+}
+__device__ __forceinline__ float lb16_dec(unsigned short b, float sc)
+{
+    return (float)__builtin_bit_cast(_Float16, b) * sc;
 }
 
 // ------------------------------------------------------- error bounds

@@ -70,16 +70,22 @@ __device__ __forceinline__ int batch_problem(const int *__restrict__ tab, int co
 }
 
 // ===================================================================== prep
-// ||x||^2 of every point (FP64 sum of the FP32 coordinates, rounded to FP32).
+// ||x||^2 of every point (FP64 sum of the FP32 coordinates, rounded to FP32),
+// and their maximum (lbsc[2], zero before; the FP32 bits of non-negative
+// values order as integers).
 __device__ __forceinline__ void b_prep(const ProbDev &P, const int bid_, const int nblk_)
 {
     const int64_t stride = (int64_t)nblk_ * blockDim.x;
+    float mx = 0.f;
     for (int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x; i < P.n; i += stride) {
         const float *x = P.X + i * P.d;
         double s = 0.0;
         for (int j = 0; j < P.d; ++j) s += (double)x[j] * x[j];
         P.xn[i] = (float)s;
+        mx = fmaxf(mx, (float)s);
     }
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane_id() == 0 && mx > 0.f) atomicMax((unsigned *)&P.lbsc[2], __float_as_uint(mx));
 }
 __global__ __launch_bounds__(256) void k_prep(ProbDev P)
 {
@@ -204,6 +210,18 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
         __syncthreads();
     }
     if (tid == 0) {
+        if (first && P.prec) {
+            // scale of the FP16 bound codes: a distance is at most
+            // R = max ||x|| + max ||c0||; R lands in [2^10, 2^11)
+            double cm = 0.0;
+            for (int s = 0; s < P.kg; ++s)
+                if (P.perm[s] >= 0) cm = fmax(cm, (double)P.cn[s]);
+            const double R = sqrt((double)P.lbsc[2]) + sqrt(cm);
+            int e = R > 0.0 ? ilogb(R) - 10 : 0;
+            e = max(-100, min(100, e));
+            P.lbsc[0] = ldexpf(1.f, e);
+            P.lbsc[1] = ldexpf(1.f, -e);
+        }
         const double sd = first ? 0.0 : (P.Sd[0] + red[0]) * up;
         P.Sd[0] = sd;
         P.Sdud[0] = d2f_up(sd);
@@ -912,7 +930,9 @@ __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dens
     PointState nsv;
     nsv.a = win;
     nsv.ga = pack_ga(P.slot_group[win], r.og);
-    P.lb[(size_t)pid * P.gs + r.bg] = store_lb(root_lo(r.bm2), P.Sgd[r.bg]);
+    const float sv = store_lb(root_lo(r.bm2), P.Sgd[r.bg]);
+    if (P.lb16) P.lbh[(size_t)pid * P.gs + r.bg] = lb16_enc(sv, P.lbsc[1]);
+    else P.lb[(size_t)pid * P.gs + r.bg] = sv;
     nsv.u = store_u(Ub, P.Scd[win]);
     nsv.p = store_lb(fminf(minnc, Ls), sdd);
     P.st[pid] = nsv;
@@ -1091,6 +1111,7 @@ __global__ __launch_bounds__(WAVE * GT_WAVES) void kb_group_test(const ProbDev *
 // tile, the visit list of the distance kernel: every group open for some
 // point of the tile, in group order, with the four waves' 16-bit point masks
 // (g, m0 | m1 << 16, m2 | m3 << 16, 0), and its length.
+template <bool LB16>   // bounds stored as FP16 codes
 __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ float gsu[GMAX_BF16];
@@ -1102,6 +1123,8 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const long long count = list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
+    const float lsc = P.lbsc[0];
+    constexpr bool lb16 = LB16;
     int rb = 0;   // mask buffer, alternating over every round of the launch
     for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
         const long long pos = tl * 64 + 16 * wv + pt;
@@ -1115,22 +1138,41 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
             ga = min(max(e.w, 0), P.g - 1);
         }
         const float *lbrow = P.lb + (size_t)pid * P.gs;
+        const uint16_t *lbrow16 = P.lbh + (size_t)pid * P.gs;
         int4 *vis = P.tlist + (size_t)tl * P.g;
         float cm = KP_INF;
         int nv = 0;
         for (int g0 = 0; g0 < P.g; g0 += WAVE, rb ^= 1) {
             const int gq = g0 + 16 * quad;
             float v[16], sg[16];
+            if constexpr (lb16) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int gi = gq + 8 * i;   // gs is padded to 8
+                    const uint4 h = (in && gi < P.g) ? *(const uint4 *)(lbrow16 + gi) : make_uint4(0u, 0u, 0u, 0u);
+                    const unsigned hw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        v[8 * i + 2 * q] = lb16_dec((unsigned short)(hw[q] & 0xFFFFu), lsc);
+                        v[8 * i + 2 * q + 1] = lb16_dec((unsigned short)(hw[q] >> 16), lsc);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int gi = gq + 4 * i;
+                    const float4 v4 = (in && gi < P.g) ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[4 * i] = v4.x;
+                    v[4 * i + 1] = v4.y;
+                    v[4 * i + 2] = v4.z;
+                    v[4 * i + 3] = v4.w;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int gi = gq + 4 * i;   // gs and the LDS table are padded to 4
+                const int gi = gq + 4 * i;   // the LDS table is padded to 4
                 const bool ok = in && gi < P.g;
-                const float4 v4 = ok ? *(const float4 *)(lbrow + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
                 const float4 s4 = ok ? *(const float4 *)(gsu + gi) : make_float4(0.f, 0.f, 0.f, 0.f);
-                v[4 * i] = v4.x;
-                v[4 * i + 1] = v4.y;
-                v[4 * i + 2] = v4.z;
-                v[4 * i + 3] = v4.w;
                 sg[4 * i] = s4.x;
                 sg[4 * i + 1] = s4.y;
                 sg[4 * i + 2] = s4.z;
@@ -1171,13 +1213,15 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
         if (wv == 0 && lane == 0) P.tcnt[tl] = nv;
     }
 }
-__global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter(P, (int)blockIdx.x, (int)gridDim.x); }
+template <bool LB16>
+__global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter<LB16>(P, (int)blockIdx.x, (int)gridDim.x); }
+template <bool LB16>
 __global__ __launch_bounds__(256) void kb_gfilter(const ProbDev *__restrict__ probs, const int *__restrict__ tab,
                                                   int count)
 {
     const int pi = batch_problem(tab, count);
     const ProbDev P = probs[pi];
-    b_gfilter(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+    b_gfilter<LB16>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
 }
 
 // ================================================== distance kernels (phase 2)
@@ -1449,6 +1493,8 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     const Eta3 ek = mfma_eta3_coef(P.ldb);
     const float sdd = P.Sdud[1];
     const bool track_og = P.nk1 > P.kg;   // the L1 order uses the nearest other group
+    const bool lb16 = P.lb16 != 0;        // bounds as FP16 codes
+    const float lsc = P.lbsc[0], linv = P.lbsc[1];
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
@@ -1527,10 +1573,15 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             const float lbv = dn_nonneg(root_lo(gmin) + sgd);   // offset form, rounded down
             // one unconditional store per chunk: lanes without a bound to
             // write send it to the workgroup's sink slot
-            float *dst = (mine && quad == 0) ? P.lb + (size_t)pid * P.gs + g : sink;
-            *dst = lbv;
+            if (lb16) {
+                uint16_t *dst = (mine && quad == 0) ? P.lbh + (size_t)pid * P.gs + g : (uint16_t *)sink;
+                *dst = lb16_enc(lbv, linv);
+            } else {
+                float *dst = (mine && quad == 0) ? P.lb + (size_t)pid * P.gs + g : sink;
+                *dst = lbv;
+            }
         };
-        auto skip = [&]() { *sink = 0.f; };
+        auto skip = [&]() { *(uint16_t *)sink = 0; };
         if (DENSE) {
             // every group, in order
             auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
@@ -1683,7 +1734,7 @@ __device__ __forceinline__ float team_d2(const float4 (&x)[NV], const float *__r
     return team_dist<NV>(x, c4);
 }
 
-template <int NV>
+template <int NV, bool LB16>   // LB16: bounds stored as FP16 codes
 __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, const int nblk_)
 {
     constexpr int TPB = 256 / RT;   // teams per workgroup
@@ -1701,6 +1752,8 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
     const int last_pos = (int)(positions(P) - 1);  // counters read once: other waves update their line
     const long long nteams = (long long)nblk_ * TPB;
     const long long trips = (n3 + nteams - 1) / nteams;   // the same for every lane of the grid
+    const float lsc = P.lbsc[0], linv = P.lbsc[1];
+    constexpr bool lb16 = LB16;
     for (int g = threadIdx.x; g < P.g; g += blockDim.x) sgu[g] = P.Sgu[g];
     __syncthreads();
     const unsigned long long tlanes = 0xFFull << (lane & ~(RT - 1));   // this team's lanes
@@ -1740,45 +1793,57 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         const int bslot = clamp_slot(P, __float_as_int(pin.x));
         const float umin = fminf(pin.z, dist_hi(team_d2<NV>(x, P.c32 + (size_t)bslot * P.ldc, P.ldc, t), eps2));
         float *lbrow = P.lb + (size_t)pid * P.gs;
+        uint16_t *lbrow16 = P.lbh + (size_t)pid * P.gs;
         // groups that may hold the nearest centroid, in ascending order: the
-        // team reads the bounds in blocks of 32 groups, lane t groups
-        // 32 j + 4 t .. 32 j + 4 t + 3 as one float4, SB blocks in flight
+        // team reads the bounds in blocks of 64 groups, lane t groups
+        // 64 j + 8 t .. 64 j + 8 t + 7 (16 bytes of FP16 codes or 32 of
+        // FP32), SB blocks in flight
         float minnr = KP_INF;
         int nR = 0;
         const int ng = live ? P.g : 0;
-        const int nb32 = (P.g + 31) / 32;
-        constexpr int SB = 4;
-        for (int j0 = 0; j0 < nb32; j0 += SB) {
-            float4 lv[SB];
+        const int nb64 = (P.g + 63) / 64;
+        constexpr int SB = 2;
+        for (int j0 = 0; j0 < nb64; j0 += SB) {
+            uint4 lv[SB][2];
+            const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
-                const int gq = 32 * (j0 + b) + 4 * t;   // the row is padded to a multiple of 4
-                lv[b] = gq < ng ? *(const float4 *)(lbrow + gq) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int gq = 64 * (j0 + b) + 8 * t;   // the row is padded to a multiple of 8
+                if constexpr (lb16) {
+                    lv[b][0] = gq < ng ? *(const uint4 *)(lbrow16 + gq) : z4;
+                    lv[b][1] = z4;
+                } else {
+                    lv[b][0] = gq < ng ? *(const uint4 *)(lbrow + gq) : z4;
+                    lv[b][1] = gq + 4 < ng ? *(const uint4 *)(lbrow + gq + 4) : z4;
+                }
             }
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
-                const int gq = 32 * (j0 + b) + 4 * t;
-                const float lq[4] = {lv[b].x, lv[b].y, lv[b].z, lv[b].w};
-                bool in4[4];
+                const int gq = 64 * (j0 + b) + 8 * t;
+                const unsigned hw[8] = {lv[b][0].x, lv[b][0].y, lv[b][0].z, lv[b][0].w,
+                                        lv[b][1].x, lv[b][1].y, lv[b][1].z, lv[b][1].w};
+                unsigned in8 = 0u;
                 int nbelow = 0, nteam = 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     const int g = gq + q;
                     bool inR = false;
                     if (g < ng) {
-                        const float lbe = lb_now(lq[q], sgu[g]);
+                        const float v = lb16 ? lb16_dec((unsigned short)(hw[q >> 1] >> (16 * (q & 1))), lsc)
+                                             : __uint_as_float(hw[q]);
+                        const float lbe = lb_now(v, sgu[g]);
                         inR = lbe <= umin;
                         if (!inR) minnr = fminf(minnr, lbe);
                     }
-                    in4[q] = inR;
+                    in8 |= inR ? 1u << q : 0u;
                     const unsigned long long m = __ballot(inR);
                     nbelow += __popcll(m & below);
                     nteam += __popcll(m & tlanes);
                 }
                 int pos = nR + nbelow;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (in4[q]) {
+                for (int q = 0; q < 8; ++q) {
+                    if ((in8 >> q) & 1u) {
                         if (pos < RMAX) rg[team][pos] = gq + q;
                         ++pos;
                     }
@@ -1850,7 +1915,9 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
             for (int i = t; i < nR; i += RT) {
                 const int g = rg[team][i];
                 const float lbv = dist_lo(g == gbest ? rm2[team][i] : rm1[team][i], eps2);
-                lbrow[g] = store_lb(lbv, P.Sgd[g]);
+                const float sv = store_lb(lbv, P.Sgd[g]);
+                if (lb16) lbrow16[g] = lb16_enc(sv, linv);
+                else lbrow[g] = sv;
                 minr = fminf(minr, lbv);
             }
         } else {
@@ -1869,7 +1936,9 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
                 }
                 if (on) {
                     const float lbv = dist_lo(m, eps2);
-                    if (t == 0) lbrow[g] = store_lb(lbv, P.Sgd[g]);
+                    const float sv = store_lb(lbv, P.Sgd[g]);
+                    if (t == 0 && lb16) lbrow16[g] = lb16_enc(sv, linv);
+                    if (t == 0 && !lb16) lbrow[g] = sv;
                     minr = fminf(minr, lbv);
                 }
             }
@@ -1896,17 +1965,17 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
     // one atomic per lane that decided points (lane 0 of each team)
     if (n_moved) atomicAdd(&P.ctr[CTR_MOVED], n_moved);
 }
-template <int NV>
+template <int NV, bool LB16>
 __global__ __launch_bounds__(256) void k_recheck(ProbDev P)
 {
-    b_recheck<NV>(P, (int)blockIdx.x, (int)gridDim.x);
+    b_recheck<NV, LB16>(P, (int)blockIdx.x, (int)gridDim.x);
 }
-template <int NV>
+template <int NV, bool LB16>
 __global__ __launch_bounds__(256) void kb_recheck(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
 {
     const int pi = batch_problem(tab, count);
     const ProbDev P = probs[pi];
-    b_recheck<NV>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+    b_recheck<NV, LB16>(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
 }
 
 
@@ -2268,6 +2337,14 @@ static inline int cap_grid(long long want, int cap)
     if (want < 1) want = 1;
     return (int)(want < cap ? want : cap);
 }
+template <bool LB16>
+static void launch_recheck(const ProbDev &P, hipStream_t s, int blocks)
+{
+    if (P.ldc <= 32) hipLaunchKernelGGL((k_recheck<1, LB16>), dim3(blocks), dim3(256), 0, s, P);
+    else if (P.ldc <= 64) hipLaunchKernelGGL((k_recheck<2, LB16>), dim3(blocks), dim3(256), 0, s, P);
+    else if (P.ldc <= 128) hipLaunchKernelGGL((k_recheck<4, LB16>), dim3(blocks), dim3(256), 0, s, P);
+    else hipLaunchKernelGGL((k_recheck<8, LB16>), dim3(blocks), dim3(256), 0, s, P);
+}
 
 hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
 {
@@ -2406,15 +2483,14 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
     }
     case ST_ASSIGN_DENSE: launch_dense(P, s, cfg); break;
     case ST_GFILTER:
-        hipLaunchKernelGGL(k_gfilter, dim3(cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
+        if (P.lb16) hipLaunchKernelGGL(k_gfilter<true>, dim3(cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
+        else hipLaunchKernelGGL(k_gfilter<false>, dim3(cap_grid(((P.n + 15) / 16 + 3) / 4, cfg.grid_cap)), dim3(256), 0, s, P);
         break;
     case ST_ASSIGN: launch_survivors(P, s, cfg); break;
     case ST_RECHECK: {
         const int blocks = cap_grid((P.n + 31) / 32, cfg.grid_cap);
-        if (P.ldc <= 32) hipLaunchKernelGGL(k_recheck<1>, dim3(blocks), dim3(256), 0, s, P);
-        else if (P.ldc <= 64) hipLaunchKernelGGL(k_recheck<2>, dim3(blocks), dim3(256), 0, s, P);
-        else if (P.ldc <= 128) hipLaunchKernelGGL(k_recheck<4>, dim3(blocks), dim3(256), 0, s, P);
-        else hipLaunchKernelGGL(k_recheck<8>, dim3(blocks), dim3(256), 0, s, P);
+        if (P.lb16) launch_recheck<true>(P, s, blocks);
+        else launch_recheck<false>(P, s, blocks);
         break;
     }
     case ST_UPDATE: launch_update(P, s, cfg); break;
@@ -2565,7 +2641,10 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
         KB_LAUNCH(TB_DENSE_F32 + 4, kb_dense_f32<128>, wthreads);
         batch_blk64<true, 3>(B, s);   // the dense pass keeps three chunks in flight
         break;
-    case ST_GFILTER: KB_LAUNCH(TB_GF, kb_gfilter, 256); break;
+    case ST_GFILTER:
+        if (cfg.lb16) KB_LAUNCH(TB_GF, kb_gfilter<true>, 256);
+        else KB_LAUNCH(TB_GF, kb_gfilter<false>, 256);
+        break;
     case ST_ASSIGN:
         KB_LAUNCH(TB_GT, kb_group_test, WAVE * GT_WAVES);
         KB_LAUNCH(TB_TILE_F32 + 0, kb_tile_f32<8>, wthreads);
@@ -2577,10 +2656,17 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
         else batch_blk64<false, 3>(B, s);
         break;
     case ST_RECHECK:
-        KB_LAUNCH(TB_RECHECK + 0, kb_recheck<1>, 256);
-        KB_LAUNCH(TB_RECHECK + 1, kb_recheck<2>, 256);
-        KB_LAUNCH(TB_RECHECK + 2, kb_recheck<4>, 256);
-        KB_LAUNCH(TB_RECHECK + 3, kb_recheck<8>, 256);
+        if (cfg.lb16) {
+            KB_LAUNCH(TB_RECHECK + 0, (kb_recheck<1, true>), 256);
+            KB_LAUNCH(TB_RECHECK + 1, (kb_recheck<2, true>), 256);
+            KB_LAUNCH(TB_RECHECK + 2, (kb_recheck<4, true>), 256);
+            KB_LAUNCH(TB_RECHECK + 3, (kb_recheck<8, true>), 256);
+        } else {
+            KB_LAUNCH(TB_RECHECK + 0, (kb_recheck<1, false>), 256);
+            KB_LAUNCH(TB_RECHECK + 1, (kb_recheck<2, false>), 256);
+            KB_LAUNCH(TB_RECHECK + 2, (kb_recheck<4, false>), 256);
+            KB_LAUNCH(TB_RECHECK + 3, (kb_recheck<8, false>), 256);
+        }
         break;
     case ST_UPDATE:
         KB_LAUNCH(TB_HIST, kb_hist, 256);

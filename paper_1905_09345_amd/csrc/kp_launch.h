@@ -10,6 +10,7 @@ struct LaunchCfg {
     int waves;      // waves of 64 lanes per workgroup of the assignment kernels
     int grid_cap;   // upper bound on workgroups of grid-stride kernels
     int depth;      // centroid chunks in flight per workgroup (BF16 mode): 1 or 3
+    bool lb16;      // BF16 mode: group bounds stored as FP16 codes
 };
 
 // Per-point BF16 shadow and norms, initial centroid rows, drift rings at t=0.

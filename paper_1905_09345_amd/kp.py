@@ -31,7 +31,8 @@ class kp_problem(ctypes.Structure):
 
 class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32), ("chunk_depth", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32), ("chunk_depth", ctypes.c_int32),
+                ("bound_codes", ctypes.c_int32)]
 
 
 class kp_iter_stats(ctypes.Structure):

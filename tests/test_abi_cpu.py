@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 20
+    assert ctypes.sizeof(kp.kp_tuning) == 24 and kp.kp_tuning.bound_codes.offset == 20
     assert ctypes.sizeof(kp.kp_stage_time) == 40
     assert ctypes.sizeof(kp.kp_iter_stats) == 64 and kp.kp_iter_stats.point_filter_fail.offset == 8
 
@@ -63,7 +63,8 @@ def test_invalid_problem_rejected(bad):
 
 
 @pytest.mark.parametrize("field,value", [("timing", 7), ("chunk_depth", 2), ("chunk_depth", -1),
-                                         ("waves_per_block", 5), ("use_graph", 3)])
+                                         ("waves_per_block", 5), ("use_graph", 3), ("bound_codes", 3),
+                                         ("bound_codes", -1)])
 def test_invalid_tuning_rejected(field, value):
     t = kp.kp_tuning(**{field: value})
     assert kp.kp_workspace_bytes([_prob()], t) == 0
@@ -72,6 +73,16 @@ def test_invalid_tuning_rejected(field, value):
 def test_valid_tuning_accepted():
     for depth in (0, 1, 3):
         assert kp.kp_workspace_bytes([_prob()], kp.kp_tuning(chunk_depth=depth)) > 0
+
+
+def test_fp16_bound_codes_shrink_bf16_workspace():
+    # BF16 mode: n x roundup(g, 8) bounds of 2 instead of 4 bytes; FP32 mode keeps FP32 bounds
+    bf = _prob(precision=1, n=4096, g=10)
+    fp32 = kp.kp_workspace_bytes([bf], kp.kp_tuning(bound_codes=1))
+    fp16 = kp.kp_workspace_bytes([bf], kp.kp_tuning(bound_codes=2))
+    assert fp32 == kp.kp_workspace_bytes([bf]) and fp32 - fp16 >= 4096 * 16 * 2 - 256
+    f = _prob(precision=0)
+    assert kp.kp_workspace_bytes([f], kp.kp_tuning(bound_codes=2)) == kp.kp_workspace_bytes([f])
 
 
 def test_init_argument_errors_before_device_use():

@@ -43,6 +43,14 @@ def test_batch_of_small_problems(depth):
     run_steplocked_batch([_problem(*sp) for sp in specs], 6, tuning=kp_tuning(chunk_depth=depth), check_every=2)
 
 
+def test_batch_fp16_bound_codes():
+    """The batched form with its group bounds stored as FP16 codes."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    specs = [(40 + i, 3_000 + 97 * i, 32 * (1 + i % 4), 48 + 8 * i, "bf16") for i in range(6)]
+    print("CASE batch-fp16-codes", specs, flush=True)
+    run_steplocked_batch([_problem(*sp) for sp in specs], 6, tuning=kp_tuning(bound_codes=2), check_every=2)
+
+
 def test_batch_graph_and_timing():
     """Batched iterations replayed from a captured graph, stages timed inside it."""
     import torch

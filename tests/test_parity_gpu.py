@@ -116,6 +116,29 @@ def test_graph_and_plain_launches(use_graph):
     run_steplocked(P.X, P.C0, P.g, "fp32", 6, tuning=kp_tuning(use_graph=use_graph))
 
 
+@pytest.mark.parametrize("case", ["c3", "c5", "long", "d16"])
+def test_fp16_bound_codes(case):
+    """Group bounds stored as FP16 codes rounded down (looser, never above the
+    true bound): the same exact result as the oracle."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    t = kp_tuning(bound_codes=2)
+    _print_case("fp16-codes", case=case)
+    if case == "c3":
+        P = datagen.make_config(3, n=30_011)
+        run_steplocked(P.X, P.C0, P.g, "bf16", 6, tuning=t)
+    elif case == "c5":
+        P = datagen.make_config(5, n=40_000)
+        run_steplocked(P.X, P.C0, P.g, "bf16", 4, tuning=t)
+    elif case == "long":
+        P = datagen.make_config(2, n=20_011)
+        run_steplocked(P.X, P.C0, P.g, "bf16", 45, tuning=t, check_every=3)
+    else:
+        rng = np.random.default_rng(16)
+        X = datagen.gaussian_mixture(rng, 9_001, 16, 64)
+        C0 = datagen.kmeanspp(rng, X, 64, sample=2000)
+        run_steplocked(X, C0, 7, "bf16", 8, tuning=t)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_long_run(prec):
     """Many iterations: the cumulative drift sums keep growing while bounds stay valid."""
