@@ -262,22 +262,32 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def bound_layout(P):
+    """Bytes per stored group bound and bound row stride: BF16 problems keep
+    FP32 bounds or FP16 codes (kp_tuning.bound_codes = 2), rows padded to 8;
+    FP32 problems FP32 bounds, rows padded to 4."""
+    if P.precision == "bf16":
+        return (2 if TUNING.get("bound_codes") == 2 else 4), (P.g + 7) // 8 * 8
+    return 4, (P.g + 3) // 4 * 4
+
+
 def assign_bytes(P, s):
     """Algorithmic HBM bytes of one filtered assignment launch (BF16 mode): per
     entry of L1 its FP32 row, the sorted entry, its norm, its open-group mask
     words and closed-group bound (from the group filter), the new state and the
     update entries; per visited (point, group) pair the new bound; per
     uncertain point its recheck record and list entry."""
+    bsz, _ = bound_layout(P)
     per_point = 4 * P.d + 16 + 4 + 4 * ((P.g + 31) // 32) + 4 + 16 + 12
-    return s["point_filter_fail"] * per_point + s["pairs"] * 4 + s["rechecks"] * 20
+    return s["point_filter_fail"] * per_point + s["pairs"] * bsz + s["rechecks"] * 20
 
 
 def gfilter_bytes(P, s):
     """Algorithmic HBM bytes of one group-filter launch: per entry of L1 the
-    sorted entry, the point's bound row (g FP32, padded to 4), and the written
-    mask words and closed-group bound."""
-    gs = (P.g + 3) // 4 * 4
-    return s["point_filter_fail"] * (16 + 4 * gs + 4 * ((P.g + 31) // 32) + 4)
+    sorted entry, the point's bound row (FP32 or FP16 codes, padded), and the
+    written mask words and closed-group bound."""
+    bsz, gs = bound_layout(P)
+    return s["point_filter_fail"] * (16 + bsz * gs + 4 * ((P.g + 31) // 32) + 4)
 
 
 def traffic_of(kernel, workload):
@@ -293,6 +303,9 @@ def traffic_of(kernel, workload):
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     ent = rec.get(kernel, {})
     if ent.get("source_sha256") != digest or ent.get("workload") != workload:
+        return None
+    tun = ent.get("tuning", {})
+    if any(TUNING.get(k) != v for k, v in tun.items()):   # counters taken under another launch tuning
         return None
     return ent.get("bytes_per_launch")
 
@@ -431,15 +444,15 @@ def roofline_of(stage, a, P, st):
         return dict(kernel="k_blk64 (filtered iteration: BF16x3 distances of the open groups)", bound="hbm",
                     achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     traffic=traffic_of("k_blk64_filtered", wl),
-                    work_per_launch="%.4g B (per L1 entry 4d+52+4*ceil(g/32) B, per pair 4 B, per recheck 20 B)"
-                    % byts, ms_per_launch=ms_per_launch)
+                    work_per_launch="%.4g B (per L1 entry 4d+52+4*ceil(g/32) B, per pair %d B, per recheck 20 B)"
+                    % (byts, bound_layout(P)[0]), ms_per_launch=ms_per_launch)
     if stage == "group_filter":
         filt = [s for s in st if not s["dense"]]
         byts = sum(gfilter_bytes(P, s) for s in filt) / max(len(filt), 1)
         ach = byts / (ms_per_launch * 1e-3) / 1e9
         return dict(kernel="k_gfilter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=traffic_of("k_gfilter", wl),
-                    work_per_launch="%.4g B (per L1 entry 16+4*gs+4*ceil(g/32)+4 B)" % byts,
+                    work_per_launch="%%.4g B (per L1 entry 16+%d*gs+4*ceil(g/32)+4 B)" % bound_layout(P)[0] % byts,
                     ms_per_launch=ms_per_launch)
     if stage == "assign_dense":
         flops = 2.0 * P.n * P.k * P.d
@@ -455,10 +468,14 @@ def roofline_of(stage, a, P, st):
                     unit="TFLOP/s", frac=ach / peak, traffic=None,
                     work_per_launch="2*N*K*D = %.4g flop" % flops, ms_per_launch=ms_per_launch)
     if stage == "bound_filter":
-        byts = 16.0 * P.n
+        # every point's state read, an L1 entry written per point that fails
+        filt = [s for s in st if not s["dense"]]
+        fails = sum(s["point_filter_fail"] for s in filt) / max(len(filt), 1)
+        byts = 16.0 * P.n + 16.0 * fails
         ach = byts / (ms_per_launch * 1e-3) / 1e9
         return dict(kernel="k_bound_filter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None, work_per_launch="16 B/point x N = %.4g B" % byts,
+                    frac=ach / HBM_PEAK_GBS, traffic=None,
+                    work_per_launch="16 B/point x N + 16 B per L1 entry = %.4g B" % byts,
                     ms_per_launch=ms_per_launch)
     return dict(kernel=stage, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                 ms_per_launch=ms_per_launch)
