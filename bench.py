@@ -263,12 +263,13 @@ def main():
 
 
 def bound_layout(P):
-    """Bytes per stored group bound and bound row stride: BF16 problems keep
-    FP32 bounds or FP16 codes (kp_tuning.bound_codes = 2), rows padded to 8;
-    FP32 problems FP32 bounds, rows padded to 4."""
+    """Bytes per stored group bound and the bounds a row holds that the
+    algorithm needs (g; the padding of the stored rows is not counted): BF16
+    problems keep FP32 bounds or FP16 codes (kp_tuning.bound_codes = 2), FP32
+    problems FP32 bounds."""
     if P.precision == "bf16":
-        return (2 if TUNING.get("bound_codes") == 2 else 4), (P.g + 7) // 8 * 8
-    return 4, (P.g + 3) // 4 * 4
+        return (2 if TUNING.get("bound_codes") == 2 else 4), P.g
+    return 4, P.g
 
 
 def assign_bytes(P, s):
@@ -284,8 +285,8 @@ def assign_bytes(P, s):
 
 def gfilter_bytes(P, s):
     """Algorithmic HBM bytes of one group-filter launch: per entry of L1 the
-    sorted entry, the point's bound row (FP32 or FP16 codes, padded), and the
-    written mask words and closed-group bound."""
+    sorted entry, the point's g bounds (FP32 or FP16 codes), and the written
+    mask words and closed-group bound."""
     bsz, gs = bound_layout(P)
     return s["point_filter_fail"] * (16 + bsz * gs + 4 * ((P.g + 31) // 32) + 4)
 
@@ -452,7 +453,7 @@ def roofline_of(stage, a, P, st):
         ach = byts / (ms_per_launch * 1e-3) / 1e9
         return dict(kernel="k_gfilter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=traffic_of("k_gfilter", wl),
-                    work_per_launch="%%.4g B (per L1 entry 16+%d*gs+4*ceil(g/32)+4 B)" % bound_layout(P)[0] % byts,
+                    work_per_launch="%%.4g B (per L1 entry 16+%d*g+4*ceil(g/32)+4 B)" % bound_layout(P)[0] % byts,
                     ms_per_launch=ms_per_launch)
     if stage == "assign_dense":
         flops = 2.0 * P.n * P.k * P.d

@@ -59,7 +59,10 @@ Plan plan_problem(const kp_problem &p, bool lb16)
     o.ldb = (d + 31) / 32 * 32;
     if (o.ldb == 160) o.ldb = 192;   // BF16 tiles take 1, 2, 3, 4, 6 or 8 steps of 32
     if (o.ldb == 224) o.ldb = 256;
-    o.gs = bf ? (g + 7) / 8 * 8 : (g + 3) / 4 * 4;   // bound row stride (16-byte rows)
+    // bound row stride: FP32 mode 16-byte rows; BF16 mode 128-byte rows (one
+    // cache line per 64 FP16 codes or 32 FP32 bounds, so that a row's reads
+    // touch no line it does not need)
+    o.gs = bf ? (lb16 ? (g + 63) / 64 * 64 : (g + 31) / 32 * 32) : (g + 3) / 4 * 4;
     const size_t kgm = (size_t)o.kgmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {

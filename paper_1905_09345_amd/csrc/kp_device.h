@@ -6,7 +6,7 @@
 //                        formed on the fly in LDS, ldb = roundup(d, 32))
 //   st     n       16 B  PointState: assigned slot and two bounds
 //   lb     n x gs  group-level lower bounds: FP32, gs = roundup(g, 4) (FP32 mode);
-//                 FP32 or FP16 codes, gs = roundup(g, 8) (BF16 mode)
+//                 FP32 or FP16 codes in 128-byte rows (BF16 mode)
 //   centroids in "slot" order: the members of group q occupy slots
 //   gstart[q] .. gstart[q] + gsize[q] - 1 in ascending original index, and the
 //   group is padded with empty slots to a multiple of 16 so that every

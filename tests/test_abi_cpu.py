@@ -76,11 +76,14 @@ def test_valid_tuning_accepted():
 
 
 def test_fp16_bound_codes_shrink_bf16_workspace():
-    # BF16 mode: n x roundup(g, 8) bounds of 2 instead of 4 bytes; FP32 mode keeps FP32 bounds
-    bf = _prob(precision=1, n=4096, g=10)
+    # BF16 mode: 128-byte bound rows of roundup(g, 32) FP32 bounds or roundup(g, 64)
+    # FP16 codes; FP32 mode keeps its FP32 bounds
+    n, g = 4096, 100
+    bf = _prob(precision=1, n=n, g=g, k=1024)
     fp32 = kp.kp_workspace_bytes([bf], kp.kp_tuning(bound_codes=1))
     fp16 = kp.kp_workspace_bytes([bf], kp.kp_tuning(bound_codes=2))
-    assert fp32 == kp.kp_workspace_bytes([bf]) and fp32 - fp16 >= 4096 * 16 * 2 - 256
+    want = n * (128 * 4 - 128 * 2)
+    assert fp32 == kp.kp_workspace_bytes([bf]) and abs((fp32 - fp16) - want) <= 256
     f = _prob(precision=0)
     assert kp.kp_workspace_bytes([f], kp.kp_tuning(bound_codes=2)) == kp.kp_workspace_bytes([f])
 
