@@ -184,46 +184,21 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(P.X).to(dev)
     C0d = torch.from_numpy(P.C0).to(dev)
-    tun = tuned(args, KMeans, kp_tuning, [(Xd, C0d, P.g, prec, P.seed)])
-    runs = []
-    for i in range(args.warmup + args.steps):
-        runs.append(KMeans([(Xd, C0d, P.g, prec, P.seed)], tuning=tun))
-    torch.cuda.synchronize()
-    log("contexts ready: %d" % len(runs))
-    for km in runs[:args.warmup]:
-        km.iterate(P.iters)
-    torch.cuda.synchronize()
-    log("warmup done")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record()
-    for km in runs[args.warmup:]:
-        km.iterate(P.iters)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    el = max(wall, gpu_s)
+    spec = [(Xd, C0d, P.g, prec, P.seed)]
+    tun = tuned(args, KMeans, kp_tuning, spec)
+    el, agg, timed, dom, last = run_steps(args, torch, KMeans, kp_tuning, spec, tun, P.iters)
     value = P.n * P.iters * args.steps / el
-    log("timed: %d steps, %.3f ms/step (events %.3f ms/step)" % (args.steps, el / args.steps * 1e3,
-                                                                   gpu_s / args.steps * 1e3))
-
     # per-stage GPU time (HIP events the library recorded on its stream)
-    stages = [km.stage_times() for km in runs[args.warmup:]]
-    names = stages[0].keys()
-    agg = {nm: dict(ms=sum(s[nm]["ms"] for s in stages) / args.steps,
-                    launches=sum(s[nm]["launches"] for s in stages) / args.steps) for nm in names}
-    st = runs[-1].stats()
+    st = last.stats()
     if args.stats:
         for s in st:
             log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
                 "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
-    # the dominant kernel stage (the whole-replay entry is a sum of stages)
-    dom = max((nm for nm in agg if nm != "filtered_iter"), key=lambda nm: agg[nm]["ms"])
-    roofline = roofline_of(dom, agg[dom], P, st)
-    serve = serving(torch, runs[-1], Xd)
+    # the dominant kernel stage, timed inside the timed region
+    roofline = roofline_of(dom, timed[dom], P, st)
+    serve = serving(torch, last, Xd)
     log("serving: %d queries in %.3f ms (%.3g queries/s), plain FP32 argmin %.3f ms" % (
         serve["queries"], serve["ms"], serve["value"], serve["plain_fp32_ms"]))
     others = {}
@@ -231,7 +206,7 @@ def main():
         if nm in agg and nm != dom:
             r = roofline_of(nm, agg[nm], P, st)
             others[nm] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
-    del runs
+    last.close()
     torch.cuda.empty_cache()
 
     baseline = None
@@ -256,6 +231,7 @@ def main():
         "plain_fp32_lloyd": baseline,
         "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
         "stage_ms_per_step": {nm: round(a["ms"], 4) for nm, a in agg.items()},
+        "stage_ms_source": "warmup runs with every stage timed" if args.warmup else "the timed runs",
         "filter": {"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"]]
                    for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)},
     }
@@ -327,6 +303,62 @@ def tuned(args, KMeans, kp_tuning, spec):
     return tun
 
 
+def run_steps(args, torch, KMeans, kp_tuning, spec, tun, T):
+    """W warmup runs with events around every stage (the per-stage breakdown,
+    untimed), then K timed runs with events around the dominant stage only:
+    its launches are what the roofline divides by, and no other stage pays
+    for instrumentation inside the timed region.  Every run is a fresh
+    context (made outside the timed region) iterated T times.  Returns the
+    elapsed seconds, the breakdown, the timed runs' stage times, the
+    dominant stage and the last run."""
+    from paper_1905_09345_amd.kp import STAGES
+
+    def with_stages(mask):
+        t = kp_tuning(**{f: getattr(tun, f) for f, _ in kp_tuning._fields_})
+        t.timing_stages = mask
+        return t
+
+    def aggregate(runs):
+        stages = [km.stage_times() for km in runs]
+        return {nm: dict(ms=sum(x[nm]["ms"] for x in stages) / len(runs),
+                         launches=sum(x[nm]["launches"] for x in stages) / len(runs)) for nm in stages[0]}
+
+    breakdown = None
+    mask = 0
+    if args.warmup > 0:
+        warm = [KMeans(spec, tuning=with_stages(0)) for _ in range(args.warmup)]
+        for km in warm:
+            km.iterate(T)
+        torch.cuda.synchronize()
+        breakdown = aggregate(warm)
+        for km in warm:
+            km.close()
+        dom = max((nm for nm in breakdown if nm != "filtered_iter"), key=lambda nm: breakdown[nm]["ms"])
+        mask = 1 << STAGES.index(dom)
+        log("warmup done (stage breakdown; timed runs time %s only)" % dom)
+    runs = [KMeans(spec, tuning=with_stages(mask)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    log("contexts ready: %d" % len(runs))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    for km in runs:
+        km.iterate(T)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    timed = aggregate(runs)
+    if breakdown is None:
+        breakdown = timed
+    dom = max((nm for nm in breakdown if nm != "filtered_iter"), key=lambda nm: breakdown[nm]["ms"])
+    log("timed: %d steps, %.3f ms/step (events %.3f ms/step)" % (args.steps, max(wall, gpu_s) / args.steps * 1e3,
+                                                                   gpu_s / args.steps * 1e3))
+    for km in runs[:-1]:
+        km.close()
+    return max(wall, gpu_s), breakdown, timed, dom, runs[-1]
+
+
 TUNING = {}
 
 
@@ -343,44 +375,24 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
     Cd = [torch.from_numpy(p.C0).to(dev) for p in probs]
     spec = [(Xd[i], Cd[i], p.g, p.precision, p.seed) for i, p in enumerate(probs)]
     tun = tuned(args, KMeans, kp_tuning, spec)
-    runs = [KMeans(spec, tuning=tun) for _ in range(args.warmup + args.steps)]
-    torch.cuda.synchronize()
-    log("contexts ready: %d (%.1f s)" % (len(runs), time.perf_counter() - t0))
-    for km in runs[:args.warmup]:
-        km.iterate(T)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record()
-    for km in runs[args.warmup:]:
-        km.iterate(T)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    el = max(wall, ev0.elapsed_time(ev1) / 1e3)
+    el, agg, timed, dom, km = run_steps(args, torch, KMeans, kp_tuning, spec, tun, T)
     value = ntot * T * args.steps / el
-    log("timed: %d steps, %.3f ms/step" % (args.steps, el / args.steps * 1e3))
-    stages = [km.stage_times() for km in runs[args.warmup:]]
-    agg = {nm: dict(ms=sum(s[nm]["ms"] for s in stages) / args.steps,
-                    launches=sum(s[nm]["launches"] for s in stages) / args.steps) for nm in stages[0]}
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
-    dom = max((nm for nm in agg if nm != "filtered_iter"), key=lambda nm: agg[nm]["ms"])
-    km = runs[-1]
     roofline = None
     if dom == "assign":
         byts = 0.0
         for i, p in enumerate(probs):
             filt = [s for s in km.stats(i) if not s["dense"]]
             byts += sum(assign_bytes(p, s) for s in filt) / max(len(filt), 1)
-        ms = agg[dom]["ms"] / max(agg[dom]["launches"], 1e-9)
+        ms = timed[dom]["ms"] / max(timed[dom]["launches"], 1e-9)   # timed inside the timed region
         ach = byts / (ms * 1e-3) / 1e9
         roofline = dict(kernel="kb_blk64 (filtered iteration, all problems)", bound="hbm", achieved=ach,
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
                         work_per_launch="%.4g B" % byts, ms_per_launch=ms)
     else:
         roofline = dict(kernel=dom, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                        ms_per_launch=agg[dom]["ms"] / max(agg[dom]["launches"], 1e-9))
+                        ms_per_launch=timed[dom]["ms"] / max(timed[dom]["launches"], 1e-9))
     others = {}
     if "group_filter" in agg and dom != "group_filter" and agg["group_filter"]["launches"] > 0:
         byts = 0.0
@@ -392,7 +404,8 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
         ach = byts / (ms * 1e-3) / 1e9
         others["group_filter"] = dict(kernel="kb_gfilter (all problems)", bound="hbm", achieved=ach,
                                       peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
-    del runs, km
+    km.close()
+    del km
     torch.cuda.empty_cache()
     baseline = None
     if not args.no_baseline:

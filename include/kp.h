@@ -93,6 +93,13 @@ typedef struct {
                                       2 = FP16 codes rounded down (half the
                                       bound bytes, bounds up to 2^-10 looser;
                                       kp_workspace_bytes shrinks accordingly) */
+    int32_t timing_stages;         /* with timing = 1: bit s brackets stage s
+                                      with events, s = 0 "begin", 1
+                                      "bound_filter", 2 "l1_sort", 3
+                                      "assign_dense", 4 "group_filter", 5
+                                      "assign", 6 "recheck", 7 "update", 8
+                                      "centroids"; 0: every stage.  Whole
+                                      replays are always timed */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */

@@ -153,6 +153,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
             set_error("use_graph=%d outside -1..1", t->use_graph);
             return false;
         }
+        if (t->timing_stages < 0 || t->timing_stages >= (1 << kp::ST_COUNT)) {
+            set_error("timing_stages=%d outside 0..%d", t->timing_stages, (1 << kp::ST_COUNT) - 1);
+            return false;
+        }
         if (t->timing < 0 || t->timing > 1) {
             set_error("timing=%d outside 0..1", t->timing);
             return false;
@@ -304,6 +308,7 @@ struct StageTimer {
 struct kp_ctx {
     int count = 0;
     int timing = 0;
+    unsigned timed_stages = ~0u;   // bit s: stage s is bracketed by events when timing is on
     StageTimer timer;
     int device = 0;
     hipStream_t user = nullptr, own = nullptr;
@@ -413,6 +418,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         ctx->cfg.lb16 = tuning->bound_codes == 2;
         if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
         ctx->timing = tuning->timing;
+        if (tuning->timing_stages) ctx->timed_stages = (unsigned)tuning->timing_stages;
     }
     KP_HIP(hipGetDevice(&ctx->device));
     KP_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
@@ -554,19 +560,20 @@ static hipError_t launch_all(kp_ctx *ctx, bool dense)
     for (int i = 0; i < n; ++i) {
         StageTimer::Rec r;
         hipError_t e;
-        if (ctx->timing && (e = ctx->timer.begin(sts[i], ctx->own, r)) != hipSuccess) return e;
+        const bool timed = ctx->timing && ((ctx->timed_stages >> sts[i]) & 1u);
+        if (timed && (e = ctx->timer.begin(sts[i], ctx->own, r)) != hipSuccess) return e;
         if ((e = launch_call(ctx, sts[i], dense)) != hipSuccess) return e;
-        if (ctx->timing && (e = ctx->timer.end(ctx->own, r)) != hipSuccess) return e;
+        if (timed && (e = ctx->timer.end(ctx->own, r)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 // Captures one filtered iteration of every problem into ctx->graph.  With
 // timing on, each stage is captured into a graph of its own and the
-// iteration graph chains them as child graphs between event-record nodes
-// (placeholder events, re-pointed before each replay); if the runtime
-// refuses that, the graph is captured in one piece and only the whole
-// replay is timed.
+// iteration graph chains them as child graphs, the timed stages between
+// event-record nodes (placeholder events, re-pointed before each replay); if
+// the runtime refuses that, the graph is captured in one piece and only the
+// whole replay is timed.
 static hipError_t capture_plain(kp_ctx *ctx)
 {
     hipError_t e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal);
@@ -609,8 +616,9 @@ static hipError_t capture_timed(kp_ctx *ctx, const char **where)
         const int n = iteration_calls(ctx, false, sts);
         for (int i = 0; i < n; ++i) {
             hipEvent_t a = nullptr, b = nullptr;
+            const bool timed = (ctx->timed_stages >> sts[i]) & 1u;
             *where = "event-record node";
-            if ((e = add_event(a)) != hipSuccess) return e;
+            if (timed && (e = add_event(a)) != hipSuccess) return e;
             *where = "stage capture";
             if ((e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
             e = launch_call(ctx, sts[i], false);
@@ -623,10 +631,11 @@ static hipError_t capture_timed(kp_ctx *ctx, const char **where)
             }
             *where = "child graph node";
             hipGraphNode_t cn = nullptr;
-            e = hipGraphAddChildGraphNode(&cn, g, &last, 1, sg);
+            e = hipGraphAddChildGraphNode(&cn, g, last ? &last : nullptr, last ? 1 : 0, sg);
             (void)hipGraphDestroy(sg);   // the node holds its own copy
             if (e != hipSuccess) return e;
             last = cn;
+            if (!timed) continue;
             *where = "event-record node";
             if ((e = add_event(b)) != hipSuccess) return e;
             ctx->ev_stage.push_back(sts[i]);

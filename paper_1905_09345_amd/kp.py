@@ -32,7 +32,12 @@ class kp_problem(ctypes.Structure):
 class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32), ("chunk_depth", ctypes.c_int32),
-                ("bound_codes", ctypes.c_int32)]
+                ("bound_codes", ctypes.c_int32), ("timing_stages", ctypes.c_int32)]
+
+
+# stage indices of kp_tuning.timing_stages
+STAGES = ("begin", "bound_filter", "l1_sort", "assign_dense", "group_filter", "assign", "recheck", "update",
+          "centroids")
 
 
 class kp_iter_stats(ctypes.Structure):

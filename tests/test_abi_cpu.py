@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 24 and kp.kp_tuning.bound_codes.offset == 20
+    assert ctypes.sizeof(kp.kp_tuning) == 28 and kp.kp_tuning.bound_codes.offset == 20
+    assert kp.kp_tuning.timing_stages.offset == 24
     assert ctypes.sizeof(kp.kp_stage_time) == 40
     assert ctypes.sizeof(kp.kp_iter_stats) == 64 and kp.kp_iter_stats.point_filter_fail.offset == 8
 
@@ -64,7 +65,7 @@ def test_invalid_problem_rejected(bad):
 
 @pytest.mark.parametrize("field,value", [("timing", 7), ("chunk_depth", 2), ("chunk_depth", -1),
                                          ("waves_per_block", 5), ("use_graph", 3), ("bound_codes", 3),
-                                         ("bound_codes", -1)])
+                                         ("bound_codes", -1), ("timing_stages", 512), ("timing_stages", -1)])
 def test_invalid_tuning_rejected(field, value):
     t = kp.kp_tuning(**{field: value})
     assert kp.kp_workspace_bytes([_prob()], t) == 0

@@ -139,6 +139,19 @@ def test_fp16_bound_codes(case):
         run_steplocked(X, C0, 7, "bf16", 8, tuning=t)
 
 
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_fp16_bound_codes_extreme_scales(scale):
+    """FP16 bound codes on data scaled far from 1: the code scale follows the
+    data (distances land near 2^10), so the bounds stay valid and useful."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    rng = np.random.default_rng(77)
+    X = (datagen.gaussian_mixture(rng, 12_001, 32, 48) * scale).astype(np.float32)
+    C0 = datagen.kmeanspp(rng, X, 48, sample=3000)
+    _print_case("fp16-codes-scale", scale=scale)
+    r = run_steplocked(X, C0, 5, "bf16", 8, tuning=kp_tuning(bound_codes=2))
+    assert r["stats"][-1]["pairs"] < 12_001 * 5   # the group filter still prunes
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_long_run(prec):
     """Many iterations: the cumulative drift sums keep growing while bounds stay valid."""
