@@ -278,13 +278,15 @@ def traffic_of(kernel, workload):
     import hashlib
     src = os.path.join(ROOT, "paper_1905_09345_amd", "csrc", "kp_kernels.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    ent = rec.get(kernel, {})
-    if ent.get("source_sha256") != digest or ent.get("workload") != workload:
-        return None
-    tun = ent.get("tuning", {})
-    if any(TUNING.get(k) != v for k, v in tun.items()):   # counters taken under another launch tuning
-        return None
-    return ent.get("bytes_per_launch")
+    for key, ent in rec.items():   # entries "<kernel>@<tuning>", one per profiled launch tuning
+        if key.split("@")[0] != kernel:
+            continue
+        if ent.get("source_sha256") != digest or ent.get("workload") != workload:
+            continue
+        if any(TUNING.get(k) != v for k, v in ent.get("tuning", {}).items()):
+            continue   # counters taken under another launch tuning
+        return ent.get("bytes_per_launch")
+    return None
 
 
 def tuned(args, KMeans, kp_tuning, spec):
