@@ -81,9 +81,9 @@ typedef struct {
     int32_t use_graph;             /* 1 (default): replay iterations from a
                                       captured hipGraph; -1: plain launches */
     int32_t timing;                /* 1: record HIP events on the ctx's stream
-                                      around every stage (also inside graph
-                                      replays) and around every replay
-                                      (kp_stage_times); 0: none */
+                                      around every stage of timing_stages
+                                      (also inside graph replays) and around
+                                      every replay (kp_stage_times); 0: none */
     int32_t chunk_depth;           /* BF16 mode: centroid chunks in flight per
                                       workgroup in the filtered distance pass,
                                       1 or 3 (default 1; the dense first pass
