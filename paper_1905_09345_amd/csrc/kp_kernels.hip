@@ -6,13 +6,18 @@
 //                   point-level lower bound brought to this iteration; the
 //                   points where ub < lbp fails form list L1  [point-level filter]
 //   k_key_hist, k_scan, k_l1_scatter
-//                   L1 sorted by assigned centroid, so that a 64-point tile
-//                   shares its surviving groups
-//   k_assign_*      for the points of L1: tighten ub to the distance to the
-//                   assigned centroid, retest, then test every group's lower
-//                   bound against ub and compute the distances of the
-//                   surviving (point, group) pairs; new assignment and bounds
-//                                          [group-level filter + distance calculator]
+//                   L1 sorted by assigned centroid (then by a bucket of the
+//                   nearest other group), so that a 64-point tile shares its
+//                   surviving groups
+//   k_gfilter / k_group_test
+//                   every group's lower bound of each point of L1 tested
+//                   against its ub brought forward (its own group always
+//                   open); per tile of 64 points, the list of open groups
+//                                                     [group-level filter]
+//   k_blk64 / k_tile_f32
+//                   distances of the surviving (point, group) pairs (BF16x3
+//                   on the matrix cores, or FP32 direct form); new
+//                   assignment and bounds              [distance calculator]
 //   k_recheck       (BF16 mode) re-decide in FP32 direct form the points whose
 //                   BF16 decision is not certain under the error bound
 //   k_hist, k_scan, k_scatter, k_segsum
@@ -20,8 +25,8 @@
 //                   their coordinates into FP64 centroid sums    [centroid update]
 //   k_centroids     new means (FP64), their FP32 / BF16 copies, drifts
 //   k_drift         per-group and global maximum drift, cumulative sums
-// Iteration 1 replaces the filter, the sort and the survivor form of
-// k_assign_* by the dense form (every distance).  The two filters and the
+// Iteration 1 replaces the filters, the sort and the survivor form of the
+// distance kernels by their dense form (every distance).  The two filters and the
 // distance calculator are the three parts the paper names (Section 1); the
 // result is that of standard K-means (Abstract).
 #include "kp_device.h"
