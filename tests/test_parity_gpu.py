@@ -183,6 +183,33 @@ def test_stage_times():
         assert t["assign"]["ms"] > 0
 
 
+def test_stage_times_of_selected_stages():
+    """kp_tuning.timing_stages: only the selected stages carry events (plus
+    the whole replays), and the results are those of an untimed run."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning, STAGES
+    P = datagen.make_config(3, n=10_000)
+    _print_case("timing-mask")
+    X, C = torch.from_numpy(P.X).cuda(), torch.from_numpy(P.C0).cuda()
+    labels = []
+    for use_graph in (1, -1):
+        km = KMeans([(X, C, P.g, "bf16")], tuning=kp_tuning(timing=1, use_graph=use_graph,
+                                                           timing_stages=1 << STAGES.index("assign")))
+        km.iterate(4)
+        t = km.stage_times()
+        labels.append(km.assign().cpu().numpy())
+        km.close()
+        assert set(t) <= {"assign", "filtered_iter"}, sorted(t)
+        assert t["assign"]["launches"] == 3 and t["assign"]["ms"] > 0
+    km = KMeans([(X, C, P.g, "bf16")])
+    km.iterate(4)
+    ref = km.assign().cpu().numpy()
+    km.close()
+    for lab in labels:
+        assert (lab == ref).all()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n", [5, 17, 41, 63, 64, 65, 112, 129])
 def test_tail_tiles(prec, n):
