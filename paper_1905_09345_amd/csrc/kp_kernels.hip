@@ -1499,7 +1499,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     const float sdd = P.Sdud[1];
     const bool track_og = P.nk1 > P.kg;   // the L1 order uses the nearest other group
     const bool lb16 = P.lb16 != 0;        // bounds as FP16 codes
-    const float lsc = P.lbsc[0], linv = P.lbsc[1];
+    const float linv = P.lbsc[1];
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
