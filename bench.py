@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP32 Lloyd comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU seconds the oracle sample is sized for (it tends to land at about 0.6 of this)")
     ap.add_argument("--stats", action="store_true", help="print per-iteration filter statistics")
     ap.add_argument("--plain", action="store_true",
                     help="plain launches instead of graph replays")
@@ -140,11 +141,19 @@ def cpu_baseline(P, target_s):
     import oracle
     threads = oracle.threads()
     C = P.C0.astype(np.float64)
+
+    def one_iteration(m):
+        t0 = time.perf_counter()
+        lab, _ = oracle.assign(P.X[:m], C)
+        oracle.update(P.X[:m], lab, C)
+        return max(time.perf_counter() - t0, 1e-6)
+
+    # size the sample from a probe of about a second (a tiny probe is dominated
+    # by the thread pool's start and undersizes it)
     probe = min(P.n, 2000)
-    t0 = time.perf_counter()
-    lab, _ = oracle.assign(P.X[:probe], C)
-    oracle.update(P.X[:probe], lab, C)
-    dt = max(time.perf_counter() - t0, 1e-6)
+    dt = one_iteration(probe)
+    probe = int(min(P.n, max(probe, probe * 1.0 / dt)))
+    dt = one_iteration(probe)
     m = int(min(P.n, max(probe, probe * target_s / dt)))
     t0 = time.perf_counter()
     lab, _ = oracle.assign(P.X[:m], C)
