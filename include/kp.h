@@ -200,7 +200,8 @@ kp_status kp_destroy(kp_ctx *ctx);
  * problems from their initial centroids under each candidate tuning --
  * bound storage {FP32, FP16} (BF16 problems) x centroid chunks in flight
  * {1, 3} x workgroups per CU {8, 16, 32} -- in the
- * caller's workspace (kp_workspace_bytes of the same problems), timing each
+ * caller's workspace (kp_workspace_bytes of the same problems with a NULL
+ * tuning, the FP32-bound size), timing each
  * run with HIP events on `stream`, and writes the fastest to *best_host
  * (use_graph 1, timing 0).  Synchronises `stream`; leaves no ctx behind.
  * The workspace contents are undefined afterwards. */
