@@ -1,0 +1,63 @@
+"""bench.py's host-side models (no GPU): the algorithmic byte counts behind
+the roofline figures and the rule that reports measured HBM traffic only
+for the kernel source and launch tuning the counters were taken under."""
+import hashlib
+import json
+import os
+import types
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _problem(precision, d=128, g=100):
+    return types.SimpleNamespace(precision=precision, d=d, g=g)
+
+
+def test_bound_bytes_follow_the_format():
+    bench.TUNING.clear()
+    assert bench.bound_layout(_problem("bf16")) == (4, 100)
+    bench.TUNING.update(bound_codes=2)
+    assert bench.bound_layout(_problem("bf16")) == (2, 100)
+    assert bench.bound_layout(_problem("fp32")) == (4, 100)   # FP32 problems keep FP32 bounds
+    bench.TUNING.clear()
+
+
+def test_algorithmic_bytes_per_launch():
+    bench.TUNING.clear()
+    bench.TUNING.update(bound_codes=2)
+    s = dict(point_filter_fail=1000, pairs=3000, rechecks=10)
+    P = _problem("bf16", d=128, g=100)
+    per_point = 4 * 128 + 16 + 4 + 4 * 4 + 4 + 16 + 12     # row, entry, norm, masks, closed bound, state, update
+    assert bench.assign_bytes(P, s) == 1000 * per_point + 3000 * 2 + 10 * 20
+    assert bench.gfilter_bytes(P, s) == 1000 * (16 + 2 * 100 + 4 * 4 + 4)
+    bench.TUNING.clear()
+    assert bench.gfilter_bytes(P, s) == 1000 * (16 + 4 * 100 + 4 * 4 + 4)
+
+
+def test_traffic_only_for_matching_source_and_tuning(tmp_path, monkeypatch):
+    src = os.path.join(ROOT, "paper_1905_09345_amd", "csrc", "kp_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (tmp_path / "paper_1905_09345_amd" / "csrc").mkdir(parents=True)
+    (tmp_path / "paper_1905_09345_amd" / "csrc" / "kp_kernels.hip").write_bytes(open(src, "rb").read())
+    ent = dict(workload="W", source_sha256=digest, bytes_per_launch=123.0,
+               tuning=dict(chunk_depth=1, bound_codes=2))
+    (prof / "traffic.json").write_text(json.dumps({"k@depth1": ent,
+                                                   "k@depth3": dict(ent, bytes_per_launch=456.0,
+                                                                    tuning=dict(chunk_depth=3, bound_codes=2))}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    bench.TUNING.clear()
+    bench.TUNING.update(chunk_depth=3, bound_codes=2)
+    assert bench.traffic_of("k", "W") == 456.0
+    bench.TUNING.update(chunk_depth=1)
+    assert bench.traffic_of("k", "W") == 123.0
+    bench.TUNING.update(bound_codes=1)          # counters taken under another tuning
+    assert bench.traffic_of("k", "W") is None
+    bench.TUNING.update(bound_codes=2)
+    assert bench.traffic_of("k", "other workload") is None
+    (tmp_path / "paper_1905_09345_amd" / "csrc" / "kp_kernels.hip").write_text("changed")
+    assert bench.traffic_of("k", "W") is None   # the source has changed since
+    bench.TUNING.clear()
