@@ -94,7 +94,7 @@ struct ProbDev {
     float *gcn;               // per group: an upper bound on its members' FP32 norms ||c||
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
     int4 *L1;                 // points failing the point-level filter (filter order): {point, slot, ub now, group field}
-    int *L1s;                 // the same ids sorted by assigned slot (and nearest other group, bucketed)
+    int *L1s;                 // FP32 mode: the same ids sorted by assigned slot (and nearest other group, bucketed)
     int4 *L1x;                // per sorted entry: point, slot a, ub now (FP32 bits, rounded up), group of a
     int *L3;                  // positions of the points whose BF16 decision is uncertain
     float *minnc;             // per position: smallest bound of the closed groups (rounded down)

@@ -437,8 +437,8 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
             const int4 u = P.L1[e];
             const int pid = clamp_pid(P, u.x), a = clamp_slot(P, u.y), key = l1_key(P, a, u.w);
             const int pos = atomicAdd(&P.cursor1[key], 1);
-            P.L1s[pos] = pid;
-            if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);
+            if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);   // BF16 mode reads only L1x
+            else P.L1s[pos] = pid;
         }
         return;
     }
@@ -456,8 +456,8 @@ __device__ __forceinline__ void b_l1_scatter(const ProbDev &P, const int bid_, c
         const int4 u = P.L1[e];
         const int pid = clamp_pid(P, u.x), a = clamp_slot(P, u.y), key = l1_key(P, a, u.w);
         const int pos = atomicAdd(&h[key], 1);
-        P.L1s[pos] = pid;
-        if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);
+        if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);   // BF16 mode reads only L1x
+        else P.L1s[pos] = pid;
     }
 }
 __global__ __launch_bounds__(256) void k_l1_scatter(ProbDev P)
@@ -1770,7 +1770,7 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
         const bool live = e3 < n3;
         if (__ballot(live) == 0ull) continue;   // past the end of the list for this wave's eight teams
         const long long e = live ? (long long)max(min(P.L3[e3], last_pos), 0) : 0;
-        const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1s[e])) : 0;
+        const int pid = live ? (dense ? (int)e : clamp_pid(P, P.L1x[e].x)) : 0;
         const int olda = (live && !dense) ? clamp_slot(P, P.st[pid].a) : -1;
         const float4 pin = live ? P.ps4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
         float4 x[NV];
