@@ -23,11 +23,15 @@ of the five workloads the build is measured on:
 
 Blob centers are uniform in [-10, 10]^D.  Every generator is
 numpy.random.Generator(PCG64(seed)); config c uses seed 1000 + c and batched
-problem p uses seed 100000 + p, unless the caller passes a seed.
+problem p uses seed 100000 + p, unless the caller passes a seed.  The point
+rows are drawn in chunks on a thread pool, each chunk from a child generator
+of that seed, so the data do not depend on the number of threads.
 """
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -79,6 +83,30 @@ def _rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _fill_chunks(rng, n, chunk, body):
+    """Run body(child_rng, s, e) over the chunks [s, e) of range(n) on a thread
+    pool.  Chunk i draws from its own generator, seeded by child i of one
+    SeedSequence that `rng` draws, so the numbers do not depend on the
+    thread count or on the order in which chunks finish."""
+    starts = list(range(0, n, chunk))
+    seqs = np.random.SeedSequence(int(rng.integers(0, 2 ** 63))).spawn(len(starts))
+
+    def run(i):
+        s = starts[i]
+        body(np.random.Generator(np.random.PCG64(seqs[i])), s, min(n, s + chunk))
+
+    if len(starts) <= 1:
+        for i in range(len(starts)):
+            run(i)
+        return
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(run, range(len(starts))))
+
+
 def gaussian_mixture(rng, n, d, k, *, sigma=None, sigma_range=(0.3, 1.5), dirichlet=True,
                      noise_frac=0.0, box=10.0, chunk=1 << 18):
     """Isotropic Gaussian mixture with centers uniform in [-box, box]^d.
@@ -96,10 +124,12 @@ def gaussian_mixture(rng, n, d, k, *, sigma=None, sigma_range=(0.3, 1.5), dirich
     n_mix = n - n_noise
     X = np.empty((n, d), dtype=np.float32)
     lab = rng.choice(k, size=n_mix, p=w)
-    for s in range(0, n_mix, chunk):
-        e = min(n_mix, s + chunk)
-        z = rng.standard_normal(size=(e - s, d))
+
+    def body(r, s, e):
+        z = r.standard_normal(size=(e - s, d))
         X[s:e] = centers[lab[s:e]] + z * sig[lab[s:e], None]
+
+    _fill_chunks(rng, n_mix, chunk, body)
     if n_noise:
         X[n_mix:] = rng.uniform(-box, box, size=(n_noise, d))
         perm = rng.permutation(n)
@@ -127,11 +157,13 @@ def student_t_mixture(rng, n, d, k, *, nu=3.0, zipf_s=1.1, sigma_range=(0.3, 1.5
     lab = np.repeat(np.arange(k), cnt)
     rng.shuffle(lab)
     X = out if out is not None else np.empty((n, d), dtype=np.float32)
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        z = rng.standard_normal(size=(e - s, d))
-        w = rng.chisquare(nu, size=(e - s, 1))
+
+    def body(r, s, e):
+        z = r.standard_normal(size=(e - s, d))
+        w = r.chisquare(nu, size=(e - s, 1))
         X[s:e] = centers[lab[s:e]] + sig[lab[s:e], None] * z / np.sqrt(w / nu)
+
+    _fill_chunks(rng, n, chunk, body)
     return X
 
 

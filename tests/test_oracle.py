@@ -191,3 +191,67 @@ def test_datagen_shapes_and_determinism():
     np.testing.assert_array_equal(a.C0, b.C0)
     c1 = datagen.make_config(1)
     np.testing.assert_array_equal(c1.C0, c1.X[:16])
+
+
+def _exact_d2(x, c):
+    """Exact squared distance of an FP32 point to an FP64 centroid (rational arithmetic)."""
+    return sum((Fraction(float(a)) - Fraction(float(b))) ** 2 for a, b in zip(x, c))
+
+
+def test_dist2_to_hand_values():
+    """dist2_to reads the labelled row: 1-2-2 triangle distances by hand."""
+    X = np.array([[1.0, 2.0], [0.0, 0.0]], np.float32)
+    C = np.array([[0.0, 0.0], [4.0, 6.0], [1.0, 2.0]])
+    np.testing.assert_array_equal(oracle.dist2_to(X, C, np.array([1, 1])), [25.0, 52.0])
+    np.testing.assert_array_equal(oracle.dist2_to(X, C, np.array([0, 2])), [5.0, 5.0])
+    np.testing.assert_array_equal(oracle.dist2_to(X, C, np.array([2, 0])), [0.0, 0.0])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dist2_to_bruteforce(seed):
+    """Every point's distance to an arbitrary (random) labelled centroid equals
+    the exact rational value within FP64 rounding; the centroids are far
+    apart, so a wrong row, a dropped coordinate or a sign slip is visible."""
+    rng = np.random.default_rng(50 + seed)
+    n, k, d = 37, 5, 1 + seed * 3
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    C = rng.normal(size=(k, d)) + 10.0 * np.arange(k)[:, None]
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    got = oracle.dist2_to(X, C, lab)
+    for i in range(n):
+        want = float(_exact_d2(X[i], C[lab[i]]))
+        assert got[i] == pytest.approx(want, rel=4 * d * 2.0 ** -53, abs=0), (i, lab[i])
+
+
+def test_dist2_to_of_assignment_is_dmin_and_second_is_bruteforce():
+    """dist2_to under the oracle's own labels returns its nearest distances
+    bit for bit, and the second distance of assign() is the second smallest
+    of the exact distances (brute force)."""
+    rng = np.random.default_rng(9)
+    X = rng.normal(size=(60, 4)).astype(np.float32)
+    C = rng.normal(size=(7, 4))
+    lab, d1, d2 = oracle.assign(X, C, second=True)
+    np.testing.assert_array_equal(oracle.dist2_to(X, C, lab), d1)
+    for i in range(X.shape[0]):
+        ex = sorted(float(_exact_d2(X[i], C[j])) for j in range(C.shape[0]))
+        assert d1[i] == pytest.approx(ex[0], rel=1e-14)
+        assert d2[i] == pytest.approx(ex[1], rel=1e-14)
+    assert (oracle.assign(X, C[:1], second=True)[2] == np.inf).all()   # k = 1: no second
+
+
+def test_near_tie_check_rejects_a_wrong_label():
+    """The parity check (tests/parity.py) accepts the oracle's own labels,
+    accepts a swap at an exact tie, and rejects a label that is farther than
+    the near-tie band -- a mistake planted on the CPU side."""
+    from parity import check_assignment
+    X = np.array([[0.5], [3.0], [9.0]], np.float32)
+    C = np.array([[0.0], [1.0], [10.0]], np.float32)
+    lab, _ = oracle.assign(X, C.astype(np.float64))
+    assert check_assignment(X, C, lab) == (0, 0)
+    tie = lab.copy()
+    tie[0] = 1                                         # 0.5 is equidistant from 0 and 1
+    assert check_assignment(X, C, tie) == (1, 1)
+    bad = lab.copy()
+    bad[1] = 2                                         # 3.0 is 2 from c1 and 7 from c2
+    with pytest.raises(AssertionError):
+        check_assignment(X, C, bad)
