@@ -41,7 +41,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5],
+                    help="headline workload (default 5: the largest single-GPU configuration)")
+    ap.add_argument("--secondary", default="2,4",
+                    help="comma-separated workloads measured after the headline with --secondary-steps steps "
+                         "(default: 2 = plain filtered FP32, 4 = the batched form; empty to skip)")
+    ap.add_argument("--secondary-steps", type=int, default=3)
     ap.add_argument("--problems", type=int, default=512, help="problems of the batched workload (config 4)")
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain FP32 Lloyd comparator")
@@ -136,16 +141,54 @@ def serving(torch, km, Xd, nq=1_000_000, reps=5):
                 queries_recipe="training rows + N(0, 0.05^2) noise, seeded")
 
 
-def cpu_baseline(P, target_s):
-    """The FP64 oracle (one Lloyd iteration) on a bounded sample of the workload."""
+def cpu_model():
+    """The host CPU's model name and the threads the oracle uses."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def check_run(KMeans, kp_tuning, spec, tun, T):
+    """An untimed run of the same workload stopped after T-1 iterations to
+    take the centroids the last assignment step uses, then the last
+    iteration: returns (c32 before, c64 before, labels, c32, c64) as numpy
+    arrays, and the run's context (kept for serving)."""
+    t = kp_tuning(**{f: getattr(tun, f) for f, _ in kp_tuning._fields_})
+    t.timing = 0
+    t.timing_stages = 0
+    km = KMeans(spec, tuning=t)
+    if T > 1:
+        km.iterate(T - 1)
+    c32p, c64p = [a.cpu().numpy() for a in km.centroids()]
+    km.iterate(1)
+    lab = km.assign().cpu().numpy()
+    c32, c64 = [a.cpu().numpy() for a in km.centroids()]
+    return (c32p, c64p, lab, c32, c64), km
+
+
+def cpu_baseline(P, target_s, ref):
+    """The FP64 oracle on the host cores: iteration T of the workload (assign
+    with the FP32 centroids the GPU's last assignment used, then the update)
+    on a bounded sample, the first m points, m sized for about target_s.
+
+    The same oracle outputs state the GPU result's precision: the share of
+    the sample whose GPU label differs from the oracle's (a difference is
+    allowed only at a near-tie, d(x, c_gpu) - d(x, c_best) <= 1e-5 d(x,
+    c_best)), and the largest relative error of the GPU's FP64 centroids
+    against the oracle's means of all N points under the GPU's assignment."""
     import oracle
     threads = oracle.threads()
-    C = P.C0.astype(np.float64)
+    c32p, c64p, lab, c32, c64 = ref
+    C = c32p.astype(np.float64)
 
     def one_iteration(m):
         t0 = time.perf_counter()
-        lab, _ = oracle.assign(P.X[:m], C)
-        oracle.update(P.X[:m], lab, C)
+        a, _ = oracle.assign(P.X[:m], C)
+        oracle.update(P.X[:m], a, C)
         return max(time.perf_counter() - t0, 1e-6)
 
     # size the sample from a probe of about a second (a tiny probe is dominated
@@ -156,12 +199,93 @@ def cpu_baseline(P, target_s):
     dt = one_iteration(probe)
     m = int(min(P.n, max(probe, probe * target_s / dt)))
     t0 = time.perf_counter()
-    lab, _ = oracle.assign(P.X[:m], C)
-    oracle.update(P.X[:m], lab, C)
+    ref_lab, d1sq = oracle.assign(P.X[:m], C)
+    oracle.update(P.X[:m], ref_lab, C)
     el = time.perf_counter() - t0
-    return dict(value=m / el, unit="point-iterations/s", cores=threads, kind="oracle",
-                sample="one FP64 Lloyd iteration (assign + update) over the first %d of %d points, all %d "
-                       "centroids, %.1f s" % (m, P.n, P.k, el))
+    cpu = dict(value=m / el, unit="point-iterations/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
+               sample="FP64 Lloyd iteration %d (assign + update) over the first %d of %d points, all %d "
+                      "centroids, %.1f s" % (P.iters, m, P.n, P.k, el))
+    # precision of the GPU's iteration T against those oracle outputs
+    mism = ref_lab != lab[:m]
+    d2sq = oracle.dist2_to(P.X[:m], C, lab[:m])
+    d1, d2 = np.sqrt(d1sq), np.sqrt(d2sq)
+    near = (d2 - d1) <= 1e-5 * d1
+    cref, _ = oracle.update(P.X, lab, c64p)
+    scale = float(np.sqrt((P.X[:m].astype(np.float64) ** 2).sum(axis=1).mean()))
+    err = np.linalg.norm(c64 - cref, axis=1) / np.maximum(np.linalg.norm(cref, axis=1), scale)
+    prec = dict(iteration=P.iters, sample_points=m, assign_mismatch_rate=float(mism.mean()),
+                assign_mismatches=int(mism.sum()), mismatches_outside_near_tie=int((mism & ~near).sum()),
+                near_tie_band="d(x,c_gpu) - d(x,c_best) <= 1e-5 d(x,c_best)",
+                centroid_rel_err_max=float(err.max()), centroids_checked=int(P.k),
+                c32_is_rounded_c64=bool(np.array_equal(c32, c64.astype(np.float32))),
+                reference="FP64 oracle: assignment of the sample with the GPU's previous FP32 centroids; "
+                          "means of all N points under the GPU's assignment")
+    return cpu, prec
+
+
+def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmup, *, extras=True):
+    """One workload of a single problem: returns the result dict (value,
+    roofline, precision, comparators)."""
+    t0 = time.perf_counter()
+    P = datagen.make_config(config, n=args.n if config == args.config else None)
+    log("data: %s n=%d d=%d k=%d g=%d T=%d (%.1f s)" % (P.meta["name"], P.n, P.d, P.k, P.g, P.iters,
+                                                           time.perf_counter() - t0))
+    prec = "bf16" if P.precision == "bf16" else "fp32"
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(P.X).to(dev)
+    C0d = torch.from_numpy(P.C0).to(dev)
+    spec = [(Xd, C0d, P.g, prec, P.seed)]
+    tun = tuned(args, KMeans, kp_tuning, spec)
+    el, agg, timed, dom, st = run_steps(torch, KMeans, kp_tuning, spec, tun, P.iters, steps, warmup)
+    value = P.n * P.iters * steps / el
+    if args.stats:
+        for s in st:
+            log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
+                "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
+    for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
+        log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
+    # the dominant kernel stage, timed inside the timed region
+    roofline = roofline_of(dom, timed[dom], P, st)
+    others = {}
+    for nm in ("assign", "assign_dense", "group_filter", "bound_filter", "recheck"):
+        if nm in agg and nm != dom:
+            r = roofline_of(nm, agg[nm], P, st)
+            others[nm] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    ref, km = check_run(KMeans, kp_tuning, spec, tun, P.iters)
+    serve = None
+    if extras:
+        serve = serving(torch, km, Xd)
+        log("serving: %d queries in %.3f ms (%.3g queries/s), plain FP32 argmin %.3f ms" % (
+            serve["queries"], serve["ms"], serve["value"], serve["plain_fp32_ms"]))
+    km.close()
+    del km
+    torch.cuda.empty_cache()
+    baseline = None
+    if not args.no_baseline:
+        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=3)
+        baseline = dict(value=P.n / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
+                        impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration")
+        log("plain FP32 Lloyd: %.3f ms/iteration" % (sec * 1e3))
+    del Xd, C0d
+    torch.cuda.empty_cache()
+    cpu, precision = (None, None) if args.no_cpu else cpu_baseline(P, args.cpu_seconds if extras else
+                                                                   min(args.cpu_seconds, 8.0), ref)
+    if precision:
+        log("precision: %d of %d sampled labels differ from the oracle (%d outside the near-tie band); "
+            "largest centroid error %.3g" % (precision["assign_mismatches"], precision["sample_points"],
+                                             precision["mismatches_outside_near_tie"],
+                                             precision["centroid_rel_err_max"]))
+    return dict(
+        value=value, ms_per_step=el / steps * 1e3, steps=steps, warmup=warmup, dtype="bf16" if prec == "bf16" else "f32",
+        config={"workload": P.meta["name"], "n": P.n, "d": P.d, "k": P.k, "g": P.g, "iterations": P.iters,
+                "precision": "bf16 MFMA + fp32 recheck + fp64 centroids" if prec == "bf16"
+                else "fp32 direct + fp64 centroids", "tuning": dict(TUNING)},
+        roofline=roofline, stage_rooflines=others, serving=serve, cpu_baseline=cpu, precision=precision,
+        plain_fp32_lloyd=baseline, speedup_vs_plain_fp32_lloyd=(value / baseline["value"]) if baseline else None,
+        stage_ms_per_step={nm: round(a["ms"], 4) for nm, a in agg.items()},
+        stage_ms_source="warmup runs with every stage timed" if warmup else "the timed runs",
+        filter={"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"]]
+                for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)})
 
 
 def main():
@@ -183,67 +307,34 @@ def main():
     from paper_1905_09345_amd import KMeans
     from paper_1905_09345_amd.kp import kp_tuning
     if args.config == 4:
-        return main_batched(args, torch, datagen, KMeans, kp_tuning)
-
-    t0 = time.perf_counter()
-    P = datagen.make_config(args.config, n=args.n)
-    log("data: %s n=%d d=%d k=%d g=%d T=%d (%.1f s)" % (P.meta["name"], P.n, P.d, P.k, P.g, P.iters,
-                                                           time.perf_counter() - t0))
-    prec = "bf16" if P.precision == "bf16" else "fp32"
-    dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(P.X).to(dev)
-    C0d = torch.from_numpy(P.C0).to(dev)
-    spec = [(Xd, C0d, P.g, prec, P.seed)]
-    tun = tuned(args, KMeans, kp_tuning, spec)
-    el, agg, timed, dom, last = run_steps(args, torch, KMeans, kp_tuning, spec, tun, P.iters)
-    value = P.n * P.iters * args.steps / el
-    # per-stage GPU time (HIP events the library recorded on its stream)
-    st = last.stats()
-    if args.stats:
-        for s in st:
-            log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
-                "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
-    for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
-        log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
-    # the dominant kernel stage, timed inside the timed region
-    roofline = roofline_of(dom, timed[dom], P, st)
-    serve = serving(torch, last, Xd)
-    log("serving: %d queries in %.3f ms (%.3g queries/s), plain FP32 argmin %.3f ms" % (
-        serve["queries"], serve["ms"], serve["value"], serve["plain_fp32_ms"]))
-    others = {}
-    for nm in ("assign_dense", "group_filter", "bound_filter"):
-        if nm in agg and nm != dom:
-            r = roofline_of(nm, agg[nm], P, st)
-            others[nm] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
-    last.close()
-    torch.cuda.empty_cache()
-
-    baseline = None
-    if not args.no_baseline:
-        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=3)
-        baseline = dict(value=P.n / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
-                        impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration")
-        log("plain FP32 Lloyd: %.3f ms/iteration" % (sec * 1e3))
-    cpu = None if args.no_cpu else cpu_baseline(P, args.cpu_seconds)
+        res = measure_batched(args, torch, datagen, KMeans, kp_tuning, args.steps, args.warmup)
+    else:
+        res = measure_single(args, torch, datagen, KMeans, kp_tuning, args.config, args.steps, args.warmup)
     out = {
-        "metric": METRIC, "value": value, "unit": "point-iterations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if prec == "bf16" else "f32",
-        "data": "synthetic (seeded mixture, see datagen)",
-        "config": {"workload": P.meta["name"], "n": P.n, "d": P.d, "k": P.k, "g": P.g, "iterations": P.iters,
-                   "precision": "bf16 MFMA + fp32 recheck + fp64 centroids" if prec == "bf16"
-                   else "fp32 direct + fp64 centroids", "tuning": TUNING},
-        "roofline": roofline,
-        "stage_rooflines": others,
-        "serving": serve,
-        "cpu_baseline": cpu,
-        "plain_fp32_lloyd": baseline,
-        "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
-        "stage_ms_per_step": {nm: round(a["ms"], 4) for nm, a in agg.items()},
-        "stage_ms_source": "warmup runs with every stage timed" if args.warmup else "the timed runs",
-        "filter": {"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"]]
-                   for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)},
+        "metric": METRIC, "value": res["value"], "unit": "point-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": res["dtype"],
+        "data": "synthetic (seeded mixtures, see datagen)",
     }
+    out.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step", "steps", "warmup", "dtype")})
+    # the other forms the workload set names, measured in the same process
+    # with fewer steps: plain filtered FP32 (C2) and the batched form (C4)
+    secondary = {}
+    for c in [int(x) for x in args.secondary.split(",") if x.strip()]:
+        if c == args.config:
+            continue
+        TUNING.clear()
+        if c == 4:
+            r = measure_batched(args, torch, datagen, KMeans, kp_tuning, args.secondary_steps, 1, extras=False)
+        else:
+            r = measure_single(args, torch, datagen, KMeans, kp_tuning, c, args.secondary_steps, 1, extras=False)
+        secondary["C%d" % c] = {k: r[k] for k in ("value", "ms_per_step", "steps", "dtype", "config", "roofline",
+                                                  "stage_rooflines", "precision", "plain_fp32_lloyd",
+                                                  "speedup_vs_plain_fp32_lloyd", "cpu_baseline") if k in r}
+        secondary["C%d" % c]["unit"] = "point-iterations/s"
+        torch.cuda.empty_cache()
+    if secondary:
+        out["other_forms"] = secondary
     print(json.dumps(out), flush=True)
 
 
@@ -314,14 +405,16 @@ def tuned(args, KMeans, kp_tuning, spec):
     return tun
 
 
-def run_steps(args, torch, KMeans, kp_tuning, spec, tun, T):
+def run_steps(torch, KMeans, kp_tuning, spec, tun, T, steps, warmup):
     """W warmup runs with events around every stage (the per-stage breakdown,
     untimed), then K timed runs with events around the dominant stage only:
     its launches are what the roofline divides by, and no other stage pays
     for instrumentation inside the timed region.  Every run is a fresh
-    context (made outside the timed region) iterated T times.  Returns the
-    elapsed seconds, the breakdown, the timed runs' stage times, the
-    dominant stage and the last run."""
+    context iterated T times; only one context exists at a time, made and
+    destroyed outside the timed region, and each run is bracketed by a
+    device synchronisation on both sides.  Returns the summed seconds of the
+    K runs, the breakdown, the timed runs' stage times, the dominant stage
+    and the per-iteration statistics of the last run."""
     from paper_1905_09345_amd.kp import STAGES
 
     def with_stages(mask):
@@ -329,51 +422,54 @@ def run_steps(args, torch, KMeans, kp_tuning, spec, tun, T):
         t.timing_stages = mask
         return t
 
-    def aggregate(runs):
-        stages = [km.stage_times() for km in runs]
-        return {nm: dict(ms=sum(x[nm]["ms"] for x in stages) / len(runs),
-                         launches=sum(x[nm]["launches"] for x in stages) / len(runs)) for nm in stages[0]}
+    def aggregate(stages):
+        return {nm: dict(ms=sum(x[nm]["ms"] for x in stages) / len(stages),
+                         launches=sum(x[nm]["launches"] for x in stages) / len(stages)) for nm in stages[0]}
 
     breakdown = None
     mask = 0
-    if args.warmup > 0:
-        warm = [KMeans(spec, tuning=with_stages(0)) for _ in range(args.warmup)]
-        for km in warm:
+    if warmup > 0:
+        times = []
+        for _ in range(warmup):
+            km = KMeans(spec, tuning=with_stages(0))
             km.iterate(T)
-        torch.cuda.synchronize()
-        breakdown = aggregate(warm)
-        for km in warm:
+            times.append(km.stage_times())
             km.close()
+        breakdown = aggregate(times)
         dom = max((nm for nm in breakdown if nm != "filtered_iter"), key=lambda nm: breakdown[nm]["ms"])
         mask = 1 << STAGES.index(dom)
         log("warmup done (stage breakdown; timed runs time %s only)" % dom)
-    runs = [KMeans(spec, tuning=with_stages(mask)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    log("contexts ready: %d" % len(runs))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record()
-    for km in runs:
+    wall = gpu_s = 0.0
+    times = []
+    st = None
+    for i in range(steps):
+        km = KMeans(spec, tuning=with_stages(mask))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev0.record()
         km.iterate(T)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    timed = aggregate(runs)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - w0
+        gpu_s += ev0.elapsed_time(ev1) / 1e3
+        times.append(km.stage_times())
+        if i == steps - 1:
+            st = km.stats()
+        km.close()
+    timed = aggregate(times)
     if breakdown is None:
         breakdown = timed
     dom = max((nm for nm in breakdown if nm != "filtered_iter"), key=lambda nm: breakdown[nm]["ms"])
-    log("timed: %d steps, %.3f ms/step (events %.3f ms/step)" % (args.steps, max(wall, gpu_s) / args.steps * 1e3,
-                                                                   gpu_s / args.steps * 1e3))
-    for km in runs[:-1]:
-        km.close()
-    return max(wall, gpu_s), breakdown, timed, dom, runs[-1]
+    log("timed: %d steps, %.3f ms/step (events %.3f ms/step)" % (steps, max(wall, gpu_s) / steps * 1e3,
+                                                                   gpu_s / steps * 1e3))
+    return max(wall, gpu_s), breakdown, timed, dom, st
 
 
 TUNING = {}
 
 
-def main_batched(args, torch, datagen, KMeans, kp_tuning):
+def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extras=True):
     """The batched workload: many independent problems in one context, every
     stage launched once for all of them, one graph replay per iteration."""
     t0 = time.perf_counter()
@@ -386,15 +482,29 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
     Cd = [torch.from_numpy(p.C0).to(dev) for p in probs]
     spec = [(Xd[i], Cd[i], p.g, p.precision, p.seed) for i, p in enumerate(probs)]
     tun = tuned(args, KMeans, kp_tuning, spec)
-    el, agg, timed, dom, km = run_steps(args, torch, KMeans, kp_tuning, spec, tun, T)
-    value = ntot * T * args.steps / el
+    el, agg, timed, dom, _ = run_steps(torch, KMeans, kp_tuning, spec, tun, T, steps, warmup)
+    value = ntot * T * steps / el
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
+    # statistics and the oracle check come from one more (untimed) run
+    t = kp_tuning(**{f: getattr(tun, f) for f, _ in kp_tuning._fields_})
+    t.timing = 0
+    t.timing_stages = 0
+    km = KMeans(spec, tuning=t)
+    km.iterate(T - 1)
+    ncheck = len(probs) if args.no_cpu else min(len(probs), 64)
+    prev = [[a.cpu().numpy() for a in km.centroids(i)] for i in range(ncheck)]
+    km.iterate(1)
+    refs = [(prev[i][0], prev[i][1], km.assign(i).cpu().numpy()) + tuple(a.cpu().numpy() for a in km.centroids(i))
+            for i in range(ncheck)]
+    stats = [km.stats(i) for i in range(len(probs))]
+    km.close()
+    del km
     roofline = None
     if dom == "assign":
         byts = 0.0
         for i, p in enumerate(probs):
-            filt = [s for s in km.stats(i) if not s["dense"]]
+            filt = [s for s in stats[i] if not s["dense"]]
             byts += sum(assign_bytes(p, s) for s in filt) / max(len(filt), 1)
         ms = timed[dom]["ms"] / max(timed[dom]["launches"], 1e-9)   # timed inside the timed region
         ach = byts / (ms * 1e-3) / 1e9
@@ -408,15 +518,13 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
     if "group_filter" in agg and dom != "group_filter" and agg["group_filter"]["launches"] > 0:
         byts = 0.0
         for i, p in enumerate(probs):
-            filt = [s for s in km.stats(i) if not s["dense"]]
+            filt = [s for s in stats[i] if not s["dense"]]
             if p.precision == "bf16":
                 byts += sum(gfilter_bytes(p, s) for s in filt) / max(len(filt), 1)
         ms = agg["group_filter"]["ms"] / agg["group_filter"]["launches"]
         ach = byts / (ms * 1e-3) / 1e9
         others["group_filter"] = dict(kernel="kb_gfilter (all problems)", bound="hbm", achieved=ach,
                                       peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
-    km.close()
-    del km
     torch.cuda.empty_cache()
     baseline = None
     if not args.no_baseline:
@@ -424,38 +532,64 @@ def main_batched(args, torch, datagen, KMeans, kp_tuning):
         baseline = dict(value=ntot / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
                         impl="torch FP32 GEMM (TF32 off) + argmin + index_add per problem, dense every iteration")
         log("plain FP32 Lloyd: %.3f ms per iteration of all problems" % (sec * 1e3))
-    cpu = None
+    del Xd, Cd, spec
+    torch.cuda.empty_cache()
+    cpu = precision = None
     if not args.no_cpu:
-        import oracle
-        m, el_c, npts = 0, 0.0, 0
+        cpu, precision = cpu_baseline_batched(probs, args.cpu_seconds if extras else min(args.cpu_seconds, 8.0),
+                                              refs)
+        log("precision: %d of %d labels of %d problems differ from the oracle (%d outside the near-tie band); "
+            "largest centroid error %.3g" % (precision["assign_mismatches"], precision["sample_points"],
+                                             precision["problems_checked"],
+                                             precision["mismatches_outside_near_tie"],
+                                             precision["centroid_rel_err_max"]))
+    return dict(
+        value=value, ms_per_step=el / steps * 1e3, steps=steps, warmup=warmup, dtype="bf16",
+        config={"workload": "C4 batched, %d problems, N~U{2000..200000}, D in {16,32,64}, K in {16,64,256}, "
+                            "G=ceil(K/10)" % len(probs), "problems": len(probs), "sum_n": ntot,
+                "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids", "tuning": dict(TUNING)},
+        roofline=roofline, stage_rooflines=others, cpu_baseline=cpu, precision=precision,
+        plain_fp32_lloyd=baseline, speedup_vs_plain_fp32_lloyd=(value / baseline["value"]) if baseline else None,
+        stage_ms_per_step={nm: round(a["ms"], 4) for nm, a in agg.items()})
+
+
+def cpu_baseline_batched(probs, target_s, refs):
+    """The FP64 oracle on the host cores over the first problems of the batch
+    (whole problems, until about target_s has passed): iteration T of each,
+    from the FP32 centroids the GPU's last assignment used.  The same oracle
+    outputs give the precision of the GPU's result on those problems (as in
+    cpu_baseline)."""
+    import oracle
+    m, npts, mism, outside, worst = 0, 0, 0, 0, 0.0
+    el_c = 0.0
+    while m < len(refs) and el_c < target_s:
+        p = probs[m]
+        c32p, c64p, lab, c32, c64 = refs[m]
+        C = c32p.astype(np.float64)
         t1 = time.perf_counter()
-        while m < len(probs) and time.perf_counter() - t1 < args.cpu_seconds:
-            p = probs[m]
-            C = p.C0.astype(np.float64)
-            lab, _ = oracle.assign(p.X, C)
-            oracle.update(p.X, lab, C)
-            npts += p.n
-            m += 1
-        el_c = time.perf_counter() - t1
-        cpu = dict(value=npts / el_c, unit="point-iterations/s", cores=oracle.threads(), kind="oracle",
-                   sample="one FP64 Lloyd iteration of each of the first %d of %d problems (%d points), %.1f s"
-                          % (m, len(probs), npts, el_c))
-    out = {
-        "metric": METRIC, "value": value, "unit": "point-iterations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-        "data": "synthetic (seeded mixtures, see datagen)",
-        "config": {"workload": "C4 batched, %d problems, N~U{2000..200000}, D in {16,32,64}, K in {16,64,256}, "
-                               "G=ceil(K/10)" % len(probs), "problems": len(probs), "sum_n": ntot,
-                   "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids", "tuning": TUNING},
-        "roofline": roofline,
-        "stage_rooflines": others,
-        "cpu_baseline": cpu,
-        "plain_fp32_lloyd": baseline,
-        "speedup_vs_plain_fp32_lloyd": (value / baseline["value"]) if baseline else None,
-        "stage_ms_per_step": {nm: round(a["ms"], 4) for nm, a in agg.items()},
-    }
-    print(json.dumps(out), flush=True)
+        ref_lab, d1sq = oracle.assign(p.X, C)
+        oracle.update(p.X, ref_lab, C)
+        el_c += time.perf_counter() - t1
+        bad = ref_lab != lab
+        d1, d2 = np.sqrt(d1sq), np.sqrt(oracle.dist2_to(p.X, C, lab))
+        mism += int(bad.sum())
+        outside += int((bad & ((d2 - d1) > 1e-5 * d1)).sum())
+        cref, _ = oracle.update(p.X, lab, c64p)
+        scale = float(np.sqrt((p.X.astype(np.float64) ** 2).sum(axis=1).mean()))
+        err = np.linalg.norm(c64 - cref, axis=1) / np.maximum(np.linalg.norm(cref, axis=1), scale)
+        worst = max(worst, float(err.max()))
+        npts += p.n
+        m += 1
+    cpu = dict(value=npts / el_c, unit="point-iterations/s", cores=oracle.threads(), cpu_model=cpu_model(),
+               kind="oracle", sample="FP64 Lloyd iteration %d of each of the first %d of %d problems (%d points), "
+                                     "%.1f s" % (probs[0].iters, m, len(probs), npts, el_c))
+    prec = dict(iteration=probs[0].iters, problems_checked=m, sample_points=npts,
+                assign_mismatch_rate=mism / max(npts, 1), assign_mismatches=mism,
+                mismatches_outside_near_tie=outside,
+                near_tie_band="d(x,c_gpu) - d(x,c_best) <= 1e-5 d(x,c_best)", centroid_rel_err_max=worst,
+                reference="FP64 oracle per problem: assignment with the GPU's previous FP32 centroids; means "
+                          "under the GPU's assignment")
+    return cpu, prec
 
 
 def roofline_of(stage, a, P, st):
@@ -466,11 +600,17 @@ def roofline_of(stage, a, P, st):
         filt = [s for s in st if not s["dense"]]
         byts = sum(assign_bytes(P, s) for s in filt) / max(len(filt), 1)
         ach = byts / (ms_per_launch * 1e-3) / 1e9
+        # the method's flops on the same launches: 2d per distance computed
+        flops = sum(2.0 * P.d * s["distances"] for s in filt) / max(len(filt), 1)
+        tf = flops / (ms_per_launch * 1e-3) / 1e12
         return dict(kernel="k_blk64 (filtered iteration: BF16x3 distances of the open groups)", bound="hbm",
                     achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     traffic=traffic_of("k_blk64_filtered", wl),
                     work_per_launch="%.4g B (per L1 entry 4d+52+4*ceil(g/32) B, per pair %d B, per recheck 20 B)"
-                    % (byts, bound_layout(P)[0]), ms_per_launch=ms_per_launch)
+                    % (byts, bound_layout(P)[0]), ms_per_launch=ms_per_launch,
+                    mfma_side=dict(achieved=tf, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                                   frac=tf / MFMA_BF16_PEAK_TFLOPS,
+                                   work_per_launch="2*d*distances = %.4g flop" % flops))
     if stage == "group_filter":
         filt = [s for s in st if not s["dense"]]
         byts = sum(gfilter_bytes(P, s) for s in filt) / max(len(filt), 1)
@@ -483,11 +623,15 @@ def roofline_of(stage, a, P, st):
         flops = 2.0 * P.n * P.k * P.d
         ach = flops / (ms_per_launch * 1e-3) / 1e12
         if P.precision == "bf16":
-            # three BF16 products per distance on the matrix cores
-            return dict(kernel="k_blk64 (dense iteration 1, BF16x3)", bound="mfma", achieved=3 * ach,
-                        peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=3 * ach / MFMA_BF16_PEAK_TFLOPS,
+            # the method's 2NKD flops against the BF16 matrix-core peak (the
+            # BF16x3 split issues three products per distance: the issue rate
+            # is given beside it)
+            return dict(kernel="k_blk64 (dense iteration 1, BF16x3)", bound="mfma", achieved=ach,
+                        peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / MFMA_BF16_PEAK_TFLOPS,
                         traffic=traffic_of("k_blk64_dense", wl),
-                        work_per_launch="3*2*N*K*D = %.4g flop" % (3 * flops), ms_per_launch=ms_per_launch)
+                        work_per_launch="2*N*K*D = %.4g flop" % flops, ms_per_launch=ms_per_launch,
+                        mfma_issue_rate=dict(achieved=3 * ach, unit="TFLOP/s",
+                                             work_per_launch="3*2*N*K*D = %.4g flop" % (3 * flops)))
         peak = 78.6   # FP32 vector FMA without packed instructions (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
         return dict(kernel="k_dense_f32 (dense, iteration 1)", bound="alu", achieved=ach, peak=peak,
                     unit="TFLOP/s", frac=ach / peak, traffic=None,

@@ -63,9 +63,15 @@ typedef enum {
 /* One K-means problem. */
 typedef struct {
     int64_t n;                     /* points, 1 <= k <= n < 2^31 */
-    int32_t d;                     /* dimensions, 1 <= d <= 1024 (FP32 mode: d <= 128) */
+    int32_t d;                     /* dimensions: kp_workspace_bytes accepts
+                                      1 <= d <= 1024; kp_init supports
+                                      d <= 128 in FP32 mode and d <= 256 in
+                                      BF16 mode and returns
+                                      KP_ERR_UNSUPPORTED above that */
     int32_t k;                     /* centroids, 1 <= k <= 65536 */
-    int32_t g;                     /* centroid groups, 1 <= g <= k */
+    int32_t g;                     /* centroid groups, 1 <= g <= k; BF16 mode
+                                      supports g <= 1024 (KP_ERR_UNSUPPORTED
+                                      from kp_init above that) */
     int32_t precision;             /* kp_precision */
     const float *points_dev;       /* n*d FP32; BORROWED: must stay valid and
                                       unchanged until kp_destroy */
@@ -100,6 +106,19 @@ typedef struct {
                                       "assign", 6 "recheck", 7 "update", 8
                                       "centroids"; 0: every stage.  Whole
                                       replays are always timed */
+    int32_t deterministic;         /* 1: bitwise reproducible runs.  The list
+                                      of points failing the point-level filter
+                                      is compacted in point order and sorted
+                                      stably, and each update recomputes the
+                                      FP64 centroid sums from all points in a
+                                      fixed order (points sorted by centroid,
+                                      then by index) with no floating-point
+                                      atomics, so two runs of the same
+                                      problems on the same device give the
+                                      same labels, centroids and statistics
+                                      bit for bit.  0 (default): incremental
+                                      sums over the moved points with FP64
+                                      atomic adds, whose order varies */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */
@@ -125,11 +144,15 @@ typedef struct {
 } kp_stage_time;
 
 /* Bytes of device workspace kp_init needs for these problems; 0 if the
- * description is invalid (kp_last_error says why). */
+ * description is invalid (kp_last_error says why).  The workspace holds the
+ * per-point state of the filters (Section 1: the point-level filter's
+ * per-point bounds, the group-level filter's per-(point, group) bounds) and
+ * the centroid tables; its size grows with n * g. */
 size_t kp_workspace_bytes(const kp_problem *problems_host, int32_t count, const kp_tuning *tuning_host);
 
 /* Validate the problems, carve the workspace, group each problem's
- * centroids (host, once) and queue the per-point preparation on `stream`
+ * centroids (host, once: the centroid groups the group-level filter of
+ * Section 1 works on) and queue the per-point preparation on `stream`
  * (a hipStream_t; NULL = the default stream).  Synchronises the stream.
  * workspace_dev must be 256-byte aligned and hold kp_workspace_bytes().
  * On success *out receives a new ctx. */
@@ -138,23 +161,36 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems_host, int32_t count,
                   const kp_tuning *tuning_host);
 
 /* Queue `iters` K-means iterations (assignment step + centroid update) of
- * every problem on the ctx stream; returns without waiting.  The first
- * iteration of a ctx computes every distance; later ones are filtered.
- * iters must be >= 1. */
+ * every problem on the ctx stream; returns without waiting.  This is the
+ * method of Section 1 and Fig. 1: a point-level filter, a group-level
+ * filter, a distance calculator for the (point, group) pairs that are not
+ * filtered out, then the centroid update; the Abstract states that the
+ * result is that of standard K-means (Lloyd's algorithm), reached with fewer
+ * distance computations.  The first iteration of a ctx computes every
+ * distance (no bounds exist yet); later ones are filtered.  iters must be
+ * >= 1 (KP_ERR_INVALID otherwise); a HIP launch failure returns KP_ERR_HIP
+ * and poisons the ctx. */
 kp_status kp_iterate(kp_ctx *ctx, int32_t iters);
 
 /* Queue a copy of problem `problem`'s current assignment (n int32, original
- * centroid indices) to labels_dev.  KP_ERR_STATE before the first iteration. */
+ * centroid indices) to labels_dev: the output of the assignment step of
+ * standard K-means (Abstract; Section 2 compares against it).
+ * KP_ERR_STATE before the first iteration; KP_ERR_INVALID for a bad
+ * problem index or NULL labels_dev. */
 kp_status kp_assign(kp_ctx *ctx, int32_t problem, int32_t *labels_dev);
 
 /* Queue a copy of problem `problem`'s current centroids (k*d, original order)
  * as FP32 (the values distances use) and/or FP64 (the exact means); either
- * pointer may be NULL. */
+ * pointer may be NULL.  These are the means of the update step of standard
+ * K-means (Abstract); a centroid that received no point keeps its value.
+ * KP_ERR_INVALID for a bad problem index. */
 kp_status kp_centroids(kp_ctx *ctx, int32_t problem, float *c32_dev, double *c64_dev);
 
 /* Synchronise the ctx stream and copy up to `cap` per-iteration records of
  * problem `problem` (oldest first) to stats_host; *n_host receives the count
- * written.  At most the last 1024 iterations are kept. */
+ * written.  At most the last 1024 iterations are kept.  The records count
+ * what each filter level of Section 1 left to the distance calculator.
+ * KP_ERR_INVALID for a bad index, a negative cap or NULL outputs. */
 kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *stats_host, int32_t cap, int32_t *n_host);
 
 /* With kp_tuning.timing = 1: synchronise the ctx stream and return, per
@@ -170,6 +206,7 @@ kp_status kp_stage_times(kp_ctx *ctx, kp_stage_time *out_host, int32_t cap, int3
 int32_t kp_iterations(const kp_ctx *ctx);
 
 /* Serving: bytes of device scratch kp_predict needs for nq query points
+ * (the assignment step of Section 1 applied to new points)
  * (0 with kp_last_error set for a NULL ctx, a bad problem index or nq outside
  * 0..2^31-1). */
 size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq);
@@ -196,8 +233,10 @@ kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries_dev, int
 kp_status kp_destroy(kp_ctx *ctx);
 
 /* Autotuner of the launch shapes (the batched form picks its tiles and
- * workgroups per problem from it).  Runs `iters` iterations (>= 2) of the
- * problems from their initial centroids under each candidate tuning --
+ * workgroups per problem from it) -- the counterpart of the tunable
+ * parameters, such as the degree of parallelism, of Section 1.  Runs `iters`
+ * iterations (>= 2) of the problems from their initial centroids under each
+ * candidate tuning --
  * bound storage {FP32, FP16} (BF16 problems) x centroid chunks in flight
  * {1, 3} x workgroups per CU {8, 16, 32} -- in the
  * caller's workspace (kp_workspace_bytes of the same problems with a NULL
@@ -207,6 +246,43 @@ kp_status kp_destroy(kp_ctx *ctx);
  * The workspace contents are undefined afterwards. */
 kp_status kp_autotune(const kp_problem *problems_host, int32_t count, void *workspace_dev,
                       size_t workspace_bytes, void *stream, int32_t iters, kp_tuning *best_host);
+
+/* ------------------------------------------------------------ diagnostics
+ * Two read-only views of what the filtered iteration computes, for tests
+ * that check the precision argument directly rather than through the final
+ * labels. */
+
+/* The BF16x3 estimate of squared distances exactly as the distance kernels
+ * form it, and its error bound (the precision form's derived bound: the
+ * distance calculator of Section 1 run on BF16 matrix cores, whose result
+ * must still be that of standard K-means, Abstract).  For each of the nq
+ * query rows (queries_dev: nq*d FP32, row-major, 16-byte aligned) against
+ * every centroid of BF16 problem `problem` (its current FP32 centroids, the
+ * initial ones before the first iteration), est_dev[i*k + j] receives the
+ * estimate v of ||q_i - c_j||^2 that the decisions compare (the key value,
+ * low significand bits cleared) and eta_dev[i*k + j] a bound with
+ * |v - ||q_i - c_j||^2| <= eta in exact arithmetic on the FP32 inputs.  j is
+ * the original centroid index.  Outputs are caller-owned device buffers of
+ * nq*k FP32.  Queued on the ctx's stream.  KP_ERR_UNSUPPORTED for an FP32
+ * problem; KP_ERR_INVALID for a bad index, NULL or misaligned pointers or nq
+ * outside 0..2^31-1 (nq = 0 is a no-op). */
+kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries_dev, int64_t nq,
+                             float *est_dev, float *eta_dev);
+
+/* The bounds the filters of Section 1 keep for the listed points, brought
+ * to the current centroids (after the latest update): for each i < np with
+ * point x = idx_dev[i] (int32 point index) assigned to centroid a,
+ * ub_dev[i] >= d(x, c_a) (the point-level filter's upper bound),
+ * lbp_dev[i] <= d(x, c_j) for every j != a (its point-level lower bound) and
+ * lb_dev[i*g + q] <= d(x, c_j) for every member j != a of group q (the
+ * group-level filter's bounds), in exact arithmetic on the FP32 point and
+ * centroids.  group_dev (k int32, may be NULL) receives each original
+ * centroid's group.  All outputs are caller-owned device buffers; queued on
+ * the ctx's stream.  KP_ERR_STATE before the first iteration; KP_ERR_INVALID
+ * for a bad index, NULL outputs or np outside 0..2^31-1.  A listed index
+ * outside 0..n-1 is clamped into range. */
+kp_status kp_bounds(kp_ctx *ctx, int32_t problem, const int32_t *idx_dev, int64_t np, float *ub_dev,
+                    float *lbp_dev, float *lb_dev, int32_t *group_dev);
 
 /* Static description of a status code. */
 const char *kp_strerror(kp_status status);

@@ -39,13 +39,13 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
     size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, gcn, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, stats, iter, sink, lbsc;
+        cursor1, ctr, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
     size_t nk1max;   // keys of the L1 order for kgmax slots
 };
 
-Plan plan_problem(const kp_problem &p, bool lb16)
+Plan plan_problem(const kp_problem &p, bool lb16, bool det)
 {
     Plan o;
     const size_t n = (size_t)p.n;
@@ -118,8 +118,28 @@ Plan plan_problem(const kp_problem &p, bool lb16)
     o.iter = take(4);
     o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
     o.lbsc = take(16);
+    // deterministic mode: per-chunk failure counts and offsets, the (key,
+    // block) table of the stable sorts, the scan's partial sums and the
+    // pieces' partial centroid sums
+    const size_t nchunks = (n + kp::BF_CHUNK - 1) / kp::BF_CHUNK;
+    const size_t nkeys = std::max(o.nk1max, kgm);
+    const size_t npieces = (n + kp::DS_PIECE - 1) / kp::DS_PIECE;
+    o.dcnt = take(det ? nchunks * 4 : 0);
+    o.doff = take(det ? nchunks * 4 : 0);
+    o.hist2 = take(det ? nkeys * kp::SS_NB * 4 : 0);
+    o.spart = take(det ? (size_t)kp::SS_SCAN_BLOCKS * 4 : 0);
+    o.pfirst = take(det ? npieces * d * 8 : 0);
+    o.plast = take(det ? npieces * d * 8 : 0);
     o.bytes = off;
     return o;
+}
+
+// Bits needed for keys 0..maxkey.
+int bits_for(int maxkey)
+{
+    int b = 0;
+    while (b < 31 && (1 << b) <= maxkey) ++b;
+    return b;
 }
 
 bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
@@ -159,6 +179,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
         }
         if (t->timing < 0 || t->timing > 1) {
             set_error("timing=%d outside 0..1", t->timing);
+            return false;
+        }
+        if (t->deterministic < 0 || t->deterministic > 1) {
+            set_error("deterministic=%d outside 0..1", t->deterministic);
             return false;
         }
     }
@@ -363,7 +387,8 @@ size_t kp_workspace_bytes(const kp_problem *problems, int32_t count, const kp_tu
     if (!validate(problems, count, tuning)) return 0;
     size_t total = 0;
     const bool lb16 = tuning && tuning->bound_codes == 2;
-    for (int i = 0; i < count; ++i) total += plan_problem(problems[i], lb16).bytes;
+    const bool det = tuning && tuning->deterministic == 1;
+    for (int i = 0; i < count; ++i) total += plan_problem(problems[i], lb16, det).bytes;
     return total + batch_header_bytes(count);
 }
 
@@ -393,8 +418,13 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
     std::vector<Plan> plans;
     size_t need = 0;
     const bool lb16 = tuning && tuning->bound_codes == 2;
+    const bool det = tuning && tuning->deterministic == 1;
+    if (det && count > 1) {
+        set_error("deterministic mode runs one problem per ctx (got %d)", count);
+        return KP_ERR_UNSUPPORTED;
+    }
     for (int i = 0; i < count; ++i) {
-        plans.push_back(plan_problem(problems[i], lb16));
+        plans.push_back(plan_problem(problems[i], lb16, det));
         need += plans.back().bytes;
     }
     const size_t problem_bytes = need;
@@ -498,6 +528,15 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
         P.sink = (float *)(base + o.sink);
+        P.det = det ? 1 : 0;
+        P.nb_l1 = bits_for(P.nk1 - 1);
+        P.nb_slot = bits_for(P.kg - 1);
+        P.dcnt = (int *)(base + o.dcnt);
+        P.doff = (int *)(base + o.doff);
+        P.hist2 = (int *)(base + o.hist2);
+        P.spart = (int *)(base + o.spart);
+        P.pfirst = (double *)(base + o.pfirst);
+        P.plast = (double *)(base + o.plast);
         KP_HIP(hipMemcpyAsync((void *)P.perm, G.perm.data(), G.perm.size() * 4, hipMemcpyHostToDevice, ctx->user));
         KP_HIP(hipMemcpyAsync((void *)P.slot_group, G.slot_group.data(), G.slot_group.size() * 4,
                               hipMemcpyHostToDevice, ctx->user));
@@ -841,6 +880,52 @@ kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries, int64_t
         return KP_ERR_INVALID;
     }
     KP_HIP(kp::launch_serve(ctx->P[problem], ctx->user, ctx->cfg, queries, (long long)nq, labels, scratch));
+    return KP_OK;
+}
+
+kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, float *est, float *eta)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count) {
+        set_error("bad problem index %d", problem);
+        return KP_ERR_INVALID;
+    }
+    if (nq < 0 || nq > 0x7FFFFFFFll) {
+        set_error("nq=%lld outside 0..2^31-1", (long long)nq);
+        return KP_ERR_INVALID;
+    }
+    if (ctx->P[problem].prec != KP_PREC_BF16_RECHECK) {
+        set_error("problem %d is not a BF16 problem", problem);
+        return KP_ERR_UNSUPPORTED;
+    }
+    if (nq == 0) return KP_OK;
+    if (!queries || !est || !eta || ((uintptr_t)queries & 15u) != 0) {
+        set_error("NULL or misaligned queries, NULL outputs");
+        return KP_ERR_INVALID;
+    }
+    KP_HIP(kp::launch_probe(ctx->P[problem], ctx->user, queries, (long long)nq, est, eta));
+    return KP_OK;
+}
+
+kp_status kp_bounds(kp_ctx *ctx, int32_t problem, const int32_t *idx, int64_t np, float *ub, float *lbp, float *lb,
+                    int32_t *groups)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count || np < 0 || np > 0x7FFFFFFFll) {
+        set_error("bad problem index %d or np=%lld outside 0..2^31-1", problem, (long long)np);
+        return KP_ERR_INVALID;
+    }
+    if (np > 0 && (!idx || !ub || !lbp || !lb)) {
+        set_error("NULL index list or outputs");
+        return KP_ERR_INVALID;
+    }
+    if (ctx->iters == 0) {
+        set_error("no iteration has run yet");
+        return KP_ERR_STATE;
+    }
+    KP_HIP(kp::launch_bounds(ctx->P[problem], ctx->user, idx, (long long)np, ub, lbp, lb, groups));
     return KP_OK;
 }
 

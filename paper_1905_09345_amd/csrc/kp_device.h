@@ -111,7 +111,18 @@ struct ProbDev {
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
     float *sink;              // SINK_SLOTS x 16 floats, written and never read
+    // deterministic mode (kp_tuning.deterministic): fixed-order lists and sums
+    int det;                  // 1: the list of point-filter failures and the centroid sums in a fixed order
+    int nb_l1, nb_slot;       // bits of the largest L1 key (nk1 - 1) and slot (kg - 1)
+    int *dcnt, *doff;         // per chunk of BF_CHUNK points: failures, their first position in L1
+    int *hist2;               // (key, block) counts of the stable counting sorts, then their cursors
+    int *spart;               // SS_SCAN_BLOCKS partial sums of the scan of hist2, then their offsets
+    double *pfirst, *plast;   // per piece of DS_PIECE sorted points: sums of its first and last run (d each)
 };
+constexpr int BF_CHUNK = 4096;        // points per step of the bound filter (256 threads x 16)
+constexpr int SS_NB = 1024;           // one-wave blocks of the stable counting sorts
+constexpr int SS_SCAN_BLOCKS = 1024;  // workgroups of the scan of their (key, block) table
+constexpr int DS_PIECE = 512;         // sorted points per wave of the fixed-order centroid sums
 
 // ---------------------------------------------------------------- rounding
 // (selects rather than branches: these sit in the innermost loops)

@@ -286,6 +286,43 @@ __global__ void kb_begin(const ProbDev *__restrict__ probs, const int *__restric
 // from one atomic per workgroup step; within it, the order is that of the
 // points.
 constexpr int BF_PER_THREAD = 16;
+static_assert(256 * BF_PER_THREAD == BF_CHUNK, "one bound-filter step per chunk");
+
+// Does point i fail the point-level filter?  (Its upper bound brought to this
+// iteration is not below its point-level lower bound.)  Returns the state's
+// slot, group field and that upper bound for the L1 entry.
+__device__ __forceinline__ bool point_fails(const ProbDev &P, int64_t i, float sdu, int &a, int &gf, float &u)
+{
+    const PointState s = P.st[i];
+    a = clamp_slot(P, s.a);
+    gf = s.ga;
+    u = ub_now(s.u, P.Scu[a]);
+    return !(u < lb_now(s.p, sdu));
+}
+
+// Deterministic mode, first pass: failures per chunk of BF_CHUNK points.
+__device__ __forceinline__ void b_bf_count(const ProbDev &P, const int bid_, const int nblk_)
+{
+    __shared__ int wcount[4];
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    const float sdu = P.Sdud[0];
+    for (int64_t b0 = (int64_t)bid_ * BF_CHUNK; b0 < P.n; b0 += (int64_t)nblk_ * BF_CHUNK) {
+        int mine = 0;
+#pragma unroll 4
+        for (int r = 0; r < BF_PER_THREAD; ++r) {
+            const int64_t i = b0 + (int64_t)r * 256 + tid;
+            int a, gf;
+            float u;
+            const bool keep = i < P.n && point_fails(P, i, sdu, a, gf, u);
+            mine += __popcll(__ballot(keep));
+        }
+        if (lane == 0) wcount[wv] = mine;
+        __syncthreads();
+        if (tid == 0) P.dcnt[b0 / BF_CHUNK] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(256) void k_bf_count(ProbDev P) { b_bf_count(P, (int)blockIdx.x, (int)gridDim.x); }
 
 __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_, const int nblk_)
 {
@@ -302,17 +339,10 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
 #pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
-            bool keep = false;
             ka[r] = 0;
             kgf[r] = 0;
             ku[r] = 0.f;
-            if (i < P.n) {
-                const PointState s = P.st[i];
-                ka[r] = clamp_slot(P, s.a);
-                kgf[r] = s.ga;
-                ku[r] = ub_now(s.u, P.Scu[ka[r]]);
-                keep = !(ku[r] < lb_now(s.p, sdu));
-            }
+            const bool keep = i < P.n && point_fails(P, i, sdu, ka[r], kgf[r], ku[r]);
             masks[r] = __ballot(keep);
             mine += __popcll(masks[r]);
         }
@@ -320,7 +350,10 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
         __syncthreads();
         if (tid == 0) {
             const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-            base_s = tot ? atomicAdd(&P.ctr[CTR_L1], (unsigned long long)tot) : 0ull;
+            // deterministic mode: the chunk's place from the scan of the
+            // per-chunk counts (chunk order); otherwise first come, first served
+            base_s = P.det ? (unsigned long long)P.doff[b0 / BF_CHUNK]
+                           : (tot ? atomicAdd(&P.ctr[CTR_L1], (unsigned long long)tot) : 0ull);
         }
         __syncthreads();
         unsigned long long pos = base_s;
@@ -832,16 +865,22 @@ __device__ __forceinline__ float key_value(unsigned k) { return __uint_as_float(
 // against slots 4 (l >> 4) .. +3 of the chunk (hh: leading products, lo: the
 // correction products), reduced over the four lane groups: every lane of
 // point p returns p's two smallest keys.
-__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp)
+// The estimates themselves, clamped at 0 (a squared distance is >= 0, so the
+// clamp only moves an estimate toward the true value).
+__device__ __forceinline__ void chunk_est(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp, float (&v)[4])
 {
     const float cnv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = fmaxf(fmaf(-2.f, hh[r] + lo[r], xnp + cnv[r]), 0.f);
+}
+__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp)
+{
     const unsigned base = 4u * (unsigned)(lane_id() >> 4);
+    float v[4];
+    chunk_est(hh, lo, c4, xnp, v);
     unsigned k[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float v = fmaxf(fmaf(-2.f, hh[r] + lo[r], xnp + cnv[r]), 0.f);
-        k[r] = (__float_as_uint(v) & ~15u) | (base + (unsigned)r);
-    }
+    for (int r = 0; r < 4; ++r) k[r] = (__float_as_uint(v[r]) & ~15u) | (base + (unsigned)r);
     Key2 p = {min(k[0], k[1]), max(k[0], k[1])}, q = {min(k[2], k[3]), max(k[2], k[3])};
     Key2 t = key2_merge(p, q);
     return key2_fold32(key2_fold16(t));
@@ -1362,11 +1401,14 @@ __device__ __forceinline__ void stage_store(ChunkStage<KS> &S, const StageRegs<K
     if (t < 4) S.cn[t] = s.c;
 }
 
+// The two accumulators of a staged chunk against this wave's points: hh the
+// leading products, lo the two correction products.
 template <int KS>
-__device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp)
+__device__ __forceinline__ void chunk_acc(const ChunkStage<KS> &S, const PtFrag<KS> &b, f32x4 &hh, f32x4 &lo)
 {
     const int lane = lane_id();
-    f32x4 hh = {0.f, 0.f, 0.f, 0.f}, lo = {0.f, 0.f, 0.f, 0.f};
+    hh = f32x4{0.f, 0.f, 0.f, 0.f};
+    lo = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 ah = S.a[ks][lane], al = S.a[KS + ks][lane];
@@ -1374,7 +1416,13 @@ __device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<
         lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.h[ks], lo, 0, 0, 0);
         lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], lo, 0, 0, 0);
     }
-    return chunk_keys(hh, lo, S.cn[lane >> 4], xnp);
+}
+template <int KS>
+__device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp)
+{
+    f32x4 hh, lo;
+    chunk_acc<KS>(S, b, hh, lo);
+    return chunk_keys(hh, lo, S.cn[lane_id() >> 4], xnp);
 }
 
 // Chunks of a tile's visits 0 .. nv-1 (workgroup-uniform); src(k, g, m, s0,
@@ -2170,6 +2218,294 @@ __global__ __launch_bounds__(256) void kb_segsum(const ProbDev *__restrict__ pro
 }
 
 
+// ======================================================= deterministic mode
+// kp_tuning.deterministic replaces the three places where the order of
+// floating-point or list work follows the order in which waves happen to run:
+// the positions of the point-filter failures in L1 (one atomic per chunk),
+// the order of equal keys in the counting sorts (LDS atomics) and the FP64
+// atomic adds of the centroid update.  Each list is built in a fixed order
+// instead, and the centroid sums are recomputed from all points in a fixed
+// order.
+
+// Exclusive scan of the per-chunk failure counts into their L1 offsets, and
+// the list length (single workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_bf_scan(ProbDev P, int nchunks)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nchunks + 1023) / 1024;
+    const int b = tid * per, e = min(nchunks, b + per);
+    long long sum = 0;
+    for (int i = b; i < e; ++i) sum += P.dcnt[i];
+    part[tid] = (int)sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - (int)sum;
+    for (int i = b; i < e; ++i) {
+        P.doff[i] = run;
+        run += P.dcnt[i];
+    }
+    if (tid == 1023) P.ctr[CTR_L1] = (unsigned long long)part[1023];
+}
+
+// Lanes of the wave whose key equals this lane's (only active lanes; 0 for an
+// inactive lane): the key compared bit by bit with one ballot per bit.
+__device__ __forceinline__ unsigned long long match_key(int key, int nbits, bool act)
+{
+    unsigned long long m = __ballot(act);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1;
+        const unsigned long long bb = __ballot(act && bit);
+        m &= bit ? bb : ~bb;
+    }
+    return act ? m : 0ull;
+}
+
+// Stable counting sort of E items by key (0 <= key < 2^nbits), block b of
+// SS_NB one-wave blocks owning items [E b / SS_NB, E (b + 1) / SS_NB).
+// hist: counts per (key, block) at key * SS_NB + block (zeroed before);
+// after the scan they are the blocks' first positions per key, and the
+// scatter advances them.  Each (key, block) counter is touched by one wave
+// only, in item order, so every position is fixed by the keys and the input
+// order alone.
+template <class Src>
+__device__ __forceinline__ void b_ss_hist(const Src &src, long long E, int nbits, int *__restrict__ hist)
+{
+    const int b = blockIdx.x, lane = lane_id();
+    const long long lo = E * b / SS_NB, hi = E * (b + 1) / SS_NB;
+    for (long long s0 = lo; s0 < hi; s0 += WAVE) {
+        const long long i = s0 + lane;
+        const bool act = i < hi;
+        const int key = act ? src.key(i) : 0;
+        const unsigned long long m = match_key(key, nbits, act);
+        if (act && lane == __ffsll((long long)m) - 1) atomicAdd(&hist[(size_t)key * SS_NB + b], __popcll(m));
+    }
+}
+template <class Src, class Dst>
+__device__ __forceinline__ void b_ss_scatter(const Src &src, const Dst &dst, long long E, int nbits,
+                                             int *__restrict__ cur)
+{
+    const int b = blockIdx.x, lane = lane_id();
+    const long long lo = E * b / SS_NB, hi = E * (b + 1) / SS_NB;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long long s0 = lo; s0 < hi; s0 += WAVE) {
+        const long long i = s0 + lane;
+        const bool act = i < hi;
+        const int key = act ? src.key(i) : 0;
+        const unsigned long long m = match_key(key, nbits, act);
+        const int leader = act ? __ffsll((long long)m) - 1 : lane;
+        int base = 0;
+        if (act && lane == leader) base = atomicAdd(&cur[(size_t)key * SS_NB + b], __popcll(m));
+        base = __shfl(base, leader);
+        if (act) dst.put((long long)base + __popcll(m & below), i, key);
+    }
+}
+
+// Exclusive scan of the (key, block) table, L = nkeys * SS_NB entries, in three
+// launches: per-workgroup totals, their scan, then each workgroup's part.
+__global__ __launch_bounds__(256) void k_fill0(int *a, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+__device__ __forceinline__ int block_sum_256(int v)
+{
+    __shared__ int red[4];
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    const int t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+__global__ __launch_bounds__(256) void k_ss_scan_part(const int *__restrict__ a, long long L, int *part)
+{
+    const long long lo = L * blockIdx.x / SS_SCAN_BLOCKS, hi = L * (blockIdx.x + 1) / SS_SCAN_BLOCKS;
+    int s = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) s += a[i];
+    s = block_sum_256(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ __launch_bounds__(1024) void k_ss_scan_top(int *part)
+{
+    static_assert(SS_SCAN_BLOCKS == 1024, "one thread per part");
+    __shared__ int sh[1024];
+    const int tid = threadIdx.x;
+    const int v = part[tid];
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int w = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += w;
+        __syncthreads();
+    }
+    part[tid] = sh[tid] - v;
+}
+__global__ __launch_bounds__(256) void k_ss_scan_fin(int *a, long long L, const int *part)
+{
+    __shared__ int sh[256];
+    const long long lo = L * blockIdx.x / SS_SCAN_BLOCKS, hi = L * (blockIdx.x + 1) / SS_SCAN_BLOCKS;
+    const long long len = hi - lo;
+    const long long per = (len + 255) / 256;
+    const long long b = lo + threadIdx.x * per, e = min(hi, b + per);
+    int s = 0;
+    for (long long i = b; i < e; ++i) s += a[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int w = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += w;
+        __syncthreads();
+    }
+    int run = part[blockIdx.x] + sh[threadIdx.x] - s;
+    for (long long i = b; i < e; ++i) {
+        const int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+// The sorts' item sources and destinations.
+struct SrcL1 {   // L1 entries (deterministic order) keyed like the L1 order
+    ProbDev P;
+    __device__ int key(long long i) const
+    {
+        const int4 u = P.L1[i];
+        return l1_key(P, clamp_slot(P, u.y), u.w);
+    }
+};
+struct DstL1 {
+    ProbDev P;
+    __device__ void put(long long pos, long long i, int) const
+    {
+        const int4 u = P.L1[i];
+        const int pid = clamp_pid(P, u.x), a = clamp_slot(P, u.y);
+        if (P.prec) P.L1x[pos] = make_int4(pid, a, u.z, u.w & 0xFFFF);
+        else P.L1s[pos] = pid;
+    }
+};
+struct SrcPts {  // every point, keyed by its assigned slot
+    ProbDev P;
+    __device__ int key(long long i) const { return clamp_slot(P, P.st[i].a); }
+};
+struct DstPts {
+    ProbDev P;
+    __device__ void put(long long pos, long long i, int key) const
+    {
+        P.srt_pt[pos] = (int)i;
+        P.srt_key[pos] = key;
+    }
+};
+__global__ __launch_bounds__(64) void k_ss_hist_l1(ProbDev P)
+{
+    b_ss_hist(SrcL1{P}, list_len(P, CTR_L1), P.nb_l1, P.hist2);
+}
+__global__ __launch_bounds__(64) void k_ss_scatter_l1(ProbDev P)
+{
+    b_ss_scatter(SrcL1{P}, DstL1{P}, list_len(P, CTR_L1), P.nb_l1, P.hist2);
+}
+__global__ __launch_bounds__(64) void k_ss_hist_pts(ProbDev P) { b_ss_hist(SrcPts{P}, P.n, P.nb_slot, P.hist2); }
+__global__ __launch_bounds__(64) void k_ss_scatter_pts(ProbDev P)
+{
+    b_ss_scatter(SrcPts{P}, DstPts{P}, P.n, P.nb_slot, P.hist2);
+}
+
+// Fixed-order centroid sums over the points sorted by (slot, index).  After
+// the scatter, hist2[s * SS_NB + SS_NB - 1] is the end of slot s's segment.
+__device__ __forceinline__ long long seg_end(const ProbDev &P, int s)
+{
+    return s < 0 ? 0 : (long long)P.hist2[(size_t)s * SS_NB + SS_NB - 1];
+}
+// One wave per piece of DS_PIECE sorted positions (lanes over coordinates).
+// Each run of one slot inside the piece is summed in position order: a run
+// that is the slot's whole segment is written to its sums; otherwise it is
+// the piece's first run (it continues a segment from the previous piece) or
+// its last run (the segment continues in the next), kept for k_dsum_fix.
+template <int DCH>
+__global__ __launch_bounds__(256) void k_dsum_piece(ProbDev P)
+{
+    const int lane = lane_id();
+    const long long npieces = (P.n + DS_PIECE - 1) / DS_PIECE;
+    const long long nw = (long long)gridDim.x * (blockDim.x / WAVE);
+    for (long long pc = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; pc < npieces; pc += nw) {
+        const long long ps = pc * DS_PIECE, pe = min((long long)P.n, ps + DS_PIECE);
+        long long pos = ps;
+        while (pos < pe) {
+            const int s = clamp_slot(P, P.srt_key[pos]);
+            const long long ss = seg_end(P, s - 1), se = seg_end(P, s);
+            const long long re = min(pe, se);
+            double acc[DCH];
+#pragma unroll
+            for (int j = 0; j < DCH; ++j) acc[j] = 0.0;
+            constexpr int U = DCH <= 4 ? 8 : 4;   // rows in flight
+            for (long long q0 = pos; q0 < re; q0 += U) {
+                float xv[U][DCH];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = q0 + u < re;
+                    const float *xr = P.X + (size_t)clamp_pid(P, ok ? P.srt_pt[q0 + u] : 0) * P.d;
+#pragma unroll
+                    for (int j = 0; j < DCH; ++j) {
+                        const int dim = lane + WAVE * j;
+                        xv[u][j] = (ok && dim < P.d) ? xr[dim] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < DCH; ++j) acc[j] += (double)xv[u][j];
+            }
+            double *out = (pos == ss && re == se) ? P.sums + (size_t)s * P.d
+                          : (pos != ss) ? P.pfirst + (size_t)pc * P.d : P.plast + (size_t)pc * P.d;
+#pragma unroll
+            for (int j = 0; j < DCH; ++j) {
+                const int dim = lane + WAVE * j;
+                if (dim < P.d) out[dim] = acc[j];
+            }
+            pos = re;
+        }
+    }
+}
+// One wave per slot: the count, and the sum of a segment that spans pieces
+// p0 < p1 as plast[p0] + pfirst[p0 + 1] + ... + pfirst[p1], in that order.
+template <int DCH>
+__global__ __launch_bounds__(256) void k_dsum_fix(ProbDev P)
+{
+    const int lane = lane_id();
+    const int nw = gridDim.x * (blockDim.x / WAVE);
+    for (int s = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; s < P.kg; s += nw) {
+        const long long ss = seg_end(P, s - 1), se = seg_end(P, s);
+        if (lane == 0) P.cnt[s] = (int)(se - ss);
+        if (se <= ss) continue;
+        const long long p0 = ss / DS_PIECE, p1 = (se - 1) / DS_PIECE;
+        if (p0 == p1) continue;   // written whole by k_dsum_piece
+        double acc[DCH];
+#pragma unroll
+        for (int j = 0; j < DCH; ++j) {
+            const int dim = lane + WAVE * j;
+            acc[j] = dim < P.d ? P.plast[(size_t)p0 * P.d + dim] : 0.0;
+        }
+        for (long long p = p0 + 1; p <= p1; ++p)
+#pragma unroll
+            for (int j = 0; j < DCH; ++j) {
+                const int dim = lane + WAVE * j;
+                if (dim < P.d) acc[j] += P.pfirst[(size_t)p * P.d + dim];
+            }
+#pragma unroll
+        for (int j = 0; j < DCH; ++j) {
+            const int dim = lane + WAVE * j;
+            if (dim < P.d) P.sums[(size_t)s * P.d + dim] = acc[j];
+        }
+    }
+}
+
 // ================================================================ serving
 // New query points assigned to a problem's current centroids with the
 // iteration's decision rule -- the assignment step of Section 1 applied to
@@ -2317,6 +2653,88 @@ __global__ __launch_bounds__(256) void k_serve_fp32(ProbDev P, const float *__re
     }
 }
 
+// ============================================================ diagnostics
+// The estimates the distance kernels decide on, and their bounds, for query
+// rows against every centroid: the same point split, chunk staging, matrix
+// products, estimate and key truncation as the assignment, one chunk at a
+// time (no pipelining), every value written out instead of reduced.
+template <int KS>
+__global__ __launch_bounds__(256) void k_probe(ProbDev P, const float *__restrict__ Q, long long nq,
+                                               float *__restrict__ est, float *__restrict__ eta)
+{
+    __shared__ ChunkStage<KS> S;
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
+    const Eta3 ek = mfma_eta3_coef(P.ldb);
+    ProbDev Pq = P;
+    Pq.X = Q;
+    const long long ntiles = (nq + 63) / 64;
+    for (long long tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {   // uniform per workgroup
+        const long long q = tl * 64 + 16 * wv + pt;
+        const bool in = q < nq;
+        float v[KS][8];
+        load_rows16<KS>(Pq, in ? (int)q : 0, in, v);
+        const float xnp = norm_rows16<KS>(v);
+        PtFrag<KS> b;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
+        const float2 eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
+        for (int g = 0; g < P.g; ++g) {
+            const int s0 = P.gstart[g], ns = P.gsize[g];
+            const float2 gc = mfma_eta3_grp(ek, P.gcn[g]);
+            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);
+            for (int c0 = 0; c0 < ns; c0 += CHUNK) {
+                StageRegs<KS> R;
+                stage_load<KS>(P, s0 + c0, R);
+                __syncthreads();   // the previous chunk's reads are done
+                stage_store<KS>(S, R);
+                __syncthreads();
+                f32x4 hh, lo;
+                chunk_acc<KS>(S, b, hh, lo);
+                float ev[4];
+                chunk_est(hh, lo, S.cn[quad], xnp, ev);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int off = c0 + 4 * quad + r;   // slot offset in the group
+                    const int orig = off < ns ? P.perm[s0 + off] : -1;
+                    if (in && orig >= 0) {
+                        est[(size_t)q * P.k + orig] = key_value(__float_as_uint(ev[r]) & ~15u);
+                        eta[(size_t)q * P.k + orig] = e;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Bounds of listed points brought to the current centroids (offset form
+// undone with the drift sums rounded the way the filters round them).
+__global__ void k_bounds(ProbDev P, const int *__restrict__ idx, long long np, float *__restrict__ ub,
+                         float *__restrict__ lbp, float *__restrict__ lb)
+{
+    const float sdu = P.Sdud[0], lsc = P.lbsc[0];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int pid = clamp_pid(P, idx[i]);
+        const PointState s = P.st[pid];
+        const int a = clamp_slot(P, s.a);
+        ub[i] = ub_now(s.u, P.Scu[a]);
+        lbp[i] = lb_now(s.p, sdu);
+        for (int q = 0; q < P.g; ++q) {
+            const size_t o = (size_t)pid * P.gs + q;
+            const float v = (P.prec && P.lb16) ? lb16_dec(P.lbh[o], lsc) : P.lb[o];
+            lb[(size_t)i * P.g + q] = lb_now(v, P.Sgu[q]);
+        }
+    }
+}
+
+__global__ void k_groups_out(ProbDev P, int *out)
+{
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.kg; s += gridDim.x * blockDim.x) {
+        const int o = P.perm[s];
+        if (o >= 0) out[o] = P.slot_group[s];
+    }
+}
+
 // ================================================================ outputs
 __global__ void k_labels(ProbDev P, int *out)
 {
@@ -2418,8 +2836,57 @@ static void launch_survivors(const ProbDev &P, hipStream_t s, const LaunchCfg &c
     }
 }
 
+// FP64 accumulators per lane of the wave-per-row sums: ceil(d / 64), rounded
+// up to 8 or 16 above 4.
+static int dch_class_of(int d)
+{
+    const int c = (d + 63) / 64;
+    return c <= 4 ? c : (c <= 8 ? 8 : 16);
+}
+
+// Deterministic mode: the scan of a (key, block) table of nkeys keys.
+static void launch_ss_scan(const ProbDev &P, hipStream_t s, long long nkeys)
+{
+    const long long L = nkeys * SS_NB;
+    hipLaunchKernelGGL(k_ss_scan_part, dim3(SS_SCAN_BLOCKS), dim3(256), 0, s, (const int *)P.hist2, L, P.spart);
+    hipLaunchKernelGGL(k_ss_scan_top, dim3(1), dim3(1024), 0, s, P.spart);
+    hipLaunchKernelGGL(k_ss_scan_fin, dim3(SS_SCAN_BLOCKS), dim3(256), 0, s, P.hist2, L, (const int *)P.spart);
+}
+static void launch_fill0(int *a, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill0, dim3(cap_grid((n + 255) / 256, 4096)), dim3(256), 0, s, a, n);
+}
+// Deterministic update: all points sorted by (slot, index), then the
+// fixed-order sums.
+template <int DCH>
+static void launch_dsum(const ProbDev &P, hipStream_t s, int grid)
+{
+    hipLaunchKernelGGL(k_dsum_piece<DCH>, dim3(grid), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_dsum_fix<DCH>, dim3(cap_grid((P.kg + 3) / 4, 4096)), dim3(256), 0, s, P);
+}
+static void launch_update_det(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
+{
+    launch_fill0(P.hist2, (long long)P.kg * SS_NB, s);
+    hipLaunchKernelGGL(k_ss_hist_pts, dim3(SS_NB), dim3(64), 0, s, P);
+    launch_ss_scan(P, s, P.kg);
+    hipLaunchKernelGGL(k_ss_scatter_pts, dim3(SS_NB), dim3(64), 0, s, P);
+    const int grid = cap_grid(((P.n + DS_PIECE - 1) / DS_PIECE + 3) / 4, cfg.grid_cap);
+    switch (dch_class_of(P.d)) {
+    case 1: launch_dsum<1>(P, s, grid); break;
+    case 2: launch_dsum<2>(P, s, grid); break;
+    case 3: launch_dsum<3>(P, s, grid); break;
+    case 4: launch_dsum<4>(P, s, grid); break;
+    case 8: launch_dsum<8>(P, s, grid); break;
+    default: launch_dsum<16>(P, s, grid); break;
+    }
+}
+
 static void launch_update(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg)
 {
+    if (P.det) {
+        launch_update_det(P, s, cfg);
+        return;
+    }
     const int ublocks = cap_grid((2 * P.n + 255) / 256, cfg.grid_cap);
     hipLaunchKernelGGL(k_hist, dim3(ublocks), dim3(256), 0, s, P);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist, P.cursor, P.kg);
@@ -2476,10 +2943,23 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
     case ST_BEGIN:
         hipLaunchKernelGGL(k_begin, dim3(cap_grid(((long long)P.nk1 + 256) / 256, 1024)), dim3(256), 0, s, P, dense ? 1 : 0);
         break;
-    case ST_FILTER:
-        hipLaunchKernelGGL(k_bound_filter, dim3(cap_grid((P.n + 4095) / 4096, cfg.grid_cap)), dim3(256), 0, s, P);
+    case ST_FILTER: {
+        const int grid = cap_grid((P.n + BF_CHUNK - 1) / BF_CHUNK, cfg.grid_cap);
+        if (P.det) {
+            hipLaunchKernelGGL(k_bf_count, dim3(grid), dim3(256), 0, s, P);
+            hipLaunchKernelGGL(k_bf_scan, dim3(1), dim3(1024), 0, s, P, (int)((P.n + BF_CHUNK - 1) / BF_CHUNK));
+        }
+        hipLaunchKernelGGL(k_bound_filter, dim3(grid), dim3(256), 0, s, P);
         break;
+    }
     case ST_SORT: {
+        if (P.det) {
+            launch_fill0(P.hist2, (long long)P.nk1 * SS_NB, s);
+            hipLaunchKernelGGL(k_ss_hist_l1, dim3(SS_NB), dim3(64), 0, s, P);
+            launch_ss_scan(P, s, P.nk1);
+            hipLaunchKernelGGL(k_ss_scatter_l1, dim3(SS_NB), dim3(64), 0, s, P);
+            break;
+        }
         const int blocks = cap_grid((P.n + 16383) / 16384, 1024);
         hipLaunchKernelGGL(k_key_hist, dim3(blocks), dim3(256), 0, s, P);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int *)P.hist1, P.cursor1, P.nk1);
@@ -2734,6 +3214,30 @@ hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, c
     case 4: hipLaunchKernelGGL(k_serve_fp32<4>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
     default: hipLaunchKernelGGL(k_serve_fp32<8>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, float *est, float *eta)
+{
+    const int grid = cap_grid((nq + 63) / 64, 4096);
+    switch (P.ldb / 32) {
+    case 1: hipLaunchKernelGGL(k_probe<1>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 2: hipLaunchKernelGGL(k_probe<2>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 3: hipLaunchKernelGGL(k_probe<3>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 4: hipLaunchKernelGGL(k_probe<4>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 6: hipLaunchKernelGGL(k_probe<6>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 8: hipLaunchKernelGGL(k_probe<8>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    default: return hipErrorInvalidValue;   // excluded when the plan is made
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bounds(const ProbDev &P, hipStream_t s, const int *idx, long long np, float *ub, float *lbp,
+                         float *lb, int *groups)
+{
+    if (np > 0)
+        hipLaunchKernelGGL(k_bounds, dim3(cap_grid((np + 255) / 256, 4096)), dim3(256), 0, s, P, idx, np, ub, lbp, lb);
+    if (groups) hipLaunchKernelGGL(k_groups_out, dim3(cap_grid((P.kg + 255) / 256, 1024)), dim3(256), 0, s, P, groups);
     return hipGetLastError();
 }
 

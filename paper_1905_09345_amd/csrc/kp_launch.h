@@ -66,4 +66,10 @@ constexpr size_t SERVE_HEADER = 256;
 hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,
                         int *labels, void *scratch);
 
+// Diagnostics: BF16x3 estimates and bounds of query rows against every
+// centroid (est, eta: nq x k, original order); bounds of listed points.
+hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, float *est, float *eta);
+hipError_t launch_bounds(const ProbDev &P, hipStream_t s, const int *idx, long long np, float *ub, float *lbp,
+                         float *lb, int *groups);
+
 }  // namespace kp

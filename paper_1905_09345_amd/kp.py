@@ -20,7 +20,7 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
            "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_predict_scratch_bytes", "kp_predict",
-           "kp_strerror", "kp_last_error")
+           "kp_probe_estimates", "kp_bounds", "kp_strerror", "kp_last_error")
 
 
 class kp_problem(ctypes.Structure):
@@ -32,7 +32,8 @@ class kp_problem(ctypes.Structure):
 class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32), ("chunk_depth", ctypes.c_int32),
-                ("bound_codes", ctypes.c_int32), ("timing_stages", ctypes.c_int32)]
+                ("bound_codes", ctypes.c_int32), ("timing_stages", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 # stage indices of kp_tuning.timing_stages
@@ -91,6 +92,10 @@ def lib():
         L.kp_predict_scratch_bytes.restype = ctypes.c_size_t
         L.kp_predict.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t]
         L.kp_predict.restype = ctypes.c_int
+        L.kp_probe_estimates.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp]
+        L.kp_probe_estimates.restype = ctypes.c_int
+        L.kp_bounds.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.kp_bounds.restype = ctypes.c_int
         L.kp_strerror.argtypes = [ctypes.c_int]
         L.kp_strerror.restype = ctypes.c_char_p
         L.kp_last_error.argtypes = []
@@ -177,6 +182,17 @@ def kp_autotune(problems, workspace_ptr, workspace_bytes, stream=0, iters=4):
     _check(lib().kp_autotune(arr, n, ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream),
                              int(iters), ctypes.byref(best)), "kp_autotune")
     return best
+
+
+def kp_probe_estimates(ctx, problem, queries_ptr, nq, est_ptr, eta_ptr):
+    _check(lib().kp_probe_estimates(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(queries_ptr), int(nq),
+                                    ctypes.c_void_p(est_ptr), ctypes.c_void_p(eta_ptr)), "kp_probe_estimates")
+
+
+def kp_bounds(ctx, problem, idx_ptr, np_, ub_ptr, lbp_ptr, lb_ptr, group_ptr=None):
+    _check(lib().kp_bounds(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(idx_ptr), int(np_),
+                           ctypes.c_void_p(ub_ptr), ctypes.c_void_p(lbp_ptr), ctypes.c_void_p(lb_ptr),
+                           ctypes.c_void_p(group_ptr)), "kp_bounds")
 
 
 def kp_strerror(status):
@@ -279,6 +295,31 @@ class KMeans:
         # the queued work reads both; held until the next call or close
         self._serve_keep = (q, scratch)
         return out
+
+    def probe_estimates(self, queries, problem=0):
+        """(est, eta) of kp_probe_estimates: (n_q, k) FP32 tensors on the ctx's device."""
+        p = self.problems[problem]
+        q = queries.contiguous()
+        if q.dtype != self._torch.float32 or q.dim() != 2 or q.shape[1] != p.d or q.device != self.device:
+            raise ValueError("queries must be an (n, %d) float32 tensor on %s" % (p.d, self.device))
+        est = self._torch.empty((q.shape[0], p.k), dtype=self._torch.float32, device=self.device)
+        eta = self._torch.empty_like(est)
+        kp_probe_estimates(self.ctx, problem, q.data_ptr(), q.shape[0], est.data_ptr(), eta.data_ptr())
+        self._torch.cuda.current_stream(self.device).synchronize()
+        return est, eta
+
+    def bounds(self, idx, problem=0):
+        """(ub, lbp, lb, group) of kp_bounds for the int32 point indices idx."""
+        p = self.problems[problem]
+        ix = idx.to(device=self.device, dtype=self._torch.int32).contiguous()
+        n = ix.shape[0]
+        ub = self._torch.empty(n, dtype=self._torch.float32, device=self.device)
+        lbp = self._torch.empty_like(ub)
+        lb = self._torch.empty((n, p.g), dtype=self._torch.float32, device=self.device)
+        grp = self._torch.empty(p.k, dtype=self._torch.int32, device=self.device)
+        kp_bounds(self.ctx, problem, ix.data_ptr(), n, ub.data_ptr(), lbp.data_ptr(), lb.data_ptr(), grp.data_ptr())
+        self._torch.cuda.current_stream(self.device).synchronize()
+        return ub, lbp, lb, grp
 
     def centroids(self, problem=0):
         p = self.problems[problem]

@@ -52,6 +52,15 @@ def check_centroids(X, labels, c_prev64, c32, c64, scale):
     return cnt
 
 
+def rms_norm(X, chunk=1 << 20):
+    """sqrt of the mean squared norm of the rows of X (FP64, in chunks)."""
+    tot = 0.0
+    for s in range(0, X.shape[0], chunk):
+        xs = X[s:s + chunk].astype(np.float64)
+        tot += float((xs * xs).sum())
+    return float(np.sqrt(tot / max(X.shape[0], 1)))
+
+
 def run_steplocked(X, C0, g, precision, iters, *, seed=0, tuning=None, sample=None, check_every=1,
                    rng_seed=0):
     """Run `iters` GPU iterations one at a time and check each against the oracle.
@@ -67,7 +76,7 @@ def run_steplocked(X, C0, g, precision, iters, *, seed=0, tuning=None, sample=No
     Cd = torch.from_numpy(np.ascontiguousarray(C0)).cuda()
     km = KMeans([(Xd, Cd, g, precision, seed)], tuning=tuning)
     rng = np.random.default_rng(rng_seed)
-    scale = float(np.sqrt((X.astype(np.float64) ** 2).sum(axis=1).mean()))
+    scale = rms_norm(X)
     c32p, c64p = C0.astype(np.float32), C0.astype(np.float64)
     report = dict(mismatch=[], allowed=[], checked=[])
     try:
@@ -92,33 +101,45 @@ def run_steplocked(X, C0, g, precision, iters, *, seed=0, tuning=None, sample=No
     return report
 
 
-def run_steplocked_batch(problems, iters, *, tuning=None, check_every=1):
+def run_steplocked_batch(problems, iters, *, tuning=None, check_every=1, sample=None, rng_seed=0):
     """Several problems in one ctx (batched launches), each checked step-locked
     against the oracle as in run_steplocked.  problems: list of
-    (X, C0, g, precision).  Returns one report per problem."""
+    (X, C0, g, precision).  sample: when given, each problem's assignment
+    check uses that many seeded random points (its centroid check uses all
+    of them).  Returns one report per problem."""
     import torch
     from paper_1905_09345_amd import KMeans
 
     dev = [(torch.from_numpy(np.ascontiguousarray(X)).cuda(), torch.from_numpy(np.ascontiguousarray(C0)).cuda(),
             g, prec, 0) for X, C0, g, prec in problems]
     km = KMeans(dev, tuning=tuning)
+    rng = np.random.default_rng(rng_seed)
     prev = [(C0.astype(np.float32), C0.astype(np.float64)) for _, C0, _, _ in problems]
-    scales = [float(np.sqrt((X.astype(np.float64) ** 2).sum(axis=1).mean())) for X, _, _, _ in problems]
+    scales = [rms_norm(X) for X, _, _, _ in problems]
     reports = [dict(mismatch=[], allowed=[]) for _ in problems]
+
+    def checked(t):
+        return t % check_every == 0 or t == 1 or t == iters
     try:
         for t in range(1, iters + 1):
+            if t > 1 and checked(t) and not checked(t - 1):
+                prev = [tuple(a.cpu().numpy() for a in km.centroids(i)) for i in range(len(problems))]
             km.iterate(1)
+            if not checked(t):
+                continue
             for i, (X, _, _, _) in enumerate(problems):
                 lab = km.assign(i).cpu().numpy()
                 c32, c64 = [a.cpu().numpy() for a in km.centroids(i)]
-                if t % check_every == 0 or t == 1 or t == iters:
-                    try:
-                        m, a = check_assignment(X, prev[i][0], lab)
-                        check_centroids(X, lab, prev[i][1], c32, c64, scales[i])
-                    except AssertionError as e:
-                        raise AssertionError("problem %d, iteration %d: %s" % (i, t, e))
-                    reports[i]["mismatch"].append(m)
-                    reports[i]["allowed"].append(a)
+                idx = None
+                if sample is not None and sample < X.shape[0]:
+                    idx = np.sort(rng.choice(X.shape[0], size=sample, replace=False))
+                try:
+                    m, a = check_assignment(X, prev[i][0], lab, idx)
+                    check_centroids(X, lab, prev[i][1], c32, c64, scales[i])
+                except AssertionError as e:
+                    raise AssertionError("problem %d, iteration %d: %s" % (i, t, e))
+                reports[i]["mismatch"].append(m)
+                reports[i]["allowed"].append(a)
                 prev[i] = (c32, c64)
         for i in range(len(problems)):
             reports[i]["stats"] = km.stats(i)

@@ -40,7 +40,8 @@ def test_c3_shape_bf16():
     r = run_steplocked(P.X, P.C0, P.g, "bf16", 6)
     st = r["stats"]
     assert st[0]["dense"] == 1
-    assert sum(s["rechecks"] for s in st) >= 0
+    # the FP32 recheck runs: the uncertain points of the dense first pass
+    assert st[0]["rechecks"] > 0
 
 
 def test_c5_shape_bf16():
