@@ -227,6 +227,19 @@ size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq);
 kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries_dev, int64_t nq, int32_t *labels_dev,
                      void *scratch_dev, size_t scratch_bytes);
 
+/* Serving for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): as
+ * kp_predict, but the scratch is a fixed array the library holds on each
+ * device it runs on (until the process ends), so the call allocates nothing.
+ * nq may be at most KP_PREDICT_NOALLOC_MAX_QUERIES (KP_ERR_INVALID above it;
+ * the array is 16 MiB + 256 bytes).  Every call on one device shares that
+ * device's array, whose counter each call clears before use: calls that
+ * overlap on one device (other streams or threads) race and must not be
+ * issued.  Same labels as kp_predict; same argument errors. */
+#define KP_PREDICT_NOALLOC_MAX_QUERIES 4194304
+kp_status kp_predict_noalloc(kp_ctx *ctx, int32_t problem, const float *queries_dev, int64_t nq,
+                             int32_t *labels_dev);
+
 /* Synchronise and release the ctx's host resources, stream and graph.  The
  * workspace and points are the caller's to free afterwards.  NULL is a
  * no-op. */

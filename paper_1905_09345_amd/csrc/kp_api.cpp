@@ -451,6 +451,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         if (tuning->timing_stages) ctx->timed_stages = (unsigned)tuning->timing_stages;
     }
     KP_HIP(hipGetDevice(&ctx->device));
+    KP_HIP(kp::noalloc_scratch_setup(ctx->device));   // kp_predict_noalloc's scratch on this device
     KP_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
     KP_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
     KP_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
@@ -878,6 +879,33 @@ kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries, int64_t
     if (scratch_bytes < need) {
         set_error("scratch of %zu bytes, %zu needed", scratch_bytes, need);
         return KP_ERR_INVALID;
+    }
+    KP_HIP(kp::launch_serve(ctx->P[problem], ctx->user, ctx->cfg, queries, (long long)nq, labels, scratch));
+    return KP_OK;
+}
+
+kp_status kp_predict_noalloc(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, int32_t *labels)
+{
+    kp_status st = check_ctx(ctx);
+    if (st != KP_OK) return st;
+    if (problem < 0 || problem >= ctx->count) {
+        set_error("bad problem index %d", problem);
+        return KP_ERR_INVALID;
+    }
+    if (nq < 0 || nq > kp::NOALLOC_MAX_QUERIES) {
+        set_error("nq=%lld outside 0..%lld (the fixed scratch of kp_predict_noalloc)", (long long)nq,
+                  (long long)kp::NOALLOC_MAX_QUERIES);
+        return KP_ERR_INVALID;
+    }
+    if (nq == 0) return KP_OK;
+    if (!queries || !labels || ((uintptr_t)queries & 15u) != 0) {
+        set_error("NULL or misaligned queries, or NULL labels");
+        return KP_ERR_INVALID;
+    }
+    void *scratch = kp::noalloc_scratch(ctx->device);
+    if (!scratch) {
+        set_error("no scratch address for device %d", ctx->device);
+        return KP_ERR_STATE;
     }
     KP_HIP(kp::launch_serve(ctx->P[problem], ctx->user, ctx->cfg, queries, (long long)nq, labels, scratch));
     return KP_OK;

@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <climits>
+#include <mutex>
 
 namespace kp {
 
@@ -3178,6 +3179,36 @@ hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out)
 {
     hipLaunchKernelGGL(k_labels, dim3(cap_grid((P.n + 255) / 256, 4096)), dim3(256), 0, s, P, out);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ serving without allocation
+// Scratch of kp_predict_noalloc: the uncertain-query counter (SERVE_HEADER
+// bytes) and the list of uncertain queries (4 bytes per query).  Each device
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name is not a device address: its address on a device is
+// taken once with hipGetSymbolAddress, with that device current, and kept.
+static __device__ __align__(256) unsigned char scratch[SERVE_HEADER + 4 * (size_t)NOALLOC_MAX_QUERIES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,

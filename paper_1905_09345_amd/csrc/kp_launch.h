@@ -63,6 +63,14 @@ hipError_t launch_centroids_out(const ProbDev &P, hipStream_t s, float *c32, dou
 // Serving: labels of nq query rows against the problem's current centroids.
 // scratch: SERVE_HEADER bytes (uncertain-query counter) + 4 nq bytes (list).
 constexpr size_t SERVE_HEADER = 256;
+// Serving without allocation: the largest query count of kp_predict_noalloc,
+// whose scratch is a fixed per-device array inside the library.
+constexpr long long NOALLOC_MAX_QUERIES = 1ll << 22;
+// Once per device, with that device current: take the device address of the
+// fixed scratch array and keep it.  The address for a device after setup
+// (nullptr before).
+hipError_t noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
 hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,
                         int *labels, void *scratch);
 

@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
-           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_predict_scratch_bytes", "kp_predict",
+           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_predict_scratch_bytes", "kp_predict", "kp_predict_noalloc",
            "kp_probe_estimates", "kp_bounds", "kp_strerror", "kp_last_error")
 
 
@@ -92,6 +92,8 @@ def lib():
         L.kp_predict_scratch_bytes.restype = ctypes.c_size_t
         L.kp_predict.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t]
         L.kp_predict.restype = ctypes.c_int
+        L.kp_predict_noalloc.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp]
+        L.kp_predict_noalloc.restype = ctypes.c_int
         L.kp_probe_estimates.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp]
         L.kp_probe_estimates.restype = ctypes.c_int
         L.kp_bounds.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp, vp]
@@ -182,6 +184,14 @@ def kp_autotune(problems, workspace_ptr, workspace_bytes, stream=0, iters=4):
     _check(lib().kp_autotune(arr, n, ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream),
                              int(iters), ctypes.byref(best)), "kp_autotune")
     return best
+
+
+KP_PREDICT_NOALLOC_MAX_QUERIES = 1 << 22
+
+
+def kp_predict_noalloc(ctx, problem, queries_ptr, nq, labels_ptr):
+    _check(lib().kp_predict_noalloc(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(queries_ptr), int(nq),
+                                    ctypes.c_void_p(labels_ptr)), "kp_predict_noalloc")
 
 
 def kp_probe_estimates(ctx, problem, queries_ptr, nq, est_ptr, eta_ptr):
