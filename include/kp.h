@@ -275,12 +275,17 @@ kp_status kp_autotune(const kp_problem *problems_host, int32_t count, void *work
  * estimate v of ||q_i - c_j||^2 that the decisions compare (the key value,
  * low significand bits cleared) and eta_dev[i*k + j] a bound with
  * |v - ||q_i - c_j||^2| <= eta in exact arithmetic on the FP32 inputs.  j is
- * the original centroid index.  Outputs are caller-owned device buffers of
- * nq*k FP32.  Queued on the ctx's stream.  KP_ERR_UNSUPPORTED for an FP32
- * problem; KP_ERR_INVALID for a bad index, NULL or misaligned pointers or nq
- * outside 0..2^31-1 (nq = 0 is a no-op). */
+ * the original centroid index.  anchor = -1 gives the estimate of the first
+ * (dense) iteration and of serving; anchor = a (an original centroid index)
+ * gives the form the filtered iterations use for a tile of points sorted to
+ * centroid a: every query and centroid taken relative to c_a.  Outputs are
+ * caller-owned device buffers of nq*k FP32.  Queued on the ctx's stream.
+ * KP_ERR_UNSUPPORTED for an FP32 problem, or an anchor on a problem with more
+ * than 16384 centroid slots (which keeps no anchor tables); KP_ERR_INVALID
+ * for a bad index or anchor, NULL or misaligned pointers or nq outside
+ * 0..2^31-1 (nq = 0 is a no-op). */
 kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries_dev, int64_t nq,
-                             float *est_dev, float *eta_dev);
+                             int32_t anchor, float *est_dev, float *eta_dev);
 
 /* The bounds the filters of Section 1 keep for the listed points, brought
  * to the current centroids (after the latest update): for each i < np with

@@ -7,8 +7,9 @@
 // seed, five Lloyd iterations, every empty group filled with the member of
 // the largest group that lies farthest from that group's center, and group
 // sizes capped at the smallest multiple of 16 (one matrix-core chunk) that
-// holds k / g.  The grouping only changes how much work the filter saves,
-// never the result.
+// holds k / g, and (BF16 problems) the medoid of every chunk in its first
+// slot.  The grouping only changes how much work the filter saves and how
+// tight the BF16 error bounds are, never the result.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -45,7 +46,7 @@ double sq(const float *a, const double *b, int d)
 
 }  // namespace
 
-Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed)
+Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed, bool chunk_medoids)
 {
     std::vector<int> lab(k, 0);
     if (g >= k) {
@@ -178,6 +179,37 @@ Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed)
         int s = out.gstart[q] + fill[q]++;
         out.perm[s] = j;
         out.slot_group[s] = q;
+    }
+    // The first slot of every chunk is the reference the kernels express the
+    // chunk's other rows against (their products and error bounds scale with
+    // the distance to it): move the chunk's medoid there, the member with the
+    // least summed distance to the others (the lowest original index among
+    // equals).  A far member then costs precision in its own row only.
+    for (int q = 0; chunk_medoids && q < g; ++q) {
+        for (int c0 = 0; c0 < out.gsize[q]; c0 += CHUNK_SLOTS) {
+            const int s0 = out.gstart[q] + c0, m = std::min(CHUNK_SLOTS, out.gsize[q] - c0);
+            int best = 0;
+            double bv = std::numeric_limits<double>::infinity();
+            for (int i = 0; i < m; ++i) {
+                const float *ci = C + (size_t)out.perm[s0 + i] * d;
+                double tot = 0.0;
+                for (int j = 0; j < m; ++j) {
+                    if (j == i) continue;
+                    const float *cj = C + (size_t)out.perm[s0 + j] * d;
+                    double t2 = 0.0;
+                    for (int e = 0; e < d; ++e) {
+                        const double t = (double)ci[e] - (double)cj[e];
+                        t2 += t * t;
+                    }
+                    tot += std::sqrt(t2);
+                }
+                if (tot < bv) {   // members ascend by original index, so the first of equals stays
+                    bv = tot;
+                    best = i;
+                }
+            }
+            std::swap(out.perm[s0], out.perm[s0 + best]);
+        }
     }
     return out;
 }

@@ -17,7 +17,9 @@ struct Grouping {
     std::vector<int> gsize;       // members per group
 };
 
-// Group the k centroids (k x d FP32, row-major) into g groups.
-Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed);
+// Group the k centroids (k x d FP32, row-major) into g groups; with
+// chunk_medoids the first slot of every 16-slot chunk holds the chunk's
+// medoid, otherwise slots ascend by original index within a group.
+Grouping make_groups(const float *C, int k, int d, int g, uint64_t seed, bool chunk_medoids);
 
 }  // namespace kp

@@ -33,15 +33,17 @@ void set_error(const char *fmt, ...)
 }
 
 constexpr size_t ALIGN = 256;
+constexpr size_t ANCHOR_MAX_SLOTS = 16384;   // largest slot count with anchor tables (Qt <= 1 GiB)
 inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, gcn, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, nrel, Wu, Qt, Wa, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
         cursor1, ctr, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
+    bool anch;       // BF16 filtered tiles use estimates relative to an anchor centroid
     size_t nk1max;   // keys of the L1 order for kgmax slots
 };
 
@@ -92,7 +94,15 @@ Plan plan_problem(const kp_problem &p, bool lb16, bool det)
     o.Scd = take(kgm * 4);
     o.Sgu = take((size_t)g * 4);
     o.Sgd = take((size_t)g * 4);
-    o.gcn = take((size_t)g * 4);
+    // BF16 mode: relative norms and per-chunk bounds of the chunk rows; with
+    // anchors, the slot-to-slot table of squared distances and the
+    // per-(anchor, chunk) bounds (kgmax <= ANCHOR_MAX_SLOTS keeps them <= 1 GiB)
+    const size_t nchm = kgm / kp::CHUNK;
+    o.anch = bf && kgm <= ANCHOR_MAX_SLOTS;
+    o.nrel = take(bf ? kgm * 4 : 0);
+    o.Wu = take(bf ? nchm * 8 : 0);
+    o.Qt = take(o.anch ? kgm * kgm * 4 : 0);
+    o.Wa = take(o.anch ? kgm * nchm * 8 : 0);
     o.Sdud = take(8);
     o.L1 = take(n * 16);
     o.L1s = take(n * 4);
@@ -338,6 +348,7 @@ struct kp_ctx {
     hipStream_t user = nullptr, own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<kp::ProbDev> P;
+    std::vector<std::vector<int>> slot_of;    // per problem: original centroid index -> slot
     kp::Batch batch;                           // count > 1: batched launches
     kp::LaunchCfg cfg{4, 4096, 1, false};
     int use_graph = 1;
@@ -465,7 +476,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         hc.resize((size_t)p.k * p.d);
         KP_HIP(hipMemcpyAsync(hc.data(), p.init_centroids_dev, hc.size() * 4, hipMemcpyDeviceToHost, ctx->user));
         KP_HIP(hipStreamSynchronize(ctx->user));
-        kp::Grouping G = kp::make_groups(hc.data(), p.k, p.d, p.g, p.seed);
+        kp::Grouping G = kp::make_groups(hc.data(), p.k, p.d, p.g, p.seed, p.precision == KP_PREC_BF16_RECHECK);
         kp::ProbDev P;
         std::memset(&P, 0, sizeof P);
         P.n = p.n;
@@ -505,7 +516,12 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Scd = (float *)(base + o.Scd);
         P.Sgu = (float *)(base + o.Sgu);
         P.Sgd = (float *)(base + o.Sgd);
-        P.gcn = (float *)(base + o.gcn);
+        P.nch = G.kg / kp::CHUNK;
+        P.nrel = (float *)(base + o.nrel);
+        P.Wu = (float2 *)(base + o.Wu);
+        P.anch = o.anch ? 1 : 0;
+        P.Qt = (float *)(base + o.Qt);
+        P.Wa = (float2 *)(base + o.Wa);
         P.Sdud = (float *)(base + o.Sdud);
         P.L1 = (int4 *)(base + o.L1);
         P.L1s = (int *)(base + o.L1s);
@@ -545,6 +561,12 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
                               ctx->user));
         KP_HIP(hipMemcpyAsync((void *)P.gsize, G.gsize.data(), G.gsize.size() * 4, hipMemcpyHostToDevice,
                               ctx->user));
+        {
+            std::vector<int> so((size_t)p.k, 0);
+            for (size_t sl = 0; sl < G.perm.size(); ++sl)
+                if (G.perm[sl] >= 0) so[(size_t)G.perm[sl]] = (int)sl;
+            ctx->slot_of.push_back(std::move(so));
+        }
         KP_HIP(kp::launch_prep(P, ctx->user, p.init_centroids_dev));
         KP_HIP(hipStreamSynchronize(ctx->user));   // host vectors above are reused
         ctx->P.push_back(P);
@@ -911,7 +933,8 @@ kp_status kp_predict_noalloc(kp_ctx *ctx, int32_t problem, const float *queries,
     return KP_OK;
 }
 
-kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, float *est, float *eta)
+kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, int32_t anchor,
+                             float *est, float *eta)
 {
     kp_status st = check_ctx(ctx);
     if (st != KP_OK) return st;
@@ -927,12 +950,25 @@ kp_status kp_probe_estimates(kp_ctx *ctx, int32_t problem, const float *queries,
         set_error("problem %d is not a BF16 problem", problem);
         return KP_ERR_UNSUPPORTED;
     }
+    const kp::ProbDev &P = ctx->P[problem];
+    if (anchor < -1 || anchor >= P.k) {
+        set_error("anchor %d outside -1..k-1", anchor);
+        return KP_ERR_INVALID;
+    }
+    if (anchor >= 0 && !P.anch) {
+        set_error("problem %d keeps no anchor tables (too many centroid slots)", problem);
+        return KP_ERR_UNSUPPORTED;
+    }
     if (nq == 0) return KP_OK;
     if (!queries || !est || !eta || ((uintptr_t)queries & 15u) != 0) {
         set_error("NULL or misaligned queries, NULL outputs");
         return KP_ERR_INVALID;
     }
-    KP_HIP(kp::launch_probe(ctx->P[problem], ctx->user, queries, (long long)nq, est, eta));
+    int slot = -1;
+    if (anchor >= 0) {   // the anchor's slot (the grouping's permutation is kept on the host)
+        slot = ctx->slot_of[problem][anchor];
+    }
+    KP_HIP(kp::launch_probe(P, ctx->user, queries, (long long)nq, slot, est, eta));
     return KP_OK;
 }
 

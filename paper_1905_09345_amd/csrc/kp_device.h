@@ -91,7 +91,13 @@ struct ProbDev {
     double *Sc, *Sg, *Sd;     // cumulative drifts (kg, g, 1), FP64
     float *Scu, *Scd;         // FP32 copies of Sc rounded up / down
     float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
-    float *gcn;               // per group: an upper bound on its members' FP32 norms ||c||
+    int nch;                  // 16-slot chunks: kg / CHUNK (every group is padded to whole chunks)
+    float *nrel;              // per slot j: ||fl(c_j - c_f)|| rounded up, f the first slot of j's chunk (0 for f)
+    float2 *Wu;               // per chunk: (W, c W^2) of the estimate without an anchor, W >= ||c_f||
+    int anch;                 // BF16 mode: filtered tiles take their estimates relative to an anchor centroid
+    float *Qt;                // anch: kg x kg, ||c_j - c_a||^2 (row a, column j; FP64, rounded to nearest; +inf
+                              // for padding j)
+    float2 *Wa;               // anch: kg x nch, (W, c W^2) per (anchor a, chunk), W >= ||c_f - c_a||
     float *Sdud;              // [0] Sd rounded up, [1] Sd rounded down
     int4 *L1;                 // points failing the point-level filter (filter order): {point, slot, ub now, group field}
     int *L1s;                 // FP32 mode: the same ids sorted by assigned slot (and nearest other group, bucketed)
@@ -276,26 +282,58 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 // (1 + 2^-20) (1 + 2^-16), which covers the seven roundings of the evaluation
 // (each <= u relative, on sums and products of non-negative terms), and
 // rounded up.
+//
+// Estimates relative to an anchor.  The chunk rows are not c_j but
+// c~_j = fl(c_j - c_f), f the chunk's first slot (row f itself keeps c_f),
+// and a tile of points may be taken relative to an anchor centroid r = c_a:
+// x~ = fl(x - r), w~ = fl(c_f - r) staged as the chunk's first row, and
+//   v = fl(fl(xn + Q_j) - 2 S),  S = fl(x~.c~_j + x~.w~)   (S = x~.w~ for j = f)
+// with xn the squared norm of x~ (FP64 sum rounded) and Q_j = ||c_j - r||^2
+// (FP64, rounded).  Without an anchor r = 0: x~ = x, w~ = c_f and Q_j =
+// ||c_j||^2.  With A >= ||x~||, W >= ||w~|| and N_j >= ||c~_j||, B_j = W + N_j
+// (the triangle inequality gives ||c_j - r|| <= B_j as well), the errors add
+// up to
+//   rounding of x~ and of w~ + c~_j: (2u + u^2) A^2 + 4.04 u A B_j
+//   the two products and the added S: 2 (kappa + 1.01 u) A B_j
+//   xn, Q_j, their sum and the final fused multiply-add: 1.01 u each, of
+//     A^2, B_j^2, A^2 + B_j^2 and (A + B_j)^2
+// and the bounds L = fl(v - e), U = fl(v + e) formed from v round once more
+// (1.01 u (A + B_j)^2), so with
+//   a = 6.05 u,  b = 2 kappa + 10.1 u,  c = 4.04 u
+// and e_j = a A^2 + b A B_j + c B_j^2, both L <= ||x - c_j||^2 <= U hold.
+// Per row this is evaluated as e_j = E0 + N_j (h + c N_j) from the chunk's
+// E0 = a A^2 + b A W + c W^2 and h = b A + 2 c W (every term is
+// nonnegative; the coefficients' margin covers the rounding of these FP32
+// operations).
+// Relative to an anchor near the point (its assigned centroid), A is the
+// distance to it and W, N_j distances between nearby centroids, so e_j shrinks
+// with the cell sizes instead of the norms, row by row.
 struct Eta3 {
     float a, b;
 };
+__host__ __device__ __forceinline__ double mfma_eta3_scale() { return (1.0 + 0x1p-20) * (1.0 + 0x1p-16); }
 __device__ __forceinline__ Eta3 mfma_eta3_coef(int ldb)
 {
     const double u = 5.9604644775390625e-08;
     const double kappa = 3.02 * 0x1p-16 + 2.1 * (double)(ldb + 2) * u + 2.05 * u;
-    const double s = (1.0 + 0x1p-20) * (1.0 + 0x1p-16);
     Eta3 k;
-    k.a = d2f_up((3.02 * u + 1.01 * 0x1p-19) * s);
-    k.b = d2f_up((2.0 * kappa + 2.02 * u + 2.02 * 0x1p-19) * s);
+    k.a = d2f_up(6.05 * u * mfma_eta3_scale());
+    k.b = d2f_up((2.0 * kappa + 10.1 * u) * mfma_eta3_scale());
     return k;
 }
-// A >= ||x|| from the point's squared norm rounded to FP32, once per point.
+__host__ __device__ __forceinline__ double mfma_eta3_c() { return 4.04 * 5.9604644775390625e-08 * mfma_eta3_scale(); }
+// A >= ||x~|| from its squared norm rounded to FP32, once per point.
 __device__ __forceinline__ float mfma_eta3_a(float xn) { return d2f_up(sqrt((double)xn) * (1.0 + 0x1p-22)); }
-// eta = fma(pt.x, grp.x, pt.y + grp.y) for a point with bound A and a chunk
-// whose group has bound C (both FP32, rounded up): pt = (b A, a A^2), grp =
-// (C, a C^2).
+// c and 2 c as FP32 constants, rounded up (2 c exactly twice c).
+constexpr float ETA3_C = (float)(4.04 * 0x1p-24 * (1.0 + 0x1p-20) * (1.0 + 0x1p-16) * (1.0 + 0x1p-22));
+constexpr float ETA3_C2 = 2.f * ETA3_C;
+// Per point: (b A, a A^2).
 __device__ __forceinline__ float2 mfma_eta3_pt(const Eta3 &k, float A) { return make_float2(k.b * A, k.a * (A * A)); }
-__device__ __forceinline__ float2 mfma_eta3_grp(const Eta3 &k, float C) { return make_float2(C, k.a * (C * C)); }
+// A chunk's (W, c W^2), the second rounded up (the tables hold it).
+__device__ __forceinline__ float2 mfma_eta3_w(float W)
+{
+    return make_float2(W, d2f_up(mfma_eta3_c() * (double)W * (double)W * (1.0 + 0x1p-50)));
+}
 
 // --------------------------------------------------- tuple merge (d^2, slot, second)
 struct Best3 {

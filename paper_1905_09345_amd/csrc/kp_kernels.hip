@@ -102,8 +102,17 @@ __global__ __launch_bounds__(256) void k_prep(ProbDev P)
 // ============================================================ centroid rows
 // One wave per slot.  INIT: take the caller's initial centroids (original
 // order).  Otherwise: c64 = sums / count (a centroid with no point keeps its
-// value), then the FP32 copy, its BF16 rounding, ||c_hat||^2, ||c - c_hat||
-// and the drift ||c32_new - c32_old|| (FP64, rounded up).
+// value), then the FP32 copy, ||c32||^2 and the drift ||c32_new - c32_old||
+// (FP64, rounded up).  BF16 mode: the slot's row of the matrix-core operand
+// is the BF16 split of c32 for the first slot f of its 16-slot chunk and of
+// c~ = fl(c32 - c32_f) for the others (the chunk's rows relative to its first
+// one), with ||c~|| rounded up in nrel.  c32_f is recomputed here from the
+// same sums (the wave of slot f writes the same values).
+__device__ __forceinline__ double new_c64(const ProbDev &P, int s, int j, int cntv, bool init, const float *init_c)
+{
+    if (init) return (double)init_c[(size_t)P.perm[s] * P.d + j];
+    return cntv > 0 ? P.sums[(size_t)s * P.d + j] / (double)cntv : P.c64[(size_t)s * P.d + j];
+}
 template <bool INIT>
 __device__ __forceinline__ void b_centroids(const ProbDev &P, const int bid_, const int nblk_, const float *init)
 {
@@ -125,30 +134,32 @@ __device__ __forceinline__ void b_centroids(const ProbDev &P, const int bid_, co
                 if (lane == 0) {
                     P.cn[s] = KP_INF;
                     P.delta[s] = 0.0;
+                    P.nrel[s] = 0.f;
                 }
             }
             continue;
         }
         const int cntv = INIT ? 0 : P.cnt[s];
-        double dd = 0.0, q = 0.0;
+        const int f = s & ~(CHUNK - 1);   // first slot of the chunk (always a member)
+        const int cntf = INIT ? 0 : P.cnt[f];
+        double dd = 0.0, q = 0.0, qr = 0.0;
         for (int j = lane; j < L; j += WAVE) {
-            double c64v = 0.0;
+            double c64v = 0.0, c64f = 0.0;
             float oldc = 0.f;
             if (j < P.d) {
-                if (INIT) {
-                    c64v = (double)init[(size_t)orig * P.d + j];
-                } else {
-                    oldc = P.c32[(size_t)s * P.ldc + j];
-                    c64v = cntv > 0 ? P.sums[(size_t)s * P.d + j] / (double)cntv : P.c64[(size_t)s * P.d + j];
-                }
+                if (!INIT) oldc = P.c32[(size_t)s * P.ldc + j];
+                c64v = new_c64(P, s, j, cntv, INIT, init);
+                c64f = f == s ? c64v : new_c64(P, f, j, cntf, INIT, init);
                 P.c64[(size_t)s * P.d + j] = c64v;
             }
             const float c32v = (float)c64v;
             if (j < P.ldc) P.c32[(size_t)s * P.ldc + j] = c32v;
             if (P.prec) {
-                const uint16_t h = f2bf(c32v);
+                const float rel = f == s ? c32v : c32v - (float)c64f;
+                const uint16_t h = f2bf(rel);
                 P.cb[(size_t)s * P.ldb + j] = h;
-                P.cbl[(size_t)s * P.ldb + j] = f2bf(c32v - bf2f(h));
+                P.cbl[(size_t)s * P.ldb + j] = f2bf(rel - bf2f(h));
+                if (f != s) qr += (double)rel * rel;
             }
             const double df = (double)c32v - (double)oldc;
             dd += df * df;
@@ -156,9 +167,11 @@ __device__ __forceinline__ void b_centroids(const ProbDev &P, const int bid_, co
         }
         dd = wave_sum_d(dd);
         q = wave_sum_d(q);
+        qr = wave_sum_d(qr);
         if (lane == 0) {
             P.delta[s] = INIT ? 0.0 : sqrt(dd) * (1.0 + 0x1p-46);
             P.cn[s] = (float)q;
+            if (P.prec) P.nrel[s] = qr > 0.0 ? d2f_up(sqrt(qr) * (1.0 + 0x1p-46)) : 0.f;
         }
     }
 }
@@ -187,16 +200,17 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
     const int tid = threadIdx.x;
     const double up = 1.0 + 0x1p-50;
     double gmax = 0.0;
+    if (P.prec)
+        for (int ch = tid; ch < P.nch; ch += blockDim.x) {
+            // (W, c W^2) of the estimate without an anchor, W >= ||c_f||
+            // (cn: FP64 squared norm rounded to FP32)
+            const int f = ch * CHUNK;
+            P.Wu[ch] = mfma_eta3_w(d2f_up(sqrt((double)P.cn[f]) * (1.0 + 0x1p-22)));
+        }
     for (int g = tid; g < P.g; g += blockDim.x) {
         double m = 0.0;
-        float cm = 0.f;
         const int s0 = P.gstart[g], ns = P.gsize[g];
-        for (int r = 0; r < ns; ++r) {
-            m = fmax(m, P.delta[s0 + r]);
-            if (P.perm[s0 + r] >= 0) cm = fmaxf(cm, P.cn[s0 + r]);
-        }
-        // the largest member norm (cn: FP64 squared norm rounded to FP32)
-        P.gcn[g] = d2f_up(sqrt((double)cm) * (1.0 + 0x1p-22));
+        for (int r = 0; r < ns; ++r) m = fmax(m, P.delta[s0 + r]);
         const double sg = first ? 0.0 : (P.Sg[g] + m) * up;
         P.Sg[g] = sg;
         P.Sgu[g] = d2f_up(sg);
@@ -257,6 +271,76 @@ __global__ __launch_bounds__(1024) void kb_drift(const ProbDev *__restrict__ pro
     const int pi = batch_problem(tab, count);
     const ProbDev P = probs[pi];
     b_drift(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi], first);
+}
+
+
+// ============================================================ anchor tables
+// After each update (BF16 mode with anchors): Qt[a][j] = ||c32_j - c32_a||^2,
+// FP64 direct form (the differences of FP32 values are exact in FP64) rounded
+// to nearest FP32, +inf for a padding column; and for each chunk-first column
+// j = f, Wa[a][f / 16] = (W, c W^2) with W = ||c32_f - c32_a|| (rounded up).
+// One workgroup per 64 x 64 block of slot pairs with block row <= block
+// column; the symmetric entries are the same sums in the same order.
+constexpr int AT_T = 64;
+__device__ __forceinline__ void b_atab(const ProbDev &P, int bi, int bj)
+{
+    __shared__ float ra[AT_T][AT_T + 1], rj[AT_T][AT_T + 1];
+    if (bi > bj) return;   // uniform per workgroup
+    const int t = threadIdx.x, ta = t / 16, tj = t % 16;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int c0 = 0; c0 < P.ldc; c0 += AT_T) {
+        __syncthreads();
+        for (int e = t; e < AT_T * AT_T; e += 256) {
+            const int r = e / AT_T, c = e % AT_T;
+            const int sa = bi * AT_T + r, sj = bj * AT_T + r, col = c0 + c;
+            ra[r][c] = (sa < P.kg && col < P.ldc) ? P.c32[(size_t)sa * P.ldc + col] : 0.f;
+            rj[r][c] = (sj < P.kg && col < P.ldc) ? P.c32[(size_t)sj * P.ldc + col] : 0.f;
+        }
+        __syncthreads();
+        const int cn = min(AT_T, P.ldc - c0);
+        for (int c = 0; c < cn; ++c) {
+            double xa[4], xj[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xa[i] = (double)ra[ta + 16 * i][c];
+                xj[i] = (double)rj[tj + 16 * i][c];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double df = xj[j] - xa[i];
+                    acc[i][j] = fma(df, df, acc[i][j]);
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int a = bi * AT_T + ta + 16 * i, c = bj * AT_T + tj + 16 * j;
+            if (a >= P.kg || c >= P.kg) continue;
+            const bool ra_ok = P.perm[a] >= 0, rc_ok = P.perm[c] >= 0;
+            const float q = (float)acc[i][j];
+            P.Qt[(size_t)a * P.kg + c] = rc_ok ? q : KP_INF;
+            P.Qt[(size_t)c * P.kg + a] = ra_ok ? q : KP_INF;
+            const float dist = d2f_up(sqrt(acc[i][j]) * (1.0 + 0x1p-40));
+            if (ra_ok && (c & (CHUNK - 1)) == 0) P.Wa[(size_t)a * P.nch + c / CHUNK] = mfma_eta3_w(dist);
+            if (rc_ok && (a & (CHUNK - 1)) == 0) P.Wa[(size_t)c * P.nch + a / CHUNK] = mfma_eta3_w(dist);
+        }
+}
+__global__ __launch_bounds__(256) void k_atab(ProbDev P) { b_atab(P, (int)blockIdx.y, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void kb_atab(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    const int T = (P.kg + AT_T - 1) / AT_T;
+    const int b = (int)blockIdx.x - tab[pi];
+    b_atab(P, b / T, b % T);
 }
 
 
@@ -829,97 +913,114 @@ __host__ __device__ __forceinline__ double eps2_tile(int ks)
     return (double)(8 * ks + 8) * 2.0 * 5.9604644775390625e-08;
 }
 
-// Per-point results of a chunk in key form: the estimate (clamped at 0, FP32
-// bits with the low 4 bits cleared, so at most 2^-19 relative below it) with
-// the slot's offset in the chunk in those 4 bits.  Unsigned order of keys is
-// the order of the truncated estimates, ties to the lower slot.  k1 <= k2 are
-// the two smallest keys.
-struct Key2 {
+// Per-point results of a chunk in key form.  Each row j of the chunk gives a
+// squared lower bound L_j = fl(v_j - e_j) and upper bound U_j = fl(v_j + e_j)
+// of ||x - c_j||^2 (see the bound of the estimates).  A key is L_j's FP32
+// bits with the low 4 bits cleared (so at most 2^-19 relative below L_j:
+// still a lower bound) and the row's offset in the chunk in those 4 bits;
+// unsigned order of keys is the order of the truncated bounds, ties to the
+// lower slot.  k1 <= k2 are the two smallest keys and u1 the upper bound of
+// k1's row.
+struct Key3 {
     unsigned k1, k2;
+    float u1;
 };
-__device__ __forceinline__ Key2 key2_merge(Key2 a, Key2 b)
+__device__ __forceinline__ Key3 key3_empty() { return Key3{0xFFFFFFFFu, 0xFFFFFFFFu, KP_INF}; }
+__device__ __forceinline__ Key3 key3_merge(Key3 a, Key3 b)
 {
-    Key2 r;
-    r.k1 = min(a.k1, b.k1);
-    r.k2 = min(max(a.k1, b.k1), min(a.k2, b.k2));
+    const bool ta = a.k1 < b.k1;
+    Key3 r;
+    r.k1 = ta ? a.k1 : b.k1;
+    r.u1 = ta ? a.u1 : b.u1;
+    r.k2 = min(ta ? b.k1 : a.k1, min(a.k2, b.k2));
     return r;
 }
-// Merge with the lane l ^ 16 (rows) or l ^ 32 (halves): with both operands
-// equal, v_permlane16_swap / v_permlane32_swap leave in every lane its own
-// value and its partner's, in an order that does not matter to the
-// symmetric merge.  All 64 lanes must be active.
-__device__ __forceinline__ Key2 key2_fold16(Key2 t)
+// v_permlane16_swap(X, Y) swaps the odd 16-lane rows of X with the even rows
+// of Y: afterwards X = [X0, Y0, X2, Y2] and Y = [X1, Y1, X3, Y3] by rows.
+// v_permlane32_swap(X, Y) swaps the upper half of X with the lower half of
+// Y: X = [X0, X1, Y0, Y1], Y = [X2, X3, Y2, Y3].  With X = Y every lane gets
+// its own value and its partner's (l ^ 16, l ^ 32); the symmetric merge
+// takes them in a fixed order, so both partners agree.  All 64 lanes must be
+// active.
+__device__ __forceinline__ Key3 key3_swap16(Key3 x, Key3 y, bool first)
 {
-    const auto a = __builtin_amdgcn_permlane16_swap(t.k1, t.k1, false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(t.k2, t.k2, false, false);
-    return key2_merge(Key2{a[0], b[0]}, Key2{a[1], b[1]});
+    const auto a = __builtin_amdgcn_permlane16_swap(x.k1, y.k1, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(x.k2, y.k2, false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(x.u1), __float_as_uint(y.u1), false, false);
+    return first ? Key3{a[0], b[0], __uint_as_float(c[0])} : Key3{a[1], b[1], __uint_as_float(c[1])};
 }
-__device__ __forceinline__ Key2 key2_fold32(Key2 t)
+__device__ __forceinline__ void key3_swap16_both(Key3 x, Key3 y, Key3 &nx, Key3 &ny)
 {
-    const auto a = __builtin_amdgcn_permlane32_swap(t.k1, t.k1, false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(t.k2, t.k2, false, false);
-    return key2_merge(Key2{a[0], b[0]}, Key2{a[1], b[1]});
+    const auto a = __builtin_amdgcn_permlane16_swap(x.k1, y.k1, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(x.k2, y.k2, false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(x.u1), __float_as_uint(y.u1), false, false);
+    nx = Key3{a[0], b[0], __uint_as_float(c[0])};
+    ny = Key3{a[1], b[1], __uint_as_float(c[1])};
+}
+__device__ __forceinline__ void key3_swap32_both(Key3 x, Key3 y, Key3 &nx, Key3 &ny)
+{
+    const auto a = __builtin_amdgcn_permlane32_swap(x.k1, y.k1, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(x.k2, y.k2, false, false);
+    const auto c = __builtin_amdgcn_permlane32_swap(__float_as_uint(x.u1), __float_as_uint(y.u1), false, false);
+    nx = Key3{a[0], b[0], __uint_as_float(c[0])};
+    ny = Key3{a[1], b[1], __uint_as_float(c[1])};
+}
+// The lane's partial (its four rows) merged over the four rows of lanes:
+// every lane of point p returns the chunk's result for p.
+__device__ __forceinline__ Key3 key3_fold_all(Key3 t)
+{
+    Key3 x, y;
+    key3_swap16_both(t, t, x, y);
+    t = key3_merge(x, y);
+    key3_swap32_both(t, t, x, y);
+    return key3_merge(x, y);
+}
+// Four chunks' partials p[0..3] of this lane's point reduced and spread:
+// the lane in row q returns chunk q's result for its point.  The first swap
+// leaves in even rows chunk 0 (2) merged over the row pair, in odd rows
+// chunk 1 (3); the second pairs rows 0/2 and 1/3.
+__device__ __forceinline__ Key3 key3_scatter4(const Key3 &p0, const Key3 &p1, const Key3 &p2, const Key3 &p3)
+{
+    Key3 a, b, c, d;
+    key3_swap16_both(p0, p1, a, b);
+    const Key3 q01 = key3_merge(a, b);
+    key3_swap16_both(p2, p3, c, d);
+    const Key3 q23 = key3_merge(c, d);
+    key3_swap32_both(q01, q23, a, b);
+    return key3_merge(a, b);
 }
 __device__ __forceinline__ float key_value(unsigned k) { return __uint_as_float(k & ~15u); }
 
-// Keys of the estimates v = ||x||^2 + ||c||^2 - 2 (hh + lo) of lane l's point
-// against slots 4 (l >> 4) .. +3 of the chunk (hh: leading products, lo: the
-// correction products), reduced over the four lane groups: every lane of
-// point p returns p's two smallest keys.
-// The estimates themselves, clamped at 0 (a squared distance is >= 0, so the
-// clamp only moves an estimate toward the true value).
-__device__ __forceinline__ void chunk_est(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp, float (&v)[4])
-{
-    const float cnv[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = fmaxf(fmaf(-2.f, hh[r] + lo[r], xnp + cnv[r]), 0.f);
-}
-__device__ __forceinline__ Key2 chunk_keys(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp)
-{
-    const unsigned base = 4u * (unsigned)(lane_id() >> 4);
-    float v[4];
-    chunk_est(hh, lo, c4, xnp, v);
-    unsigned k[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) k[r] = (__float_as_uint(v[r]) & ~15u) | (base + (unsigned)r);
-    Key2 p = {min(k[0], k[1]), max(k[0], k[1])}, q = {min(k[2], k[3]), max(k[2], k[3])};
-    Key2 t = key2_merge(p, q);
-    return key2_fold32(key2_fold16(t));
-}
-
-// Bounds on the true distance from an estimate v of its square with
-// |v - d^2| <= eta (eta_f: eta rounded up to FP32).  v_sqrt_f32 is within
-// 1 ulp of the square root (normal inputs); two steps cover it, and one step
-// each covers the rounding of v -/+ eta.  Tiny arguments give the bound 0.
+// Bounds on the true distance from bounds of its square: v_sqrt_f32 is
+// within 1 ulp of the square root (normal inputs); two steps cover it.  Tiny
+// arguments give the lower bound 0.
 __device__ __forceinline__ float sq_lo(float v, float eta_f) { return dn_nonneg(v - eta_f); }
 __device__ __forceinline__ float root_lo(float t)
 {
     return t > 0x1p-100f ? __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(t)) - 2u) : 0.f;
 }
-__device__ __forceinline__ float est_lo(float v, float eta_f) { return root_lo(sq_lo(v, eta_f)); }
-__device__ __forceinline__ float est_hi(float v, float eta_f)
+__device__ __forceinline__ float root_hi(float t)
 {
-    const float t = up_nonneg(v + eta_f);
     if (!(t < __builtin_huge_valf())) return t;
     return __uint_as_float(__float_as_uint(__builtin_amdgcn_sqrtf(fmaxf(t, 0x1p-100f))) + 2u);
 }
 
-// Running best of a point over BF16x3 chunk estimates, whose error bound
-// eta differs per chunk (it grows with the norms of the chunk's group).  The
-// best is chosen by estimate (bd at slot bs in group bg, with its chunk's
-// eta eb); every other estimate v enters as dn(v - eta), the square of its
-// lower bound before the root (sq_lo; root_lo is monotone, so minima carry
-// over): sec over all of them, bm2 over the best's group, ov (nearest other
-// group, for the L1 order only) over the other groups.
+// Running best of a point over chunk results: the best is the row with the
+// smallest squared lower bound bdl (slot bs in group bg, squared upper bound
+// bu); every other row enters by its squared lower bound (root_lo is
+// monotone, so minima carry over): sec over all of them, bm2 over the best's
+// group, ov (nearest other group, for the L1 order only) over the other
+// groups.
 struct RunB {
-    float bd, bdl, eb, sec, bm2, ov;
+    float bdl, bu, sec, bm2, ov;
     int bs, bg, og;
+    int wq;   // the row of lanes that folded the best (it stored the best group's bound)
 };
 __device__ __forceinline__ void runb_init(RunB &r)
 {
-    r.bd = KP_INF;
+    r.wq = 0;
     r.bdl = KP_INF;
-    r.eb = 0.f;
+    r.bu = KP_INF;
     r.sec = KP_INF;
     r.bm2 = KP_INF;
     r.ov = KP_INF;
@@ -927,16 +1028,15 @@ __device__ __forceinline__ void runb_init(RunB &r)
     r.bg = -1;
     r.og = -1;
 }
-// Fold one chunk of group g, when `on`: smallest estimate m1 at slot s1 with
-// squared lower bound l1, squared lower bound l2 of the chunk's second
-// estimate, the chunk's eta e, and gprev the squared lower bound of the
-// group's earlier chunks (+inf for its first).  A tie of estimates can never
-// be decided under the error bound, so ties keep the earlier result.
-__device__ __forceinline__ void runb_fold(RunB &r, bool on, float m1, float l1, int s1, float l2, float e, int g,
-                                          float gprev, bool track_og)
+// Fold one chunk of group g, when `on`: smallest lower bound l1 at slot s1
+// with upper bound u1, the second smallest l2, and gprev the smallest lower
+// bound of the group's earlier chunks (+inf for its first).  Equal bounds can
+// never be decided, so ties keep the earlier result.
+__device__ __forceinline__ void runb_fold(RunB &r, bool on, float l1, float u1, int s1, float l2, int g, float gprev,
+                                          bool track_og)
 {
-    const bool nb = on && m1 < r.bd;
-    // the old best (and everything below it) becomes an other estimate
+    const bool nb = on && l1 < r.bdl;
+    // the old best (and everything below it) becomes an other row
     const float sec = nb ? fminf(fminf(r.bdl, r.sec), l2) : fminf(r.sec, l1);
     const float bm2 = nb ? fminf(l2, gprev) : (g == r.bg ? fminf(r.bm2, l1) : r.bm2);
     if (track_og) {   // wave-uniform
@@ -950,34 +1050,92 @@ __device__ __forceinline__ void runb_fold(RunB &r, bool on, float m1, float l1, 
     }
     r.sec = on ? sec : r.sec;
     r.bm2 = on ? bm2 : r.bm2;
-    r.bd = nb ? m1 : r.bd;
     r.bdl = nb ? l1 : r.bdl;
-    r.eb = nb ? e : r.eb;
+    r.bu = nb ? u1 : r.bu;
     r.bs = nb ? s1 : r.bs;
     r.bg = nb ? g : r.bg;
+    r.wq = nb ? (lane_id() >> 4) : r.wq;
+}
+// Two running bests over disjoint sets of groups (the lanes of one point
+// that handled different chunks), merged; a and b are the states of the
+// lower and the upper lane of the pair, so both lanes compute the same.
+__device__ __forceinline__ RunB runb_merge(const RunB &a, const RunB &b)
+{
+    const bool tb = b.bdl < a.bdl;
+    const RunB &w = tb ? b : a, &l = tb ? a : b;
+    RunB r = w;
+    r.sec = fminf(fminf(w.sec, l.sec), l.bdl);
+    // nearest other group: the winner's, the loser's best group or its other
+    float ov = w.ov;
+    int og = w.og;
+    if (l.bg >= 0 && l.bdl < ov) {
+        ov = l.bdl;
+        og = l.bg;
+    }
+    if (l.og >= 0 && l.ov < ov) {
+        ov = l.ov;
+        og = l.og;
+    }
+    r.ov = ov;
+    r.og = og;
+    return r;
+}
+__device__ __forceinline__ RunB runb_swap(const RunB &x, bool half32, bool upper)
+{
+    auto sw = [&](unsigned v) {
+        const auto t = half32 ? __builtin_amdgcn_permlane32_swap(v, v, false, false)
+                              : __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return upper ? t[1] : t[0];
+    };
+    RunB r;
+    r.bdl = __uint_as_float(sw(__float_as_uint(x.bdl)));
+    r.bu = __uint_as_float(sw(__float_as_uint(x.bu)));
+    r.sec = __uint_as_float(sw(__float_as_uint(x.sec)));
+    r.bm2 = __uint_as_float(sw(__float_as_uint(x.bm2)));
+    r.ov = __uint_as_float(sw(__float_as_uint(x.ov)));
+    r.bs = (int)sw((unsigned)x.bs);
+    r.bg = (int)sw((unsigned)x.bg);
+    r.og = (int)sw((unsigned)x.og);
+    r.wq = (int)sw((unsigned)x.wq);
+    return r;
+}
+// The four lanes of a point (rows 0..3) hold running bests over disjoint
+// chunks; afterwards each holds the merge of all four.
+__device__ __forceinline__ RunB runb_allreduce(const RunB &r)
+{
+    const RunB e16 = runb_swap(r, false, false), o16 = runb_swap(r, false, true);   // rows (0|2) and (1|3)
+    const RunB m = runb_merge(e16, o16);
+    const RunB lo32 = runb_swap(m, true, false), hi32 = runb_swap(m, true, true);    // rows (0|1) and (2|3)
+    return runb_merge(lo32, hi32);
 }
 
-// BF16 decision under the error bound; writes the point's state and bound
-// fix-ups when the decision is certain, else reports it as uncertain with
-// U* (an upper bound on its true nearest distance).  The upper bound on the
-// best distance comes from its estimate with est_hi under its chunk's eta.
+// BF16 decision under the error bounds: certain iff the best row's upper
+// bound is below every other row's lower bound.  Every lane of the point
+// computes it.  When certain, the lane of row r.wq -- the one whose chunk
+// store wrote the best group's bound, so that the two stores keep their
+// order -- replaces that bound by the best group's second (bm2), and the
+// lane of row 0 writes the point's state; otherwise the point is reported
+// uncertain with U* (an upper bound on its true nearest distance).
 __device__ __forceinline__ void decide_bf16(const ProbDev &P, int pid, bool dense, int a, float minnc, const RunB &r,
                                             float sdd, bool &moved, bool &amb, int &win, float &umin)
 {
-    const float Ub = est_hi(r.bd, r.eb), Ls = root_lo(r.sec);
-    amb = !(Ub < Ls);   // certain iff the best is below every other estimate
+    const float Ub = root_hi(r.bu), Ls = root_lo(r.sec);
+    amb = !(Ub < Ls) || r.bs < 0;
     moved = false;
-    if (amb) {
-        umin = Ub;
-        return;
+    win = -1;
+    umin = Ub;
+    if (amb) return;
+    const int q = lane_id() >> 4;
+    if (q == r.wq) {
+        const float sv = store_lb(root_lo(r.bm2), P.Sgd[r.bg]);
+        if (P.lb16) P.lbh[(size_t)pid * P.gs + r.bg] = lb16_enc(sv, P.lbsc[1]);
+        else P.lb[(size_t)pid * P.gs + r.bg] = sv;
     }
+    if (q != 0) return;
     win = r.bs;
     PointState nsv;
     nsv.a = win;
     nsv.ga = pack_ga(P.slot_group[win], r.og);
-    const float sv = store_lb(root_lo(r.bm2), P.Sgd[r.bg]);
-    if (P.lb16) P.lbh[(size_t)pid * P.gs + r.bg] = lb16_enc(sv, P.lbsc[1]);
-    else P.lb[(size_t)pid * P.gs + r.bg] = sv;
     nsv.u = store_u(Ub, P.Scd[win]);
     nsv.p = store_lb(fminf(minnc, Ls), sdd);
     P.st[pid] = nsv;
@@ -1351,7 +1509,16 @@ __global__ __launch_bounds__(256) void kb_tile_f32(const ProbDev *__restrict__ p
 template <int KS>
 struct ChunkStage {
     bf16x8 a[2 * KS][WAVE];
-    float4 cn[4];
+    float4 cn[8];   // the rows' Q: ||c_j||^2, or ||c_j - r||^2 relative to an anchor r;
+                    // then (cn[4 + q], read as nr[q]) their N_j >= ||c~_j|| (0 for the first row, padding)
+    float2 wt;      // the chunk's (W, c W^2) for the bounds
+};
+// The anchor of a tile's estimates: slot a (-1: none, r = 0) and this
+// thread's coordinate t of c32_a (0 beyond the row), which it subtracts from
+// the chunk's first row when staging it.
+struct Anchor {
+    int a;
+    float rt;
 };
 // One visit of a tile: a group and the four waves' 16-bit point masks.
 struct Visit {
@@ -1364,20 +1531,24 @@ struct BlockLds {
     Visit vis[GMAX_BF16];           // the tile's visits (filtered iterations)
     int gst[GMAX_BF16], gsz[GMAX_BF16];
     float gsd[GMAX_BF16];           // Sg rounded down
-    float2 gcn[GMAX_BF16];          // (C, a C^2): C bounds the members' norms
+    float ar[32 * KS];              // the tile's anchor row (filtered iterations with anchors)
 };
 template <int KS>
 struct StageRegs {
     bf16x8 r[(2 * KS * WAVE + 255) / 256];
-    float4 c;
+    float4 c;  // threads 0..3: Q of rows 4t..4t+3; threads 4..7: N of rows 4(t-4)..
+    float2 wt;
+    float w;   // with an anchor: coordinate t of the chunk's first row, c32_f
 };
 
 // Loads of the chunk at slot0 into this thread's staging registers.  Every
 // thread issues the same loads whatever the sizes (entries past the chunk
 // repeat one inside it), so that the memory counters of the pipelined loop
-// below stay exact.
+// below stay exact.  With an anchor the rows' Q come from its row of the
+// table Qt and the chunk's first row is loaded in FP32 (one coordinate per
+// thread) to be staged relative to the anchor.
 template <int KS>
-__device__ __forceinline__ void stage_load(const ProbDev &P, int slot0, StageRegs<KS> &s)
+__device__ __forceinline__ void stage_load(const ProbDev &P, int slot0, StageRegs<KS> &s, const Anchor &anc)
 {
     const int t = threadIdx.x;
 #pragma unroll
@@ -1388,18 +1559,99 @@ __device__ __forceinline__ void stage_load(const ProbDev &P, int slot0, StageReg
         const int ks = f % KS;
         s.r[i] = *(const bf16x8 *)(base + (size_t)(slot0 + (l & 15)) * P.ldb + 32 * ks + 8 * (l >> 4));
     }
-    s.c = *(const float4 *)(P.cn + slot0 + 4 * (t & 3));
+    const int ch = slot0 / CHUNK;
+    const float *qrow = anc.a >= 0 ? P.Qt + (size_t)anc.a * P.kg : P.cn;
+    s.c = *(const float4 *)((t & 4) ? P.nrel + slot0 + 4 * (t & 3) : qrow + slot0 + 4 * (t & 3));
+    if (anc.a >= 0) {
+        s.wt = P.Wa[(size_t)anc.a * P.nch + ch];
+        s.w = P.c32[(size_t)slot0 * P.ldc + min(t, P.ldc - 1)];
+    } else {
+        s.wt = P.Wu[ch];
+        s.w = 0.f;
+    }
 }
 template <int KS>
-__device__ __forceinline__ void stage_store(ChunkStage<KS> &S, const StageRegs<KS> &s)
+__device__ __forceinline__ void stage_store(ChunkStage<KS> &S, const StageRegs<KS> &s, const Anchor &anc,
+                                            int ldc)
 {
     const int t = threadIdx.x;
+    // every fragment of a thread with t % 16 == 0 is a row-0 fragment (e = t
+    // + 256 i keeps e % 64 = t % 64): with an anchor those are restaged below
+    if (!(anc.a >= 0 && (t & 15) == 0)) {
 #pragma unroll
-    for (int i = 0; i < (2 * KS * WAVE + 255) / 256; ++i) {
-        const int e = t + 256 * i;
-        if ((2 * KS * WAVE) % 256 == 0 || e < 2 * KS * WAVE) S.a[e / WAVE][e % WAVE] = s.r[i];
+        for (int i = 0; i < (2 * KS * WAVE + 255) / 256; ++i) {
+            const int e = t + 256 * i;
+            if ((2 * KS * WAVE) % 256 == 0 || e < 2 * KS * WAVE) S.a[e / WAVE][e % WAVE] = s.r[i];
+        }
     }
-    if (t < 4) S.cn[t] = s.c;
+    if (anc.a >= 0 && t < 32 * KS) {
+        // coordinate t of w~ = fl(c32_f - r) into row 0: fragment ks = t / 32,
+        // lane 16 (t % 32 / 8), element t % 8, split as the other rows
+        const float w = (t < ldc ? s.w : 0.f) - anc.rt;
+        const __bf16 h = (__bf16)w;
+        const __bf16 l = (__bf16)(w - (float)h);
+        const int ks = t / 32, lane = 16 * ((t & 31) >> 3), el = t & 7;
+        S.a[ks][lane][el] = h;
+        S.a[KS + ks][lane][el] = l;
+    }
+    if (t < 8) S.cn[t] = s.c;   // cn[0..3], then nr[0..3] (adjacent)
+    if (t == 0) S.wt = s.wt;
+}
+
+// Row 0's product of this lane's point (lane p, element 0) in every lane of
+// the point: two swaps move it from row 0 to rows 2, then 1 and 3.
+__device__ __forceinline__ float row0_bcast(float x)
+{
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(a[0], a[0], false, false);
+    return __uint_as_float(b[0]);
+}
+// The estimates themselves, clamped at 0 (a squared distance is >= 0, so the
+// clamp only moves an estimate toward the true value).  Row 0 of the chunk
+// is its first slot f: its product is x~.w~; every other row j gives x~.c~_j,
+// to which x~.w~ is added (the rows are stored relative to row 0).
+__device__ __forceinline__ void chunk_est(const f32x4 &hh, const f32x4 &lo, float4 c4, float xnp, float (&v)[4])
+{
+    const float s0 = row0_bcast(hh[0] + lo[0]);
+    const bool q0 = lane_id() < 16;
+    const float cnv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float sj = hh[r] + lo[r];
+        const float S = (q0 && r == 0) ? sj : sj + s0;
+        v[r] = fmaxf(fmaf(-2.f, S, xnp + cnv[r]), 0.f);
+    }
+}
+// The bound e_j of each of this lane's rows from the point's (b A, a A^2),
+// the chunk's (W, c W^2) and the rows' N_j: e_j = E0 + N_j (h + c N_j).
+__device__ __forceinline__ void chunk_eta(float2 pt, float2 wt, float4 n4, float (&e)[4])
+{
+    const float E0 = fmaf(pt.x, wt.x, pt.y + wt.y);
+    const float h = fmaf(ETA3_C2, wt.x, pt.x);
+    e[0] = fmaf(n4.x, fmaf(ETA3_C, n4.x, h), E0);
+    e[1] = fmaf(n4.y, fmaf(ETA3_C, n4.y, h), E0);
+    e[2] = fmaf(n4.z, fmaf(ETA3_C, n4.z, h), E0);
+    e[3] = fmaf(n4.w, fmaf(ETA3_C, n4.w, h), E0);
+}
+// This lane's partial Key3 over its four rows (slots 4 (l >> 4) .. +3).
+__device__ __forceinline__ Key3 chunk_key3(const f32x4 &hh, const f32x4 &lo, float4 c4, float4 n4, float xnp, float2 pt,
+                                           float2 wt)
+{
+    const unsigned base = 4u * (unsigned)(lane_id() >> 4);
+    float v[4], e[4];
+    chunk_est(hh, lo, c4, xnp, v);
+    chunk_eta(pt, wt, n4, e);
+    unsigned k[4];
+    float u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float L = fmaxf(v[r] - e[r], 0.f);
+        u[r] = v[r] + e[r];
+        k[r] = (__float_as_uint(L) & ~15u) | (base + (unsigned)r);
+    }
+    const Key3 p = k[0] < k[1] ? Key3{k[0], k[1], u[0]} : Key3{k[1], k[0], u[1]};
+    const Key3 q = k[2] < k[3] ? Key3{k[2], k[3], u[2]} : Key3{k[3], k[2], u[3]};
+    return key3_merge(p, q);
 }
 
 // The two accumulators of a staged chunk against this wave's points: hh the
@@ -1419,11 +1671,12 @@ __device__ __forceinline__ void chunk_acc(const ChunkStage<KS> &S, const PtFrag<
     }
 }
 template <int KS>
-__device__ __forceinline__ Key2 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp)
+__device__ __forceinline__ Key3 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp, float2 pt)
 {
     f32x4 hh, lo;
     chunk_acc<KS>(S, b, hh, lo);
-    return chunk_keys(hh, lo, S.cn[lane_id() >> 4], xnp);
+    const int q = lane_id() >> 4;
+    return chunk_key3(hh, lo, S.cn[q], S.cn[4 + q], xnp, pt, S.wt);
 }
 
 // Chunks of a tile's visits 0 .. nv-1 (workgroup-uniform); src(k, g, m, s0,
@@ -1473,19 +1726,48 @@ __device__ __forceinline__ void seq_next_load(ChunkSeq &q, int nv, Src &src)
     }
 }
 
-// The workgroup's visits 0 .. nv-1 from src.  fold(g, m, slot0, nreal,
-// first, sgd, key2) receives each chunk's two smallest keys per point of this
-// wave; a wave with no point in the visit skips the chunk and calls skip()
-// instead, which issues the same memory operations.  Every thread of the
-// workgroup calls it.
+// The workgroup's visits 0 .. nv-1 from src.  Every thread of the workgroup
+// calls it.  Per chunk, each lane reduces its four rows of its point to a
+// Key3 partial (a wave with no point in the visit skips the products and
+// calls skip(), which issues the same memory operations).
+//   TRANS (every group is one chunk): the partials of four consecutive
+//   chunks are reduced and spread together (key3_scatter4), and
+//   fold4(p0..p3, m0..m3, n) is called with row q of lanes finishing chunk
+//   q of the n (<= 4) pending ones, m_q its description.
+//   Otherwise every chunk is reduced over the four rows (key3_fold_all) and
+//   fold1(g, m, slot0, first, sgd, key3) called with every lane holding the
+//   chunk's result for its point.
+// note(g, m, nreal, first) sees every chunk (wave-uniform counts).
 //
 // DEPTH chunks are in flight: chunk i is read from LDS while chunks
 // i+1 .. i+DEPTH-1 are loading into registers; after chunk i the loads of
 // chunk i+DEPTH are issued and chunk i+1 goes to LDS.  With DEPTH = 1 the
 // next chunk's loads are issued before the current chunk's work.
-template <int KS, int DEPTH, class Src, class Fold, class Skip>
+struct ChunkMeta {
+    int g, slot0;
+    unsigned m;
+    float sgd;
+};
+// Wave-uniform values read from LDS, moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uni(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+// The description of chunk q of four (field by field: a selection of whole
+// structures would take their addresses).
+__device__ __forceinline__ ChunkMeta meta_of(int q, ChunkMeta m0, ChunkMeta m1, ChunkMeta m2, ChunkMeta m3)
+{
+    ChunkMeta r;
+    r.g = q == 0 ? m0.g : (q == 1 ? m1.g : (q == 2 ? m2.g : m3.g));
+    r.slot0 = q == 0 ? m0.slot0 : (q == 1 ? m1.slot0 : (q == 2 ? m2.slot0 : m3.slot0));
+    r.m = q == 0 ? m0.m : (q == 1 ? m1.m : (q == 2 ? m2.m : m3.m));
+    r.sgd = q == 0 ? m0.sgd : (q == 1 ? m1.sgd : (q == 2 ? m2.sgd : m3.sgd));
+    return r;
+}
+template <int KS, int DEPTH, bool TRANS, class Src, class Note, class Fold1, class Fold4, class Skip>
 __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, int nv, Src src,
-                                             const PtFrag<KS> &b, float xnp, Fold fold, Skip skip)
+                                             const PtFrag<KS> &b, float xnp, float2 pt, const Anchor &anc,
+                                             Note note, Fold1 fold1, Fold4 fold4, Skip skip)
 {
     if (nv <= 0) return;
     ChunkSeq cp, ld;
@@ -1494,41 +1776,67 @@ __device__ __forceinline__ void block_visits(const ProbDev &P, BlockLds<KS> &L, 
     StageRegs<KS> R[DEPTH];
 #pragma unroll
     for (int k = 0; k < DEPTH; ++k) {
-        stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
+        stage_load<KS>(P, ld.s0 + ld.c0, R[k], anc);
         seq_next_load(ld, nv, src);
     }
-    stage_store<KS>(L.st[0], R[0]);
+    stage_store<KS>(L.st[0], R[0], anc, P.ldc);
     __syncthreads();
     int buf = 0;
-    auto work = [&]() {
+    // the pending chunks' partials and descriptions (named registers: the
+    // slot of a step is a constant of the unrolled loop)
+    Key3 p0 = key3_empty(), p1 = key3_empty(), p2 = key3_empty(), p3 = key3_empty();
+    ChunkMeta m0{0, 0, 0u, 0.f}, m1 = m0, m2 = m0, m3 = m0;
+    auto work = [&](int slot) {
         int g, s0, ns;
         unsigned m;
         float sgd;
         src(cp.k, g, m, s0, ns, sgd);
-        if (m) {
-            const Key2 t = chunk_lds<KS>(L.st[buf], b, xnp);
-            fold(g, m, cp.s0 + cp.c0, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0, sgd, t);
-        } else {
-            skip();
+        note(g, m, min(CHUNK, cp.ns - cp.c0), cp.c0 == 0);
+        Key3 t = key3_empty();
+        if (m) t = chunk_lds<KS>(L.st[buf], b, xnp, pt);
+        else if (!TRANS) skip();
+        if (TRANS) {
+            const ChunkMeta mt{g, cp.s0 + cp.c0, m, sgd};
+            if (slot == 0) {
+                p0 = t;
+                m0 = mt;
+            } else if (slot == 1) {
+                p1 = t;
+                m1 = mt;
+            } else if (slot == 2) {
+                p2 = t;
+                m2 = mt;
+            } else {
+                p3 = t;
+                m3 = mt;
+            }
+        } else if (m) {
+            fold1(g, m, cp.s0 + cp.c0, cp.c0 == 0, sgd, key3_fold_all(t));
         }
     };
+    constexpr int U = TRANS ? (DEPTH == 3 ? 12 : 4) : DEPTH;
     for (;;) {
 #pragma unroll
-        for (int k = 0; k < DEPTH; ++k) {
+        for (int i = 0; i < U; ++i) {
+            const int k = i % DEPTH, slot = i % 4;
             if (DEPTH == 1) {
-                stage_load<KS>(P, ld.s0 + ld.c0, R[0]);
+                stage_load<KS>(P, ld.s0 + ld.c0, R[0], anc);
                 seq_next_load(ld, nv, src);
-                work();
+                work(slot);
             } else {
-                work();
-                stage_load<KS>(P, ld.s0 + ld.c0, R[k]);
+                work(slot);
+                stage_load<KS>(P, ld.s0 + ld.c0, R[k], anc);
                 seq_next_load(ld, nv, src);
             }
-            stage_store<KS>(L.st[buf ^ 1], R[(k + 1) % DEPTH]);
+            stage_store<KS>(L.st[buf ^ 1], R[(k + 1) % DEPTH], anc, P.ldc);
             __syncthreads();
             seq_next(cp, nv, src);
             buf ^= 1;
-            if (!cp.valid) return;
+            if (TRANS && slot == 3) fold4(p0, p1, p2, p3, m0, m1, m2, m3, 4);
+            if (!cp.valid) {
+                if (TRANS && slot != 3) fold4(p0, p1, p2, p3, m0, m1, m2, m3, slot + 1);
+                return;
+            }
         }
     }
 }
@@ -1548,6 +1856,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     const float sdd = P.Sdud[1];
     const bool track_og = P.nk1 > P.kg;   // the L1 order uses the nearest other group
     const bool lb16 = P.lb16 != 0;        // bounds as FP16 codes
+    const bool anchored = !DENSE && P.anch != 0;   // estimates relative to the tile's anchor centroid
     const float linv = P.lbsc[1];
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
@@ -1556,7 +1865,6 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         L.gst[i] = P.gstart[i];
         L.gsz[i] = P.gsize[i];
         L.gsd[i] = P.Sgd[i];
-        L.gcn[i] = mfma_eta3_grp(ek, P.gcn[i]);
     }
     __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
@@ -1570,9 +1878,11 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     // A tile's inputs, fetched while the previous tile is finished: this
     // lane's point, old slot, norm, closed-group bound and FP32 coordinates,
     // and (filtered) the length of the tile's visit list and this thread's
-    // entry of it.
-    int f_pid = 0, f_a = -1, f_nv = 0;
-    float f_xn = 0.f, f_minnc = KP_INF;
+    // entry of it; with anchors, the tile's anchor slot (that of its first
+    // entry: the entries are sorted by slot) and this thread's coordinate of
+    // the anchor's row.
+    int f_pid = 0, f_a = -1, f_nv = 0, f_anc = -1;
+    float f_xn = 0.f, f_minnc = KP_INF, f_rt = 0.f;
     float f_v[KS][8];
     int4 f_ent = make_int4(0, 0, 0, 0);
     auto fetch = [&](long long tf) {
@@ -1589,12 +1899,16 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
                 f_a = clamp_slot(P, e.y);
             }
         }
-        f_xn = ok ? P.xn[f_pid] : 0.f;
+        f_xn = (ok && !anchored) ? P.xn[f_pid] : 0.f;
         f_minnc = (!DENSE && ok) ? P.minnc[ix] : KP_INF;
         load_rows16<KS>(P, f_pid, ok, f_v);
         if (!DENSE && tf < ntiles) {
             f_nv = P.tcnt[tf];
             if ((int)threadIdx.x < P.g) f_ent = P.tlist[(size_t)tf * P.g + threadIdx.x];
+            if (anchored) {
+                f_anc = clamp_slot(P, P.L1x[tf * 64].y);
+                f_rt = (int)threadIdx.x < P.ldc ? P.c32[(size_t)f_anc * P.ldc + threadIdx.x] : 0.f;
+            }
         }
     };
     if (bid_ < ntiles) fetch(bid_);
@@ -1602,54 +1916,82 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         const long long idx = tl * 64 + 16 * wv + pt;
         const bool in = idx < count;
         const int pid = f_pid, a = f_a;
-        const float xnp = f_xn, minnc = f_minnc;
-        const float2 eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
+        const float minnc = f_minnc;
+        const Anchor anc = {anchored ? f_anc : -1, anchored ? f_rt : 0.f};
         const unsigned inm = (unsigned)__ballot(in) & 0xFFFFu;   // this wave's points
         PtFrag<KS> b;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) split8(f_v[ks], b.h[ks], b.l[ks]);
+        float xnp = f_xn;
         RunB r;
         runb_init(r);
         float gmin = KP_INF;   // squared lower bound of the group being visited, so far
+        float2 eA;
         unsigned t_pairs = 0u, t_dist = 0u;   // this tile's counts (< 2^32)
-        auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
+        auto note = [&](int, unsigned m, int nreal, bool first) {
             const unsigned pm = (unsigned)__popc(m);
             t_pairs += first ? pm : 0u;
             t_dist += pm * (unsigned)nreal;
-            const bool mine = (m >> pt) & 1u;
-            const float2 gc = L.gcn[g];
-            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);   // the chunk's eta
-            const float m1 = key_value(kk.k1);
-            const float l1 = sq_lo(m1, e), l2 = sq_lo(key_value(kk.k2), e);
-            const float gprev = first ? KP_INF : gmin;
-            gmin = fminf(gprev, l1);
-            runb_fold(r, mine, m1, l1, slot0 + (int)(kk.k1 & 15u), l2, e, g, gprev, track_og);
-            const float lbv = dn_nonneg(root_lo(gmin) + sgd);   // offset form, rounded down
-            // one unconditional store per chunk: lanes without a bound to
-            // write send it to the workgroup's sink slot
+        };
+        // a visited group's bound of this lane's point, offset form, rounded
+        // down; lanes with nothing to write send the store to the sink slot
+        auto put_lb = [&](bool mine, int g, float l) {
+            const float lbv = dn_nonneg(root_lo(l) + L.gsd[g]);
             if (lb16) {
-                uint16_t *dst = (mine && quad == 0) ? P.lbh + (size_t)pid * P.gs + g : (uint16_t *)sink;
+                uint16_t *dst = mine ? P.lbh + (size_t)pid * P.gs + g : (uint16_t *)sink;
                 *dst = lb16_enc(lbv, linv);
             } else {
-                float *dst = (mine && quad == 0) ? P.lb + (size_t)pid * P.gs + g : sink;
+                float *dst = mine ? P.lb + (size_t)pid * P.gs + g : sink;
                 *dst = lbv;
             }
         };
+        // every lane holds the chunk's result for its point (groups of more
+        // than one chunk); one unconditional store per chunk
+        auto fold1 = [&](int g, unsigned m, int slot0, bool first, float, const Key3 &kk) {
+            const bool mine = (m >> pt) & 1u;
+            const float l1 = key_value(kk.k1), l2 = key_value(kk.k2);
+            const float gprev = first ? KP_INF : gmin;
+            gmin = fminf(gprev, l1);
+            runb_fold(r, mine, l1, kk.u1, slot0 + (int)(kk.k1 & 15u), l2, g, gprev, track_og);
+            r.wq = 0;   // every lane folds every chunk; the stores are row 0's
+            put_lb(mine && quad == 0, g, gmin);
+        };
+        // row q of lanes finishes chunk q of the n pending ones (every group
+        // is one chunk, so l1 is the group's bound); one store per lane
+        auto fold4 = [&](Key3 p0, Key3 p1, Key3 p2, Key3 p3, ChunkMeta m0, ChunkMeta m1, ChunkMeta m2, ChunkMeta m3,
+                         int n) {
+            const Key3 kk = key3_scatter4(p0, p1, p2, p3);
+            const ChunkMeta mq = meta_of(quad, m0, m1, m2, m3);
+            const bool mine = quad < n && ((mq.m >> pt) & 1u);
+            const float l1 = key_value(kk.k1), l2 = key_value(kk.k2);
+            runb_fold(r, mine, l1, kk.u1, mq.slot0 + (int)(kk.k1 & 15u), l2, mq.g, KP_INF, track_og);
+            put_lb(mine, mq.g, l1);
+        };
         auto skip = [&]() { *(uint16_t *)sink = 0; };
+        const bool trans = P.maxgs <= CHUNK;   // every group is one chunk
+        auto visits = [&](int nv, auto src) {
+            if (trans) {
+                block_visits<KS, DEPTH, true>(P, L, nv, src, b, xnp, eA, anc, note, fold1, fold4, skip);
+                r = runb_allreduce(r);
+            } else {
+                block_visits<KS, DEPTH, false>(P, L, nv, src, b, xnp, eA, anc, note, fold1, fold4, skip);
+            }
+        };
         if (DENSE) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) split8(f_v[ks], b.h[ks], b.l[ks]);
+            eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
             // every group, in order
             auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
                 g = k;
                 m = inm;
-                s0 = L.gst[k];
-                ns = L.gsz[k];
-                sgd = L.gsd[k];
+                s0 = uni(L.gst[k]);
+                ns = uni(L.gsz[k]);
+                sgd = uni(L.gsd[k]);
             };
             n_visits += wv == 0 ? (unsigned long long)P.g : 0ull;
-            block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
+            visits(P.g, src);
         } else {
             // the tile's visit list, written by the group filter (the first
-            // entries fetched with the tile's inputs)
+            // entries fetched with the tile's inputs), and the anchor's row
             const int nv = min(max(f_nv, 0), P.g);
             const int4 *tv = P.tlist + (size_t)tl * P.g;
             for (int k = threadIdx.x; k < nv; k += blockDim.x) {
@@ -1661,17 +2003,40 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
                 d.m[2] = (unsigned short)((unsigned)v.z & 0xFFFFu);
                 d.m[3] = (unsigned short)((unsigned)v.z >> 16);
             }
+            if (anchored && (int)threadIdx.x < 32 * KS) L.ar[threadIdx.x] = anc.rt;
             __syncthreads();
+            if (anchored) {
+                // x~ = fl(x - c_a) and its squared norm (FP64, rounded once)
+                double sq = 0.0;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const float4 r0 = *(const float4 *)&L.ar[32 * ks + 8 * quad];
+                    const float4 r1 = *(const float4 *)&L.ar[32 * ks + 8 * quad + 4];
+                    const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float xv = f_v[ks][j] - rr[j];
+                        f_v[ks][j] = xv;
+                        sq = fma((double)xv, (double)xv, sq);
+                    }
+                }
+                sq += __shfl_xor(sq, 16);
+                sq += __shfl_xor(sq, 32);
+                xnp = (float)sq;
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) split8(f_v[ks], b.h[ks], b.l[ks]);
+            eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
             auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
                 const Visit &v = L.vis[k];
-                g = v.g;
-                m = v.m[wv];
-                s0 = L.gst[g];
-                ns = L.gsz[g];
-                sgd = L.gsd[g];
+                g = uni(v.g);
+                m = uni((unsigned)v.m[wv]);
+                s0 = uni(L.gst[g]);
+                ns = uni(L.gsz[g]);
+                sgd = uni(L.gsd[g]);
             };
             n_visits += wv == 0 ? (unsigned long long)nv : 0ull;
-            block_visits<KS, DEPTH>(P, L, nv, src, b, xnp, fold, skip);
+            visits(nv, src);
         }
         n_pairs += t_pairs;
         n_dist += t_dist;
@@ -1680,9 +2045,10 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         bool moved = false, amb = false;
         int win = -1;
         const long long pos = DENSE ? (long long)pid : idx;
-        if (in && quad == 0) {
+        if (in) {
             float umin = KP_INF;
             decide_bf16(P, pid, DENSE, a, minnc, r, sdd, moved, amb, win, umin);
+            amb = amb && quad == 0;   // one entry per point
             // the recheck's inputs: the BF16 best slot and U*
             if (amb) P.ps4[pos] = make_float4(__int_as_float(r.bs), 0.f, umin, 0.f);
         }
@@ -1932,7 +2298,9 @@ __device__ __forceinline__ void b_recheck(const ProbDev &P, const int bid_, cons
                 for (int q = 0; q < BATCH; ++q) {
                     const float v = team_dist<NV>(x, c4[q]);
                     if (r + q < ns) {
-                        if (v < m1) {
+                        // slots need not ascend by original index (a chunk's
+                        // first slot is its medoid): exact ties go to the lower one
+                        if (before(P, v, s0 + r + q, m1, s1)) {
                             m2 = m1;
                             m1 = v;
                             s1 = s0 + r + q;
@@ -2545,7 +2913,6 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         L.gst[i] = P.gstart[i];
         L.gsz[i] = P.gsize[i];
         L.gsd[i] = 0.f;
-        L.gcn[i] = mfma_eta3_grp(ek, P.gcn[i]);
     }
     __syncthreads();
     ProbDev Pq = P;   // the query rows in place of the training points
@@ -2565,29 +2932,40 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         RunB r;
         runb_init(r);
         float gmin = KP_INF;
-        auto fold = [&](int g, unsigned m, int slot0, int nreal, bool first, float sgd, const Key2 &kk) {
-            const float2 gc = L.gcn[g];
-            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);
-            const float m1 = key_value(kk.k1);
-            const float l1 = sq_lo(m1, e), l2 = sq_lo(key_value(kk.k2), e);
+        auto note = [&](int, unsigned, int, bool) {};
+        auto fold1 = [&](int g, unsigned m, int slot0, bool first, float, const Key3 &kk) {
+            const float l1 = key_value(kk.k1), l2 = key_value(kk.k2);
             const float gprev = first ? KP_INF : gmin;
             gmin = fminf(gprev, l1);
-            runb_fold(r, true, m1, l1, slot0 + (int)(kk.k1 & 15u), l2, e, g, gprev, false);
+            runb_fold(r, (m >> pt) & 1u, l1, kk.u1, slot0 + (int)(kk.k1 & 15u), l2, g, gprev, false);
+        };
+        auto fold4 = [&](Key3 p0, Key3 p1, Key3 p2, Key3 p3, ChunkMeta m0, ChunkMeta m1, ChunkMeta m2, ChunkMeta m3,
+                         int n) {
+            const Key3 kk = key3_scatter4(p0, p1, p2, p3);
+            const ChunkMeta mq = meta_of(quad, m0, m1, m2, m3);
+            const bool mine = quad < n && ((mq.m >> pt) & 1u);
+            runb_fold(r, mine, key_value(kk.k1), kk.u1, mq.slot0 + (int)(kk.k1 & 15u), key_value(kk.k2), mq.g,
+                      KP_INF, false);
         };
         auto skip = [&]() {};
         auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
             g = k;
             m = inm;
-            s0 = L.gst[k];
-            ns = L.gsz[k];
-            sgd = L.gsd[k];
+            s0 = uni(L.gst[k]);
+            ns = uni(L.gsz[k]);
+            sgd = uni(L.gsd[k]);
         };
-        block_visits<KS, DEPTH>(P, L, P.g, src, b, xnp, fold, skip);
+        if (P.maxgs <= CHUNK) {
+            block_visits<KS, DEPTH, true>(P, L, P.g, src, b, xnp, eA, Anchor{-1, 0.f}, note, fold1, fold4, skip);
+            r = runb_allreduce(r);
+        } else {
+            block_visits<KS, DEPTH, false>(P, L, P.g, src, b, xnp, eA, Anchor{-1, 0.f}, note, fold1, fold4, skip);
+        }
         bool amb = false;
         if (in && quad == 0) {
-            // certain iff the best estimate's upper bound is below every
-            // other estimate's lower bound
-            const float Ub = est_hi(r.bd, r.eb), Ls = root_lo(r.sec);
+            // certain iff the best row's upper bound is below every other
+            // row's lower bound
+            const float Ub = root_hi(r.bu), Ls = root_lo(r.sec);
             if (Ub < Ls && r.bs >= 0) labels[q] = P.perm[clamp_slot(P, r.bs)];
             else amb = true;
         }
@@ -2657,15 +3035,23 @@ __global__ __launch_bounds__(256) void k_serve_fp32(ProbDev P, const float *__re
 // ============================================================ diagnostics
 // The estimates the distance kernels decide on, and their bounds, for query
 // rows against every centroid: the same point split, chunk staging, matrix
-// products, estimate and key truncation as the assignment, one chunk at a
-// time (no pipelining), every value written out instead of reduced.
+// products, estimate and per-row bound as the assignment, one chunk at a
+// time (no pipelining), every value written out instead of reduced (the
+// kernels form L = v - e and U = v + e from them).  With
+// an anchor slot (>= 0) every query is taken relative to that centroid, as
+// the filtered iterations take a tile's points relative to its anchor.
 template <int KS>
-__global__ __launch_bounds__(256) void k_probe(ProbDev P, const float *__restrict__ Q, long long nq,
+__global__ __launch_bounds__(256) void k_probe(ProbDev P, const float *__restrict__ Q, long long nq, int anchor,
                                                float *__restrict__ est, float *__restrict__ eta)
 {
     __shared__ ChunkStage<KS> S;
+    __shared__ float ar[32 * KS];
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const Eta3 ek = mfma_eta3_coef(P.ldb);
+    const int t = threadIdx.x;
+    const Anchor anc = {anchor, (anchor >= 0 && t < P.ldc) ? P.c32[(size_t)anchor * P.ldc + t] : 0.f};
+    if (t < 32 * KS) ar[t] = anc.rt;
+    __syncthreads();
     ProbDev Pq = P;
     Pq.X = Q;
     const long long ntiles = (nq + 63) / 64;
@@ -2674,32 +3060,46 @@ __global__ __launch_bounds__(256) void k_probe(ProbDev P, const float *__restric
         const bool in = q < nq;
         float v[KS][8];
         load_rows16<KS>(Pq, in ? (int)q : 0, in, v);
-        const float xnp = norm_rows16<KS>(v);
+        float xnp;
+        if (anchor >= 0) {
+            double sq = 0.0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    v[ks][j] -= ar[32 * ks + 8 * quad + j];
+                    sq = fma((double)v[ks][j], (double)v[ks][j], sq);
+                }
+            sq += __shfl_xor(sq, 16);
+            sq += __shfl_xor(sq, 32);
+            xnp = (float)sq;
+        } else {
+            xnp = norm_rows16<KS>(v);
+        }
         PtFrag<KS> b;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
         const float2 eA = mfma_eta3_pt(ek, mfma_eta3_a(xnp));
         for (int g = 0; g < P.g; ++g) {
             const int s0 = P.gstart[g], ns = P.gsize[g];
-            const float2 gc = mfma_eta3_grp(ek, P.gcn[g]);
-            const float e = fmaf(eA.x, gc.x, eA.y + gc.y);
             for (int c0 = 0; c0 < ns; c0 += CHUNK) {
                 StageRegs<KS> R;
-                stage_load<KS>(P, s0 + c0, R);
+                stage_load<KS>(P, s0 + c0, R, anc);
                 __syncthreads();   // the previous chunk's reads are done
-                stage_store<KS>(S, R);
+                stage_store<KS>(S, R, anc, P.ldc);
                 __syncthreads();
                 f32x4 hh, lo;
                 chunk_acc<KS>(S, b, hh, lo);
-                float ev[4];
+                float ev[4], ee[4];
                 chunk_est(hh, lo, S.cn[quad], xnp, ev);
+                chunk_eta(eA, S.wt, S.cn[4 + quad], ee);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int off = c0 + 4 * quad + r;   // slot offset in the group
                     const int orig = off < ns ? P.perm[s0 + off] : -1;
                     if (in && orig >= 0) {
-                        est[(size_t)q * P.k + orig] = key_value(__float_as_uint(ev[r]) & ~15u);
-                        eta[(size_t)q * P.k + orig] = e;
+                        est[(size_t)q * P.k + orig] = ev[r];
+                        eta[(size_t)q * P.k + orig] = ee[r];
                     }
                 }
             }
@@ -2770,11 +3170,19 @@ static void launch_recheck(const ProbDev &P, hipStream_t s, int blocks)
     else hipLaunchKernelGGL((k_recheck<8, LB16>), dim3(blocks), dim3(256), 0, s, P);
 }
 
+static void launch_atab(const ProbDev &P, hipStream_t s)
+{
+    if (!P.anch) return;
+    const int T = (P.kg + AT_T - 1) / AT_T;
+    hipLaunchKernelGGL(k_atab, dim3(T, T), dim3(256), 0, s, P);
+}
+
 hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
 {
     if (P.prec) hipLaunchKernelGGL(k_prep, dim3(cap_grid((P.n + 255) / 256, 4096)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(k_centroids<true>, dim3(cap_grid((P.kg + 3) / 4, 4096)), dim3(256), 0, s, P, init_dev);
     hipLaunchKernelGGL(k_drift, dim3(1), dim3(1024), 0, s, P, 1);
+    launch_atab(P, s);
     return hipGetLastError();
 }
 
@@ -2911,6 +3319,7 @@ static void launch_centroid_rows(const ProbDev &P, hipStream_t s)
     hipLaunchKernelGGL(k_centroids<false>, dim3(cap_grid((P.kg + 3) / 4, 4096)), dim3(256), 0, s, P,
                        (const float *)nullptr);
     hipLaunchKernelGGL(k_drift, dim3(1), dim3(1024), 0, s, P, 0);
+    launch_atab(P, s);
 }
 
 const char *stage_name(Stage st)
@@ -3045,6 +3454,10 @@ static int tab_blocks(int id, const ProbDev &P, const LaunchCfg &cfg, int cap)
     case TB_GF: return f32 ? 0 : cap_grid(((n + 15) / 16 + 3) / 4, cap);
     case TB_HIST: return cap_grid((2 * n + 255) / 256, cap);
     case TB_SCATTER: return cap_grid((2 * n + 4095) / 4096, 1024);
+    case TB_ATAB: {
+        const int T = (P.kg + AT_T - 1) / AT_T;
+        return P.anch ? T * T : 0;
+    }
     default: return 0;
     }
 }
@@ -3168,6 +3581,7 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
     case ST_CENTROIDS:
         KB_LAUNCH(TB_CENT, kb_centroids<false>, 256, (const float *)nullptr);
         KB_LAUNCH(TB_ONE, kb_drift, 1024, 0);
+        KB_LAUNCH(TB_ATAB, kb_atab, 256);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -3248,16 +3662,17 @@ hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, c
     return hipGetLastError();
 }
 
-hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, float *est, float *eta)
+hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, int anchor, float *est,
+                        float *eta)
 {
     const int grid = cap_grid((nq + 63) / 64, 4096);
     switch (P.ldb / 32) {
-    case 1: hipLaunchKernelGGL(k_probe<1>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
-    case 2: hipLaunchKernelGGL(k_probe<2>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
-    case 3: hipLaunchKernelGGL(k_probe<3>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
-    case 4: hipLaunchKernelGGL(k_probe<4>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
-    case 6: hipLaunchKernelGGL(k_probe<6>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
-    case 8: hipLaunchKernelGGL(k_probe<8>, dim3(grid), dim3(256), 0, s, P, Q, nq, est, eta); break;
+    case 1: hipLaunchKernelGGL(k_probe<1>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
+    case 2: hipLaunchKernelGGL(k_probe<2>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
+    case 3: hipLaunchKernelGGL(k_probe<3>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
+    case 4: hipLaunchKernelGGL(k_probe<4>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
+    case 6: hipLaunchKernelGGL(k_probe<6>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
+    case 8: hipLaunchKernelGGL(k_probe<8>, dim3(grid), dim3(256), 0, s, P, Q, nq, anchor, est, eta); break;
     default: return hipErrorInvalidValue;   // excluded when the plan is made
     }
     return hipGetLastError();

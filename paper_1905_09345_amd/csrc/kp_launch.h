@@ -33,7 +33,7 @@ hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const L
 // gives each problem a contiguous range of blocks; a problem outside the
 // class gets none.
 enum TabId {
-    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_GF, TB_HIST, TB_SCATTER,
+    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_GF, TB_HIST, TB_SCATTER, TB_ATAB,
     TB_DENSE_F32,                     // + DMAX class (5)
     TB_TILE_F32 = TB_DENSE_F32 + 5,   // + DMAX class (5)
     TB_BLK64 = TB_TILE_F32 + 5,       // + KS class (6)
@@ -76,7 +76,8 @@ hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, c
 
 // Diagnostics: BF16x3 estimates and bounds of query rows against every
 // centroid (est, eta: nq x k, original order); bounds of listed points.
-hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, float *est, float *eta);
+hipError_t launch_probe(const ProbDev &P, hipStream_t s, const float *Q, long long nq, int anchor, float *est,
+                        float *eta);
 hipError_t launch_bounds(const ProbDev &P, hipStream_t s, const int *idx, long long np, float *ub, float *lbp,
                          float *lb, int *groups);
 

@@ -94,7 +94,7 @@ def lib():
         L.kp_predict.restype = ctypes.c_int
         L.kp_predict_noalloc.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp]
         L.kp_predict_noalloc.restype = ctypes.c_int
-        L.kp_probe_estimates.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp]
+        L.kp_probe_estimates.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
         L.kp_probe_estimates.restype = ctypes.c_int
         L.kp_bounds.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp, vp]
         L.kp_bounds.restype = ctypes.c_int
@@ -194,9 +194,10 @@ def kp_predict_noalloc(ctx, problem, queries_ptr, nq, labels_ptr):
                                     ctypes.c_void_p(labels_ptr)), "kp_predict_noalloc")
 
 
-def kp_probe_estimates(ctx, problem, queries_ptr, nq, est_ptr, eta_ptr):
+def kp_probe_estimates(ctx, problem, queries_ptr, nq, anchor, est_ptr, eta_ptr):
     _check(lib().kp_probe_estimates(ctypes.c_void_p(ctx), int(problem), ctypes.c_void_p(queries_ptr), int(nq),
-                                    ctypes.c_void_p(est_ptr), ctypes.c_void_p(eta_ptr)), "kp_probe_estimates")
+                                    int(anchor), ctypes.c_void_p(est_ptr), ctypes.c_void_p(eta_ptr)),
+           "kp_probe_estimates")
 
 
 def kp_bounds(ctx, problem, idx_ptr, np_, ub_ptr, lbp_ptr, lb_ptr, group_ptr=None):
@@ -306,7 +307,7 @@ class KMeans:
         self._serve_keep = (q, scratch)
         return out
 
-    def probe_estimates(self, queries, problem=0):
+    def probe_estimates(self, queries, problem=0, anchor=-1):
         """(est, eta) of kp_probe_estimates: (n_q, k) FP32 tensors on the ctx's device."""
         p = self.problems[problem]
         q = queries.contiguous()
@@ -314,7 +315,7 @@ class KMeans:
             raise ValueError("queries must be an (n, %d) float32 tensor on %s" % (p.d, self.device))
         est = self._torch.empty((q.shape[0], p.k), dtype=self._torch.float32, device=self.device)
         eta = self._torch.empty_like(est)
-        kp_probe_estimates(self.ctx, problem, q.data_ptr(), q.shape[0], est.data_ptr(), eta.data_ptr())
+        kp_probe_estimates(self.ctx, problem, q.data_ptr(), q.shape[0], anchor, est.data_ptr(), eta.data_ptr())
         self._torch.cuda.current_stream(self.device).synchronize()
         return est, eta
 

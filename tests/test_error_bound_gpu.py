@@ -31,26 +31,34 @@ def _fp64_d2(Q, C):
     return d2, err
 
 
-def _probe_and_check(name, X, C, g, Q, chunk=8192):
+def _probe_and_check(name, X, C, g, Q, chunk=8192, anchors=("none", "near", "random")):
+    """Every query chunk is probed without an anchor (the dense first pass and
+    serving), relative to the centroid nearest its first query (a filtered
+    tile sorted to that centroid) and relative to a random centroid (a point
+    far from the anchor, as at a tile boundary)."""
     import torch
     from paper_1905_09345_amd import KMeans
     print("CASE", name, dict(n=X.shape[0], d=X.shape[1], k=C.shape[0], g=g, nq=Q.shape[0]), flush=True)
     km = KMeans([(torch.from_numpy(np.ascontiguousarray(X)).cuda(),
                   torch.from_numpy(np.ascontiguousarray(C)).cuda(), g, "bf16")])
+    rng = np.random.default_rng(len(name))
     try:
         worst, viol, ratio = 0.0, 0, []
         for s in range(0, Q.shape[0], chunk):
             q = np.ascontiguousarray(Q[s:s + chunk])
-            est, eta = km.probe_estimates(torch.from_numpy(q).cuda())
-            est, eta = est.cpu().numpy().astype(np.float64), eta.cpu().numpy().astype(np.float64)
             d2, err = _fp64_d2(q, C)
-            gap = np.abs(est - d2) - err
-            assert np.isfinite(est).all() and (eta > 0).all()
-            v = gap > eta
-            viol += int(v.sum())
-            worst = max(worst, float((gap / eta).max()))
-            ratio.append(np.median(np.abs(est - d2) / eta))
-            TOTAL["pairs"] += est.size
+            for mode in anchors:
+                anchor = -1 if mode == "none" else (int(np.argmin(d2[0])) if mode == "near"
+                                                    else int(rng.integers(C.shape[0])))
+                est, eta = km.probe_estimates(torch.from_numpy(q).cuda(), anchor=anchor)
+                est, eta = est.cpu().numpy().astype(np.float64), eta.cpu().numpy().astype(np.float64)
+                gap = np.abs(est - d2) - err
+                assert np.isfinite(est).all() and (eta > 0).all()
+                v = gap > eta
+                viol += int(v.sum())
+                worst = max(worst, float((gap / eta).max()))
+                ratio.append(np.median(np.abs(est - d2) / eta))
+                TOTAL["pairs"] += est.size
         print("  pairs so far %d, violations %d, largest |v - d2| / eta %.3f, median %.3g"
               % (TOTAL["pairs"], viol, worst, float(np.median(ratio))), flush=True)
         assert viol == 0, "%d pairs outside the bound (worst %.3f eta)" % (viol, worst)
@@ -60,13 +68,34 @@ def _probe_and_check(name, X, C, g, Q, chunk=8192):
 
 
 def test_mixture_c3_shape():
-    """1.0e8 pairs: the C3 recipe (D=128, K=1024, G=100) with 98,000 queries."""
+    """3.0e8 pairs: the C3 recipe (D=128, K=1024, G=100) with 98,000 queries,
+    each in the three forms."""
     P = datagen.make_config(3, n=100_000)
     _probe_and_check("c3-shape", P.X, P.C0, P.g, P.X[:98_000])
 
 
+def test_anchored_eta_is_tight_near_the_anchor():
+    """Relative to the nearest centroid the bound shrinks with the cell size:
+    on the C5 recipe it is far below the bound without an anchor."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    P = datagen.make_config(5, n=20_000)
+    km = KMeans([(torch.from_numpy(P.X).cuda(), torch.from_numpy(P.C0).cuda(), P.g, "bf16")])
+    try:
+        q = np.ascontiguousarray(P.X[:64])
+        d2, _ = _fp64_d2(q, P.C0)
+        a = int(np.argmin(d2[0]))
+        _, eta0 = km.probe_estimates(torch.from_numpy(q).cuda(), anchor=-1)
+        _, eta1 = km.probe_estimates(torch.from_numpy(q).cuda(), anchor=a)
+        e0, e1 = float(eta0[0].cpu().numpy()[a]), float(eta1[0].cpu().numpy()[a])
+        print("eta at the nearest centroid: %.4g without an anchor, %.4g relative to it" % (e0, e1), flush=True)
+        assert e1 < 0.2 * e0
+    finally:
+        km.close()
+
+
 def test_student_t_c5_shape():
-    """1.0e8 pairs at D=256 (eight 32-wide steps per product, the widest
+    """3.1e8 pairs at D=256 (eight 32-wide steps per product, the widest
     supported), K=4096, G=410, heavy-tailed points and centroids."""
     P = datagen.make_config(5, n=40_000)
     _probe_and_check("c5-shape", P.X, P.C0, P.g, P.X[:25_000])
