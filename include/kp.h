@@ -84,8 +84,14 @@ typedef struct {
 typedef struct {
     int32_t waves_per_block;       /* 1..4 waves of 64 lanes per workgroup */
     int32_t blocks_per_cu;         /* grid = 256 CUs * this (grid-stride loops) */
-    int32_t use_graph;             /* 1 (default): replay iterations from a
-                                      captured hipGraph; -1: plain launches */
+    int32_t use_graph;             /* 1 (default): replay each filtered
+                                      iteration from a captured hipGraph;
+                                      2: every iteration of a kp_iterate call
+                                      (the dense first one included) in one
+                                      graph, captured on the first call of
+                                      that iteration count and replayed by
+                                      later ones (requires timing = 0);
+                                      -1: plain launches */
     int32_t timing;                /* 1: record HIP events on the ctx's stream
                                       around every stage of timing_stages
                                       (also inside graph replays) and around

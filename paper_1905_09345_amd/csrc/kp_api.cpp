@@ -179,8 +179,12 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
             set_error("bound_codes=%d outside 0..2", t->bound_codes);
             return false;
         }
-        if (t->use_graph < -1 || t->use_graph > 1) {
-            set_error("use_graph=%d outside -1..1", t->use_graph);
+        if (t->use_graph < -1 || t->use_graph > 2) {
+            set_error("use_graph=%d outside -1..2", t->use_graph);
+            return false;
+        }
+        if (t->use_graph == 2 && t->timing) {
+            set_error("use_graph=2 (one graph per kp_iterate call) records no stage events; set timing=0");
             return false;
         }
         if (t->timing_stages < 0 || t->timing_stages >= (1 << kp::ST_COUNT)) {
@@ -356,6 +360,11 @@ struct kp_ctx {
     bool poisoned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // use_graph = 2: every iteration of a kp_iterate call in one graph, kept
+    // for the next call of the same shape (iteration count, dense first)
+    hipGraphExec_t rexec = nullptr;
+    int run_iters = 0;
+    bool run_dense = false;
     // timing inside the graph: event-record nodes around each stage, pointed
     // at fresh events before every replay
     std::vector<hipEvent_t> cap_events;        // placeholders recorded at capture
@@ -372,6 +381,7 @@ static void release_ctx(kp_ctx *ctx)
     ctx->timer.destroy();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->rexec) (void)hipGraphExecDestroy(ctx->rexec);
     for (hipEvent_t e : ctx->cap_events) (void)hipEventDestroy(e);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
@@ -457,7 +467,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         if (tuning->blocks_per_cu) ctx->cfg.grid_cap = 256 * tuning->blocks_per_cu;
         if (tuning->chunk_depth) ctx->cfg.depth = tuning->chunk_depth;
         ctx->cfg.lb16 = tuning->bound_codes == 2;
-        if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? 1 : 0;
+        if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? tuning->use_graph : 0;
         ctx->timing = tuning->timing;
         if (tuning->timing_stages) ctx->timed_stages = (unsigned)tuning->timing_stages;
     }
@@ -728,6 +738,33 @@ static hipError_t capture_iteration(kp_ctx *ctx)
     return capture_plain(ctx);
 }
 
+// use_graph = 2: the iterations of one call (the dense first one included
+// when the ctx has not iterated yet) captured as a single graph.  Every
+// iteration's work sizes live on the device (list lengths, counters), so
+// the same graph serves any later call of the same shape.
+static hipError_t capture_run(kp_ctx *ctx, bool dense_first, int iters)
+{
+    if (ctx->rexec) (void)hipGraphExecDestroy(ctx->rexec);
+    ctx->rexec = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->own, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int t = 0; t < iters && e == hipSuccess; ++t) {
+        const bool dense = dense_first && t == 0;
+        kp::Stage sts[kp::ST_COUNT];
+        const int n = iteration_calls(ctx, dense, sts);
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_call(ctx, sts[i], dense);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->own, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->rexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);   // the executable graph keeps what it needs
+    if (e != hipSuccess) return e;
+    ctx->run_iters = iters;
+    ctx->run_dense = dense_first;
+    return hipSuccess;
+}
+
 kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
 {
     kp_status st = check_ctx(ctx);
@@ -738,6 +775,16 @@ kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
     }
     KP_HIP(hipEventRecord(ctx->ev_in, ctx->user));
     KP_HIP(hipStreamWaitEvent(ctx->own, ctx->ev_in, 0));
+    if (ctx->use_graph == 2) {
+        const bool dense_first = ctx->iters == 0;
+        if (!ctx->rexec || ctx->run_iters != iters || ctx->run_dense != dense_first)
+            KP_HIP(capture_run(ctx, dense_first, iters));
+        KP_HIP(hipGraphLaunch(ctx->rexec, ctx->own));
+        ctx->iters += iters;
+        KP_HIP(hipEventRecord(ctx->ev_out, ctx->own));
+        KP_HIP(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+        return KP_OK;
+    }
     int todo = iters;
     if (ctx->iters == 0) {
         KP_HIP(launch_all(ctx, true));

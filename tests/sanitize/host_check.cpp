@@ -90,13 +90,21 @@ static void check_abi()
         int32_t kp_tuning::*f;
         int32_t v;
     } badt[] = {{&kp_tuning::waves_per_block, 5},  {&kp_tuning::waves_per_block, -1}, {&kp_tuning::blocks_per_cu, 65},
-                {&kp_tuning::chunk_depth, 2},      {&kp_tuning::bound_codes, 3},      {&kp_tuning::use_graph, 2},
+                {&kp_tuning::chunk_depth, 2},      {&kp_tuning::bound_codes, 3},      {&kp_tuning::use_graph, 3},
                 {&kp_tuning::timing, 2},           {&kp_tuning::timing_stages, -1},   {&kp_tuning::timing_stages, 1 << 9},
                 {&kp_tuning::deterministic, 2},    {&kp_tuning::deterministic, -1}};
     for (const Field &b : badt) {
         kp_tuning t;
         std::memset(&t, 0, sizeof t);
         t.*(b.f) = b.v;
+        CHECK(kp_workspace_bytes(&ok32, 1, &t) == 0);
+    }
+    {
+        kp_tuning t;
+        std::memset(&t, 0, sizeof t);
+        t.use_graph = 2;
+        CHECK(kp_workspace_bytes(&ok32, 1, &t) > 0);
+        t.timing = 1;   // one graph per call has no stage events
         CHECK(kp_workspace_bytes(&ok32, 1, &t) == 0);
     }
 

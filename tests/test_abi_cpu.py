@@ -74,6 +74,14 @@ def test_invalid_tuning_rejected(field, value):
 def test_valid_tuning_accepted():
     for depth in (0, 1, 3):
         assert kp.kp_workspace_bytes([_prob()], kp.kp_tuning(chunk_depth=depth)) > 0
+    for g in (-1, 1, 2):
+        assert kp.kp_workspace_bytes([_prob()], kp.kp_tuning(use_graph=g)) > 0
+
+
+def test_whole_call_graph_needs_timing_off():
+    # one graph per kp_iterate call has no stage events to time
+    assert kp.kp_workspace_bytes([_prob()], kp.kp_tuning(use_graph=2, timing=1)) == 0
+    assert "timing" in kp.kp_last_error()
 
 
 def test_fp16_bound_codes_shrink_bf16_workspace():

@@ -78,3 +78,33 @@ def test_autotune_then_run():
     best = KMeans.autotune(dev, iters=3)
     assert best.chunk_depth in (1, 3) and best.blocks_per_cu in (8, 16, 32) and best.use_graph == 1
     run_steplocked_batch(probs, 5, tuning=best)
+
+
+def test_batch_whole_call_graph():
+    """A batch iterated with use_graph = 2: the calls' iterations run as one
+    graph each (the last call replays the previous one's); the final step is
+    checked against the oracle."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning
+    from parity import check_assignment, check_centroids, rms_norm
+    specs = [(1, 3000, 16, 16, "bf16"), (2, 2500, 32, 64, "fp32"), (3, 4000, 64, 256, "bf16"),
+             (4, 1200, 8, 16, "fp32")]
+    probs = [_problem(*sp) for sp in specs]
+    print("CASE batch whole-call graph", len(probs), flush=True)
+    dev = [(torch.from_numpy(np.ascontiguousarray(X)).cuda(), torch.from_numpy(np.ascontiguousarray(C0)).cuda(),
+            g, prec, 0) for X, C0, g, prec in probs]
+    km = KMeans(dev, tuning=kp_tuning(use_graph=2))
+    try:
+        for c in (3, 4, 4):
+            km.iterate(c)
+        prev = [tuple(a.cpu().numpy() for a in km.centroids(i)) for i in range(len(probs))]
+        km.iterate(1)
+        assert km.iterations == 12
+        for i, (X, _, _, _) in enumerate(probs):
+            lab = km.assign(i).cpu().numpy()
+            c32, c64 = [a.cpu().numpy() for a in km.centroids(i)]
+            check_assignment(X, prev[i][0], lab)
+            check_centroids(X, lab, prev[i][1], c32, c64, rms_norm(X))
+    finally:
+        km.close()

@@ -73,3 +73,36 @@ def test_deterministic_zipf_segments():
     print("CASE deterministic-big-segments", flush=True)
     run_steplocked(X, C0, 3, "bf16", 6, tuning=kp_tuning(deterministic=1))
     run_steplocked(X, C0, 3, "fp32", 6, tuning=kp_tuning(deterministic=1))
+
+
+def _run_calls(X, C0, g, prec, calls, tuning):
+    import torch
+    from paper_1905_09345_amd import KMeans
+    km = KMeans([(torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda(), g, prec)], tuning=tuning)
+    try:
+        for c in calls:
+            km.iterate(c)
+        lab = km.assign().cpu().numpy()
+        c32, c64 = [a.cpu().numpy() for a in km.centroids()]
+        st = km.stats()
+    finally:
+        km.close()
+    return lab, c32, c64, st
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_whole_call_graph_bitwise(prec):
+    """use_graph = 2 (every iteration of a kp_iterate call in one graph,
+    replayed by a later call of the same length) gives bit for bit what
+    per-iteration graphs and plain launches give, in deterministic mode."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    P = datagen.make_config(3 if prec == "bf16" else 2, n=40_000)
+    print("CASE whole-call graph", prec, flush=True)
+    calls = [3, 4, 4, 1]   # the third call replays the second's graph
+    ref = _run_calls(P.X, P.C0, P.g, prec, calls, kp_tuning(deterministic=1, use_graph=-1))
+    for ug in (1, 2):
+        got = _run_calls(P.X, P.C0, P.g, prec, calls, kp_tuning(deterministic=1, use_graph=ug))
+        np.testing.assert_array_equal(got[0], ref[0])
+        assert got[1].tobytes() == ref[1].tobytes()
+        assert got[2].tobytes() == ref[2].tobytes()
+        assert got[3] == ref[3]

@@ -109,7 +109,7 @@ def test_ties_duplicates_and_empty_clusters(prec):
     assert r["c64"][6].tolist() == [100.0, 100.0, 100.0]
 
 
-@pytest.mark.parametrize("use_graph", [1, -1])
+@pytest.mark.parametrize("use_graph", [1, -1, 2])
 def test_graph_and_plain_launches(use_graph):
     from paper_1905_09345_amd.kp import kp_tuning
     P = datagen.make_config(1, n=4_097)
