@@ -223,8 +223,11 @@ size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq);
  * iteration (Section 1) applied to points outside the training set, with its
  * decision rule: labels_dev[i] receives the original index of the nearest
  * centroid, ties to the lowest index.  BF16 problems decide on the BF16x3
- * estimate under its error bound and recompute the uncertain points in FP32
- * direct form over every centroid; FP32 problems use the FP32 direct form.
+ * estimate under its error bound; with anchor tables (at most 16384 slots)
+ * the uncertain queries are sorted by their provisional nearest centroid
+ * and estimated again relative to it, and those still uncertain are
+ * recomputed in FP32 direct form over every centroid; FP32 problems use the
+ * FP32 direct form.
  * Before the first iteration the initial centroids are used.  Nothing of the
  * problem's state changes.  scratch_dev: caller-owned device memory of
  * kp_predict_scratch_bytes(), 256-byte aligned, overwritten.  Ordered on the
@@ -238,8 +241,9 @@ kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries_dev, int
  * kp_predict, but the scratch is a fixed array the library holds on each
  * device it runs on (until the process ends), so the call allocates nothing.
  * nq may be at most KP_PREDICT_NOALLOC_MAX_QUERIES (KP_ERR_INVALID above it;
- * the array is 16 MiB + 256 bytes).  Every call on one device shares that
- * device's array, whose counter each call clears before use: calls that
+ * the array is about 64 MiB: 16 bytes per query and a slot histogram).
+ * Every call on one device shares that device's array, whose counters and
+ * histogram each call clears before use: calls that
  * overlap on one device (other streams or threads) race and must not be
  * issued.  Same labels as kp_predict; same argument errors. */
 #define KP_PREDICT_NOALLOC_MAX_QUERIES 4194304

@@ -33,7 +33,7 @@ void set_error(const char *fmt, ...)
 }
 
 constexpr size_t ALIGN = 256;
-constexpr size_t ANCHOR_MAX_SLOTS = 16384;   // largest slot count with anchor tables (Qt <= 1 GiB)
+using kp::ANCHOR_MAX_SLOTS;
 inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of one problem's arrays inside the workspace.
@@ -919,7 +919,7 @@ size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq)
         set_error("NULL ctx, bad problem index %d or nq=%lld outside 0..2^31-1", problem, (long long)nq);
         return 0;
     }
-    return kp::SERVE_HEADER + ((size_t)nq * 4 + 255) / 256 * 256;
+    return kp::serve_scratch_bytes(nq, ctx->P[problem].anch != 0);
 }
 
 kp_status kp_predict(kp_ctx *ctx, int32_t problem, const float *queries, int64_t nq, int32_t *labels,

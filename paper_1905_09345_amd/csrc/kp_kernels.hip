@@ -2899,12 +2899,23 @@ __device__ __forceinline__ float norm_rows16(const float (&v)[KS][8])
     return (float)s;
 }
 
-__global__ void k_serve_begin(unsigned long long *ucnt) { *ucnt = 0ull; }
+__global__ void k_serve_begin(unsigned long long *ucnt) { ucnt[0] = ucnt[1] = 0ull; }
 
-template <int KS, int DEPTH>
+// Serving, BF16 passes.  Pass 1 (ANCH = false): every query against every
+// chunk with the plain estimate; a query whose decision is certain gets its
+// label, any other goes to the list unc with its provisional best slot
+// (ubest).  Pass 2 (ANCH = true; problems with anchor tables): the listed
+// queries, sorted by that slot (sorted, scnt entries), in tiles of 64 taken
+// relative to the slot of the tile's first entry -- the error bound then
+// scales with the distances to a nearby centroid instead of the norms, as in
+// the filtered iterations -- and the queries still uncertain go to unc for
+// the FP32 direct pass.
+template <int KS, int DEPTH, bool ANCH>
 __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restrict__ Q, long long nq,
-                                        int *__restrict__ labels, int *__restrict__ unc,
-                                        unsigned long long *__restrict__ ucnt, const int bid_, const int nblk_)
+                                        int *__restrict__ labels, const int2 *__restrict__ sorted,
+                                        const unsigned long long *__restrict__ scnt, int *__restrict__ unc,
+                                        int *__restrict__ ubest, unsigned long long *__restrict__ ucnt,
+                                        const int bid_, const int nblk_)
 {
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
@@ -2917,13 +2928,44 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
     __syncthreads();
     ProbDev Pq = P;   // the query rows in place of the training points
     Pq.X = Q;
-    const long long ntiles = (nq + 63) / 64;
+    const long long count = ANCH ? (long long)min(*scnt, (unsigned long long)nq) : nq;
+    const long long ntiles = (count + 63) / 64;
     for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
-        const long long q = tl * 64 + 16 * wv + pt;
-        const bool in = q < nq;
+        const long long e = tl * 64 + 16 * wv + pt;
+        const bool in = e < count;
+        long long q = e;
+        Anchor anc = {-1, 0.f};
+        if (ANCH) {
+            q = in ? (long long)min(max(sorted[e].x, 0), (int)(nq - 1)) : 0;
+            anc.a = clamp_slot(P, sorted[tl * 64].y);   // the tile's first entry is always listed
+            anc.rt = (int)threadIdx.x < P.ldc ? P.c32[(size_t)anc.a * P.ldc + threadIdx.x] : 0.f;
+            if ((int)threadIdx.x < 32 * KS) L.ar[threadIdx.x] = anc.rt;
+            __syncthreads();
+        }
         float v[KS][8];
         load_rows16<KS>(Pq, in ? (int)q : 0, in, v);
-        const float xnp = norm_rows16<KS>(v);
+        float xnp;
+        if (ANCH) {
+            // x~ = fl(x - c_a) and its squared norm (FP64, rounded once)
+            double sq = 0.0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const float4 r0 = *(const float4 *)&L.ar[32 * ks + 8 * quad];
+                const float4 r1 = *(const float4 *)&L.ar[32 * ks + 8 * quad + 4];
+                const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float xv = v[ks][j] - rr[j];
+                    v[ks][j] = xv;
+                    sq = fma((double)xv, (double)xv, sq);
+                }
+            }
+            sq += __shfl_xor(sq, 16);
+            sq += __shfl_xor(sq, 32);
+            xnp = (float)sq;
+        } else {
+            xnp = norm_rows16<KS>(v);
+        }
         PtFrag<KS> b;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) split8(v[ks], b.h[ks], b.l[ks]);
@@ -2956,10 +2998,10 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
             sgd = uni(L.gsd[k]);
         };
         if (P.maxgs <= CHUNK) {
-            block_visits<KS, DEPTH, true>(P, L, P.g, src, b, xnp, eA, Anchor{-1, 0.f}, note, fold1, fold4, skip);
+            block_visits<KS, DEPTH, true>(P, L, P.g, src, b, xnp, eA, anc, note, fold1, fold4, skip);
             r = runb_allreduce(r);
         } else {
-            block_visits<KS, DEPTH, false>(P, L, P.g, src, b, xnp, eA, Anchor{-1, 0.f}, note, fold1, fold4, skip);
+            block_visits<KS, DEPTH, false>(P, L, P.g, src, b, xnp, eA, anc, note, fold1, fold4, skip);
         }
         bool amb = false;
         if (in && quad == 0) {
@@ -2969,15 +3011,42 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
             if (Ub < Ls && r.bs >= 0) labels[q] = P.perm[clamp_slot(P, r.bs)];
             else amb = true;
         }
-        const long long e = wave_append(ucnt, amb);
-        if (e >= 0) unc[e] = (int)q;
+        const long long ea = wave_append(ucnt, amb);
+        if (ea >= 0) {
+            unc[ea] = (int)q;
+            if (!ANCH && ubest) ubest[ea] = r.bs;
+        }
     }
 }
-template <int KS, int DEPTH>
-__global__ __launch_bounds__(256) void k_serve(ProbDev P, const float *Q, long long nq, int *labels, int *unc,
-                                               unsigned long long *ucnt)
+template <int KS, int DEPTH, bool ANCH>
+__global__ __launch_bounds__(256) void k_serve(ProbDev P, const float *Q, long long nq, int *labels,
+                                               const int2 *sorted, const unsigned long long *scnt, int *unc,
+                                               int *ubest, unsigned long long *ucnt)
 {
-    b_serve<KS, DEPTH>(P, Q, nq, labels, unc, ucnt, (int)blockIdx.x, (int)gridDim.x);
+    b_serve<KS, DEPTH, ANCH>(P, Q, nq, labels, sorted, scnt, unc, ubest, ucnt, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Counting sort of pass 1's uncertain queries by provisional slot: the
+// histogram, then (after k_scan) every entry placed at its slot's cursor.
+__global__ __launch_bounds__(256) void k_sv_hist(ProbDev P, const int *__restrict__ ubest,
+                                                 const unsigned long long *__restrict__ ucnt, long long nq,
+                                                 int *__restrict__ hist)
+{
+    const long long cnt = (long long)min(*ucnt, (unsigned long long)nq);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x)
+        atomicAdd(&hist[clamp_slot(P, ubest[e])], 1);
+}
+__global__ __launch_bounds__(256) void k_sv_scatter(ProbDev P, const int *__restrict__ unc,
+                                                    const int *__restrict__ ubest,
+                                                    const unsigned long long *__restrict__ ucnt, long long nq,
+                                                    int *__restrict__ cursor, int2 *__restrict__ sorted)
+{
+    const long long cnt = (long long)min(*ucnt, (unsigned long long)nq);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x) {
+        const int sl = clamp_slot(P, ubest[e]);
+        const int pos = atomicAdd(&cursor[sl], 1);
+        sorted[min(max(pos, 0), (int)(cnt - 1))] = make_int2(unc[e], sl);
+    }
 }
 
 // FP32 direct form over every centroid, eight lanes per query (as the
@@ -3596,12 +3665,13 @@ hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out)
 }
 
 // ------------------------------------------------ serving without allocation
-// Scratch of kp_predict_noalloc: the uncertain-query counter (SERVE_HEADER
-// bytes) and the list of uncertain queries (4 bytes per query).  Each device
-// the library runs on holds its own copy until the process ends.  In host
+// Scratch of kp_predict_noalloc, laid out as serve_scratch_bytes describes
+// for NOALLOC_MAX_QUERIES queries with anchors (about 64 MiB: 16 bytes per
+// query and the slot histogram).  Each device the library runs on holds its
+// own copy until the process ends.  In host
 // code the array's name is not a device address: its address on a device is
 // taken once with hipGetSymbolAddress, with that device current, and kept.
-static __device__ __align__(256) unsigned char scratch[SERVE_HEADER + 4 * (size_t)NOALLOC_MAX_QUERIES];
+static __device__ __align__(256) unsigned char scratch[serve_scratch_bytes(NOALLOC_MAX_QUERIES, true)];
 constexpr int NOALLOC_MAX_DEVICES = 64;
 static std::mutex g_scratch_mu;
 static void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
@@ -3628,29 +3698,56 @@ void *noalloc_scratch(int device)
 hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, const float *Q, long long nq,
                         int *labels, void *scratch)
 {
-    auto *ucnt = (unsigned long long *)scratch;
-    int *unc = (int *)((char *)scratch + SERVE_HEADER);
+    // scratch layout: see serve_scratch_bytes
+    char *base = (char *)scratch;
+    auto *ucnt = (unsigned long long *)base;   // [0] pass 1, [1] pass 2
+    int *unc = (int *)(base + SERVE_HEADER);
+    int *ubest = (int *)((char *)unc + serve_up((size_t)nq * 4));
+    int2 *sorted = (int2 *)((char *)ubest + serve_up((size_t)nq * 4));
+    int *hist = (int *)((char *)sorted + serve_up((size_t)nq * 8));
+    int *cursor = hist + (ANCHOR_MAX_SLOTS + 1);
+    const bool two = P.prec && P.anch;   // anchored second pass
     const int nv = P.d <= 32 ? 1 : P.d <= 64 ? 2 : P.d <= 128 ? 4 : 8;
     const int grid2 = cap_grid((nq + 31) / 32, cfg.grid_cap);
     const unsigned long long *cnt_in = nullptr;
     const int *list = nullptr;
     if (P.prec) {
         hipLaunchKernelGGL(k_serve_begin, dim3(1), dim3(1), 0, s, ucnt);
+        if (two) hipLaunchKernelGGL(k_fill0, dim3(cap_grid((P.kg + 255) / 256, 64)), dim3(256), 0, s, hist, (long long)P.kg);
         const int grid = cap_grid((nq + 63) / 64, cfg.grid_cap);
-#define KP_SERVE(KS)                                                                                       \
-    if (cfg.depth == 1) hipLaunchKernelGGL((k_serve<KS, 1>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, unc, ucnt); \
-    else hipLaunchKernelGGL((k_serve<KS, 3>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, unc, ucnt)
-        switch (P.ldb / 32) {
-        case 1: KP_SERVE(1); break;
-        case 2: KP_SERVE(2); break;
-        case 3: KP_SERVE(3); break;
-        case 4: KP_SERVE(4); break;
-        case 6: KP_SERVE(6); break;
-        case 8: KP_SERVE(8); break;
-        default: break;   // excluded when the plan is made
-        }
-#undef KP_SERVE
+#define KP_SERVE(KS, ANCH, SRT, SCNT, UB, CNT)                                                                   \
+    if (cfg.depth == 1)                                                                                          \
+        hipLaunchKernelGGL((k_serve<KS, 1, ANCH>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, SRT, SCNT, unc, UB, \
+                           CNT);                                                                                 \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_serve<KS, 3, ANCH>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, SRT, SCNT, unc, UB, \
+                           CNT)
+#define KP_SERVE_KS(ANCH, SRT, SCNT, UB, CNT)          \
+    switch (P.ldb / 32) {                             \
+    case 1: KP_SERVE(1, ANCH, SRT, SCNT, UB, CNT); break; \
+    case 2: KP_SERVE(2, ANCH, SRT, SCNT, UB, CNT); break; \
+    case 3: KP_SERVE(3, ANCH, SRT, SCNT, UB, CNT); break; \
+    case 4: KP_SERVE(4, ANCH, SRT, SCNT, UB, CNT); break; \
+    case 6: KP_SERVE(6, ANCH, SRT, SCNT, UB, CNT); break; \
+    case 8: KP_SERVE(8, ANCH, SRT, SCNT, UB, CNT); break; \
+    default: break; /* excluded when the plan is made */ \
+    }
+        // pass 1: every query, plain estimate
+        KP_SERVE_KS(false, (const int2 *)nullptr, (const unsigned long long *)nullptr, two ? ubest : nullptr, ucnt);
         cnt_in = ucnt;
+        if (two) {
+            // the uncertain queries sorted by provisional slot, then pass 2
+            // relative to each tile's anchor; its uncertain queries replace
+            // the list (pass 1's entries are in `sorted` by then)
+            const int gs = cap_grid((nq + 255) / 256, cfg.grid_cap);
+            hipLaunchKernelGGL(k_sv_hist, dim3(gs), dim3(256), 0, s, P, ubest, ucnt, nq, hist);
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, P.kg);
+            hipLaunchKernelGGL(k_sv_scatter, dim3(gs), dim3(256), 0, s, P, unc, ubest, ucnt, nq, cursor, sorted);
+            KP_SERVE_KS(true, (const int2 *)sorted, (const unsigned long long *)ucnt, (int *)nullptr, ucnt + 1);
+            cnt_in = ucnt + 1;
+        }
+#undef KP_SERVE_KS
+#undef KP_SERVE
         list = unc;
     }
     switch (nv) {

@@ -61,8 +61,22 @@ hipError_t launch_labels(const ProbDev &P, hipStream_t s, int *out);
 // Current centroids in original order (either output may be null).
 hipError_t launch_centroids_out(const ProbDev &P, hipStream_t s, float *c32, double *c64);
 // Serving: labels of nq query rows against the problem's current centroids.
-// scratch: SERVE_HEADER bytes (uncertain-query counter) + 4 nq bytes (list).
+// Largest slot count that keeps anchor tables (the per-anchor squared
+// distances Qt: kg^2 FP32 <= 1 GiB), and with them the anchored estimates of
+// the filtered iterations and of serving's second pass.
+constexpr size_t ANCHOR_MAX_SLOTS = 16384;
+// scratch: a SERVE_HEADER-byte header (the two passes' uncertain-query
+// counters), the list of uncertain queries (4 nq bytes); with anchors also
+// their provisional slots (4 nq), the list sorted by that slot (8 nq) and a
+// slot histogram and its scan (2 x 4 (ANCHOR_MAX_SLOTS + 1)), each rounded up
+// to 256 bytes.
 constexpr size_t SERVE_HEADER = 256;
+constexpr size_t serve_up(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t serve_scratch_bytes(long long nq, bool anchored)
+{
+    return SERVE_HEADER + serve_up((size_t)nq * 4) +
+           (anchored ? serve_up((size_t)nq * 4) + serve_up((size_t)nq * 8) + serve_up(8 * (ANCHOR_MAX_SLOTS + 1)) : 0);
+}
 // Serving without allocation: the largest query count of kp_predict_noalloc,
 // whose scratch is a fixed per-device array inside the library.
 constexpr long long NOALLOC_MAX_QUERIES = 1ll << 22;

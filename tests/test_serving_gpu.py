@@ -136,3 +136,44 @@ def test_predict_argument_errors():
         check_assignment(X[:100], c32, lab.cpu().numpy())
     finally:
         km.close()
+
+
+def test_predict_c5_shape_two_passes():
+    """The C5 recipe (D = 256, Student-t mixture): many queries are uncertain
+    under the plain estimate, so the sorted, anchored second pass and the
+    FP32 pass both run.  Exact ties (queries equal to a centroid's midpoint
+    pair) and far outliers are mixed in."""
+    P = datagen.make_config(5, n=90_000)
+    k = P.C0.shape[0]
+    X, Q = P.X[:60_000], P.X[60_000:]   # queries from the same mixture
+    _case("predict-c5", nq=Q.shape[0], k=k, g=P.g)
+    km, _ = _train(X, P.C0, P.g, "bf16", 3)
+    try:
+        c32 = km.centroids()[0].cpu().numpy()
+        mid = 0.5 * (c32[:50].astype(np.float64) + c32[50:100].astype(np.float64))
+        far = c32[:7] * np.float32(40.0)
+        Qx = np.concatenate([Q, mid.astype(np.float32), far, c32[:13]]).astype(np.float32)
+        (mism, allowed), lab, _ = _predict_check(km, Qx)
+        assert mism == allowed
+        # a query equal to a centroid gets that centroid (or an equal one)
+        d = ((Qx[-13:, None, :].astype(np.float64) - c32[None].astype(np.float64)) ** 2).sum(2)
+        assert (d[np.arange(13), lab[-13:]] == d.min(1)).all()
+    finally:
+        km.close()
+
+
+def test_predict_without_anchor_tables():
+    """More than 16384 slots: no anchor tables, so serving keeps the plain
+    estimate and sends every uncertain query to the FP32 pass."""
+    rng = np.random.default_rng(5)
+    d, k, g = 16, 17_000, 1000
+    X = datagen.gaussian_mixture(rng, 20_000, d, 400)
+    C0 = X[rng.choice(X.shape[0], k, replace=False)].copy()
+    Q = datagen.gaussian_mixture(np.random.default_rng(6), 5_003, d, 400)
+    _case("predict-no-anchor", d=d, k=k, g=g, nq=Q.shape[0])
+    km, _ = _train(X, C0, g, "bf16", 2)
+    try:
+        (mism, allowed), _, _ = _predict_check(km, Q)
+        assert mism == allowed
+    finally:
+        km.close()
