@@ -1655,20 +1655,27 @@ __device__ __forceinline__ Key3 chunk_key3(const f32x4 &hh, const f32x4 &lo, flo
 }
 
 // The two accumulators of a staged chunk against this wave's points: hh the
-// leading products, lo the two correction products.
+// leading products, lo the two correction products (accumulated apart and
+// added once, so that no product waits on the one issued just before it;
+// every element still sums at most ldb + 1 terms, which the bound covers).
 template <int KS>
 __device__ __forceinline__ void chunk_acc(const ChunkStage<KS> &S, const PtFrag<KS> &b, f32x4 &hh, f32x4 &lo)
 {
     const int lane = lane_id();
     hh = f32x4{0.f, 0.f, 0.f, 0.f};
     lo = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 l2 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 ah = S.a[ks][lane], al = S.a[KS + ks][lane];
         hh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.h[ks], hh, 0, 0, 0);
         lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.h[ks], lo, 0, 0, 0);
-        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], lo, 0, 0, 0);
+        l2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.l[ks], l2, 0, 0, 0);
     }
+    lo[0] += l2[0];
+    lo[1] += l2[1];
+    lo[2] += l2[2];
+    lo[3] += l2[3];
 }
 template <int KS>
 __device__ __forceinline__ Key3 chunk_lds(const ChunkStage<KS> &S, const PtFrag<KS> &b, float xnp, float2 pt)
