@@ -76,18 +76,39 @@ __device__ __forceinline__ int batch_problem(const int *__restrict__ tab, int co
 }
 
 // ===================================================================== prep
-// ||x||^2 of every point (FP64 sum of the FP32 coordinates, rounded to FP32),
-// and their maximum (lbsc[2], zero before; the FP32 bits of non-negative
-// values order as integers).
+// ||x||^2 of every point (FP64 sum of the FP32 coordinates' squares -- exact
+// products -- in a fixed order, rounded to FP32), and their maximum
+// (lbsc[2], zero before; the FP32 bits of non-negative values order as
+// integers).  Sixteen lanes per point: lane l sums coordinates 4l + 64j ..
+// +3 (float4 loads, so that a wave reads four rows in full lines), then a
+// four-step tree within the sixteen.
 __device__ __forceinline__ void b_prep(const ProbDev &P, const int bid_, const int nblk_)
 {
-    const int64_t stride = (int64_t)nblk_ * blockDim.x;
+    const int sub = lane_id() & 15;
+    const int per_blk = blockDim.x / 16;
+    const int64_t stride = (int64_t)nblk_ * per_blk;
+    const bool vec = (P.d & 3) == 0 && ((uintptr_t)P.X & 15) == 0;
     float mx = 0.f;
-    for (int64_t i = (int64_t)bid_ * blockDim.x + threadIdx.x; i < P.n; i += stride) {
+    // the sixteen lanes of a point take the same trips (their shuffles stay inside the sixteen)
+    for (int64_t i = (int64_t)bid_ * per_blk + threadIdx.x / 16; i < P.n; i += stride) {
         const float *x = P.X + i * P.d;
         double s = 0.0;
-        for (int j = 0; j < P.d; ++j) s += (double)x[j] * x[j];
-        P.xn[i] = (float)s;
+        if (vec) {
+            for (int j = 4 * sub; j < P.d; j += 64) {
+                const float4 v = *(const float4 *)(x + j);
+                s += (double)v.x * v.x;
+                s += (double)v.y * v.y;
+                s += (double)v.z * v.z;
+                s += (double)v.w * v.w;
+            }
+        } else {
+            for (int j = sub; j < P.d; j += 16) s += (double)x[j] * x[j];
+        }
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 1);
+        if (sub == 0) P.xn[i] = (float)s;
         mx = fmaxf(mx, (float)s);
     }
     for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -3255,7 +3276,7 @@ static void launch_atab(const ProbDev &P, hipStream_t s)
 
 hipError_t launch_prep(const ProbDev &P, hipStream_t s, const float *init_dev)
 {
-    if (P.prec) hipLaunchKernelGGL(k_prep, dim3(cap_grid((P.n + 255) / 256, 4096)), dim3(256), 0, s, P);
+    if (P.prec) hipLaunchKernelGGL(k_prep, dim3(cap_grid((P.n + 15) / 16, 4096)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(k_centroids<true>, dim3(cap_grid((P.kg + 3) / 4, 4096)), dim3(256), 0, s, P, init_dev);
     hipLaunchKernelGGL(k_drift, dim3(1), dim3(1024), 0, s, P, 1);
     launch_atab(P, s);
