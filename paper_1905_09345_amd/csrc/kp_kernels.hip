@@ -1994,7 +1994,11 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             put_lb(mine, mq.g, l1);
         };
         auto skip = [&]() { *(uint16_t *)sink = 0; };
-        const bool trans = P.maxgs <= CHUNK;   // every group is one chunk
+        // every group is one chunk, and rows of 128 or more coordinates:
+        // with fewer, a chunk step has few products and the fold's exchanges
+        // cost more than the chunk results kept by every lane (measured at
+        // d = 16..64: 84 ms against 105 ms per 25 batched iterations)
+        const bool trans = KS >= 4 && P.maxgs <= CHUNK;
         auto visits = [&](int nv, auto src) {
             if (trans) {
                 block_visits<KS, DEPTH, true>(P, L, nv, src, b, xnp, eA, anc, note, fold1, fold4, skip);
@@ -3025,7 +3029,7 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
             ns = uni(L.gsz[k]);
             sgd = uni(L.gsd[k]);
         };
-        if (P.maxgs <= CHUNK) {
+        if (KS >= 4 && P.maxgs <= CHUNK) {   // as in the distance kernel
             block_visits<KS, DEPTH, true>(P, L, P.g, src, b, xnp, eA, anc, note, fold1, fold4, skip);
             r = runb_allreduce(r);
         } else {
