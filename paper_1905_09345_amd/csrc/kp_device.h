@@ -237,51 +237,20 @@ __device__ __forceinline__ float dist_lo(float d2, double eps2, double rho = 0.0
     const double r = (v > 0.0 ? sqrt(v) * (1.0 - 0x1p-46) : 0.0) - rho;
     return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
 }
-// BF16 MFMA estimate v = ||xb||^2 + ||cb||^2 - 2 xb.cb of ||xb - cb||^2:
-//   | v - ||xb - cb||^2 | <= eta,  | ||xb - cb|| - ||x - c|| | <= rho,
-// so the true distance lies in [sqrt(max(v - eta, 0)) - rho, sqrt(v + eta) + rho].
-__device__ __forceinline__ float mfma_hi(float v, double eta, double rho)
-{
-    if (!(v < __builtin_huge_valf())) return v;
-    const double t = (double)v + eta;
-    return d2f_up((sqrt(t > 0.0 ? t : 0.0) + rho) * (1.0 + 0x1p-46));
-}
-__device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
-{
-    if (!(v < __builtin_huge_valf())) return v;
-    const double t = (double)v - eta;
-    const double s = t > 0.0 ? sqrt(t) * (1.0 - 0x1p-46) : 0.0;
-    const double r = s - rho;
-    return r > 0.0 ? d2f_dn(r * (1.0 - 0x1p-46)) : 0.f;
-}
-// eta of a (point, centroid) pair for the BF16x3 estimate v = fl(fl(xn + cn) - 2 S) of
-// ||x - c||^2, where S = hh + lo, hh = xh.ch accumulated in FP32 on the
-// matrix cores (exact products) and lo = xl.ch + xh.cl in a second FP32
-// accumulator.
-// Rounding to nearest with 8-bit significands gives x = xh + xl + rx with
-// |xl_i| <= 2^-8 (1 + 2^-8) |x_i| and |rx_i| <= 2^-16 |x_i|; the same for c.
-// With u = 2^-24, A >= ||x||, C >= ||c||:
+// Error bound of the BF16x3 estimates (the distance calculator of Section 1
+// must return what standard K-means returns, Abstract).  Products: rounding to
+// nearest with 8-bit significands splits x = xh + xl + rx with
+// |xl_i| <= 2^-8 (1 + 2^-8) |x_i| and |rx_i| <= 2^-16 |x_i|, and a centroid
+// row c the same way.  With u = 2^-24, A >= ||x||, C >= ||c||:
 //   |xh.ch + xl.ch + xh.cl - x.c| <= |xl.cl| + |rx.c| + |xh.rc| + |xl.rc|
 //                                  <= 3.02 * 2^-16 A C
-//   hh sums ldb products, lo 2 ldb products of size <= 2^-8 (1.01) |x_i c_i|:
+// hh = xh.ch sums ldb exact products in FP32 on the matrix cores; xl.ch and
+// xh.cl (2 ldb products of size <= 2^-8 (1.01) |x_i c_i|) sum in two more
+// accumulators, added once:
 //   gamma_ldb (1.01) A C + gamma_2ldb 2^-7 (1.01) A C, doubled for the
 //   unspecified summation order inside the matrix cores: <= 2.1 (ldb + 2) u A C
-//   the add forming S (two are allowed for): <= 2.05 u A C
-// so |S - x.c| <= kappa A C.  xn and cn are FP64 norms rounded to FP32 (u each,
-// relative), xn + cn rounds once more, and the final fused multiply-add
-// rounds |xn + cn - 2S| <= 1.01 (A + C)^2 once:
-//   |v - ||x - c||^2| <= 3.02 u (A^2 + C^2) + (2 kappa + 2.02 u) A C.
-// The estimates are then compared with their low 4 significand bits
-// cleared (at most 2^-19 v <= 2^-19 * 1.01 (A + C)^2 less), which a third
-// term adds.  With it expanded,
-//   eta = a (A^2 + C^2) + b A C,  a = 3.02 u + 1.01 2^-19,
-//                                 b = 2 kappa + 2.02 u + 2.02 2^-19,
-// and the true distance lies in [sqrt(max(v - eta, 0)), sqrt(v + eta)].
-// A is per point, C per chunk of centroids: the bound on the norms of the
-// chunk's group.  eta is evaluated in FP32 with a and b scaled by
-// (1 + 2^-20) (1 + 2^-16), which covers the seven roundings of the evaluation
-// (each <= u relative, on sums and products of non-negative terms), and
-// rounded up.
+//   the adds forming S (two are allowed for): <= 2.05 u A C
+// so |S - x.c| <= kappa A C, kappa = 3.02 2^-16 + 2.1 (ldb + 2) u + 2.05 u.
 //
 // Estimates relative to an anchor.  The chunk rows are not c_j but
 // c~_j = fl(c_j - c_f), f the chunk's first slot (row f itself keeps c_f),
@@ -301,6 +270,9 @@ __device__ __forceinline__ float mfma_lo(float v, double eta, double rho)
 // (1.01 u (A + B_j)^2), so with
 //   a = 6.05 u,  b = 2 kappa + 10.1 u,  c = 4.04 u
 // and e_j = a A^2 + b A B_j + c B_j^2, both L <= ||x - c_j||^2 <= U hold.
+// The kernels order rows by L with its low 4 significand bits cleared (the
+// row's index rides there); clearing only lowers a non-negative L, so it
+// stays a lower bound.
 // Per row this is evaluated as e_j = E0 + N_j (h + c N_j) from the chunk's
 // E0 = a A^2 + b A W + c W^2 and h = b A + 2 c W (every term is
 // nonnegative; the coefficients' margin covers the rounding of these FP32
