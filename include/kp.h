@@ -223,11 +223,12 @@ size_t kp_predict_scratch_bytes(const kp_ctx *ctx, int32_t problem, int64_t nq);
  * iteration (Section 1) applied to points outside the training set, with its
  * decision rule: labels_dev[i] receives the original index of the nearest
  * centroid, ties to the lowest index.  BF16 problems decide on the BF16x3
- * estimate under its error bound; with anchor tables (at most 16384 slots)
- * the uncertain queries are sorted by their provisional nearest centroid
- * and estimated again relative to it, and those still uncertain are
- * recomputed in FP32 direct form over every centroid; FP32 problems use the
- * FP32 direct form.
+ * estimate under its error bound.  With anchor tables (at most 16384 slots)
+ * every query is first estimated relative to its nearest chunk medoid
+ * (queries sorted by it), the uncertain ones again relative to their
+ * provisional nearest centroid, and those still uncertain are recomputed in
+ * FP32 direct form over every centroid; without, one plain BF16 pass comes
+ * before the FP32 one.  FP32 problems use the FP32 direct form.
  * Before the first iteration the initial centroids are used.  Nothing of the
  * problem's state changes.  scratch_dev: caller-owned device memory of
  * kp_predict_scratch_bytes(), 256-byte aligned, overwritten.  Ordered on the

@@ -2931,17 +2931,88 @@ __device__ __forceinline__ float norm_rows16(const float (&v)[KS][8])
     return (float)s;
 }
 
-__global__ void k_serve_begin(unsigned long long *ucnt) { ucnt[0] = ucnt[1] = 0ull; }
+// ucnt[0], ucnt[1]: the two passes' uncertain-query counters; ucnt[2]: nq,
+// the length of the list of every query (the first anchored pass reads it).
+__global__ void k_serve_begin(unsigned long long *ucnt, long long nq)
+{
+    ucnt[0] = ucnt[1] = 0ull;
+    ucnt[2] = (unsigned long long)nq;
+}
 
-// Serving, BF16 passes.  Pass 1 (ANCH = false): every query against every
-// chunk with the plain estimate; a query whose decision is certain gets its
-// label, any other goes to the list unc with its provisional best slot
-// (ubest).  Pass 2 (ANCH = true; problems with anchor tables): the listed
-// queries, sorted by that slot (sorted, scnt entries), in tiles of 64 taken
-// relative to the slot of the tile's first entry -- the error bound then
-// scales with the distances to a nearby centroid instead of the norms, as in
-// the filtered iterations -- and the queries still uncertain go to unc for
-// the FP32 direct pass.
+// Serving's anchor of every query: the group whose chunk medoid (the first
+// slot of its first chunk) has the smallest single-product BF16 estimate
+// ||c_f||^2 - 2 xh.ch, written as that slot.  The choice only has to be
+// near; the anchored passes that follow bound their own errors.  Tiles of 64
+// queries (16 per wave); the medoid rows of 16 groups are staged in LDS per
+// step, rows past g repeating the last group with +inf as norm.
+template <int KS>
+__global__ __launch_bounds__(256) void k_serve_pre(ProbDev P, const float *__restrict__ Q, long long nq,
+                                                   int *__restrict__ anch)
+{
+    __shared__ bf16x8 A[KS][WAVE];
+    __shared__ float cnv[16];
+    const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
+    const int t = threadIdx.x;
+    ProbDev Pq = P;
+    Pq.X = Q;
+    const long long ntiles = (nq + 63) / 64;
+    for (long long tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {   // uniform per workgroup
+        const long long q = tl * 64 + 16 * wv + pt;
+        const bool in = q < nq;
+        float v[KS][8];
+        load_rows16<KS>(Pq, in ? (int)q : 0, in, v);
+        bf16x8 bh[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8 bl;
+            split8(v[ks], bh[ks], bl);
+        }
+        float best = KP_INF;
+        int bg = 0;
+        for (int g0 = 0; g0 < P.g; g0 += 16) {
+            __syncthreads();   // the previous step's reads of A are done
+            for (int e = t; e < KS * WAVE; e += blockDim.x) {
+                const int ks = e / WAVE, l = e % WAVE;
+                const int slot = P.gstart[min(g0 + (l & 15), P.g - 1)];
+                A[ks][l] = *(const bf16x8 *)(P.cb + (size_t)slot * P.ldb + 32 * ks + 8 * (l >> 4));
+            }
+            if (t < 16) cnv[t] = g0 + t < P.g ? P.cn[P.gstart[g0 + t]] : KP_INF;
+            __syncthreads();
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][lane], bh[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 4 * quad + r;
+                const float e = fmaf(-2.f, acc[r], cnv[row]);
+                if (e < best) {
+                    best = e;
+                    bg = g0 + row;
+                }
+            }
+        }
+        // the four lanes of a query hold disjoint rows
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ob = __shfl_xor(best, o);
+            const int og = __shfl_xor(bg, o);
+            if (ob < best || (ob == best && og < bg)) {
+                best = ob;
+                bg = og;
+            }
+        }
+        if (in && quad == 0) anch[q] = P.gstart[min(max(bg, 0), P.g - 1)];
+    }
+}
+
+// Serving, one BF16 pass over every chunk.  ANCH = false (problems without
+// anchor tables): every query with the plain estimate.  ANCH = true: the
+// queries of the list `sorted` (scnt entries, sorted by a slot), in tiles of
+// 64 taken relative to the slot of the tile's first entry -- the error bound
+// then scales with the distances to a nearby centroid instead of the norms,
+// as in the filtered iterations.  A query whose decision is certain gets its
+// label; any other goes to the list unc (ucnt entries), with its provisional
+// best slot in ubest when given.
 template <int KS, int DEPTH, bool ANCH>
 __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restrict__ Q, long long nq,
                                         int *__restrict__ labels, const int2 *__restrict__ sorted,
@@ -3046,7 +3117,7 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         const long long ea = wave_append(ucnt, amb);
         if (ea >= 0) {
             unc[ea] = (int)q;
-            if (!ANCH && ubest) ubest[ea] = r.bs;
+            if (ubest) ubest[ea] = r.bs;
         }
     }
 }
@@ -3058,26 +3129,52 @@ __global__ __launch_bounds__(256) void k_serve(ProbDev P, const float *Q, long l
     b_serve<KS, DEPTH, ANCH>(P, Q, nq, labels, sorted, scnt, unc, ubest, ucnt, (int)blockIdx.x, (int)gridDim.x);
 }
 
-// Counting sort of pass 1's uncertain queries by provisional slot: the
-// histogram, then (after k_scan) every entry placed at its slot's cursor.
-__global__ __launch_bounds__(256) void k_sv_hist(ProbDev P, const int *__restrict__ ubest,
-                                                 const unsigned long long *__restrict__ ucnt, long long nq,
-                                                 int *__restrict__ hist)
+// Counting sort of listed queries by slot: the histogram, then (after
+// k_scan) every entry placed at its slot's cursor.  Entry e is query unc[e]
+// with slot ubest[e], or (unc == nullptr) query e itself.  Each workgroup
+// takes a contiguous range of entries and counts it in LDS first (at most
+// ANCHOR_MAX_SLOTS slots), so that the global counters take one atomic per
+// (workgroup, slot) instead of one per entry: every query of the first
+// anchored pass falls on one of only g medoid slots.
+constexpr int SV_BLOCKS = 256;
+__global__ __launch_bounds__(1024) void k_sv_hist(ProbDev P, const int *__restrict__ ubest,
+                                                  const unsigned long long *__restrict__ ucnt, long long nq,
+                                                  int *__restrict__ hist)
 {
+    __shared__ int h[ANCHOR_MAX_SLOTS];
     const long long cnt = (long long)min(*ucnt, (unsigned long long)nq);
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x)
-        atomicAdd(&hist[clamp_slot(P, ubest[e])], 1);
+    const long long per = (cnt + gridDim.x - 1) / gridDim.x;
+    const long long e0 = (long long)blockIdx.x * per, e1 = min(cnt, e0 + per);
+    const int kg = min(P.kg, (int)ANCHOR_MAX_SLOTS);
+    for (int i = threadIdx.x; i < kg; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[min(clamp_slot(P, ubest[e]), kg - 1)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kg; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
 }
-__global__ __launch_bounds__(256) void k_sv_scatter(ProbDev P, const int *__restrict__ unc,
-                                                    const int *__restrict__ ubest,
-                                                    const unsigned long long *__restrict__ ucnt, long long nq,
-                                                    int *__restrict__ cursor, int2 *__restrict__ sorted)
+__global__ __launch_bounds__(1024) void k_sv_scatter(ProbDev P, const int *__restrict__ unc,
+                                                     const int *__restrict__ ubest,
+                                                     const unsigned long long *__restrict__ ucnt, long long nq,
+                                                     int *__restrict__ cursor, int2 *__restrict__ sorted)
 {
+    __shared__ int h[ANCHOR_MAX_SLOTS];   // the range's count per slot, then its next place
     const long long cnt = (long long)min(*ucnt, (unsigned long long)nq);
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x) {
-        const int sl = clamp_slot(P, ubest[e]);
-        const int pos = atomicAdd(&cursor[sl], 1);
-        sorted[min(max(pos, 0), (int)(cnt - 1))] = make_int2(unc[e], sl);
+    const long long per = (cnt + gridDim.x - 1) / gridDim.x;
+    const long long e0 = (long long)blockIdx.x * per, e1 = min(cnt, e0 + per);
+    const int kg = min(P.kg, (int)ANCHOR_MAX_SLOTS);
+    for (int i = threadIdx.x; i < kg; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[min(clamp_slot(P, ubest[e]), kg - 1)], 1);
+    __syncthreads();
+    // this range's places: one reservation per slot it holds
+    for (int i = threadIdx.x; i < kg; i += blockDim.x)
+        if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
+    __syncthreads();
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int sl = min(clamp_slot(P, ubest[e]), kg - 1);
+        const int pos = atomicAdd(&h[sl], 1);
+        sorted[min(max(pos, 0), (int)(cnt - 1))] = make_int2(unc ? unc[e] : (int)e, sl);
     }
 }
 
@@ -3130,6 +3227,65 @@ __global__ __launch_bounds__(256) void k_serve_fp32(ProbDev P, const float *__re
             }
         }
         if (live && t == 0) labels[q] = bo;
+    }
+}
+
+// The listed queries in FP32 direct form over every centroid, a whole wave
+// per query: its eight teams of eight lanes take interleaved runs of slots
+// and combine their minima at the end (the list is short, so a query's
+// latency, not the count, sets the time).  Lowest original index on exact
+// ties.
+template <int NV>
+__global__ __launch_bounds__(256) void k_serve_fp32_list(ProbDev P, const float *__restrict__ Q, long long nq,
+                                                         const int *__restrict__ unc,
+                                                         const unsigned long long *__restrict__ ucnt,
+                                                         int *__restrict__ labels)
+{
+    const int lane = lane_id();
+    const int t = lane & (RT - 1), tw = lane / RT;   // lane in its team, team in the wave
+    const long long cnt = (long long)min(*ucnt, (unsigned long long)nq);
+    const long long nwaves = (long long)gridDim.x * (blockDim.x / WAVE);
+    const long long wid = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (long long e = wid; e < cnt; e += nwaves) {   // uniform per wave
+        const long long q = (long long)min(max(unc[e], 0), (int)(nq - 1));
+        float4 x[NV];
+        const float *xrow = Q + (size_t)q * P.d;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int i = 4 * t + 32 * j;
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = i + u < P.d ? xrow[i + u] : 0.f;
+            x[j] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        float bd = KP_INF;
+        int bo = 0x7FFFFFFF;
+        constexpr int BATCH = NV <= 4 ? 4 : 2;   // rows in flight per team
+        for (int s0 = tw * BATCH; s0 < P.kg; s0 += (WAVE / RT) * BATCH) {
+            float4 c4[BATCH][NV];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u)
+                team_load<NV>(c4[u], P.c32 + (size_t)min(s0 + u, P.kg - 1) * P.ldc, P.ldc, t);
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const float dv = team_dist<NV>(x, c4[u]);
+                const int o = s0 + u < P.kg ? P.perm[s0 + u] : -1;   // -1: padding slot
+                if (o >= 0 && (dv < bd || (dv == bd && o < bo))) {
+                    bd = dv;
+                    bo = o;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = RT; o < WAVE; o <<= 1) {
+            const float ob = __shfl_xor(bd, o);
+            const int oo = __shfl_xor(bo, o);
+            if (ob < bd || (ob == bd && oo < bo)) {
+                bd = ob;
+                bo = oo;
+            }
+        }
+        if (lane == 0) labels[q] = bo;
     }
 }
 
@@ -3732,28 +3888,22 @@ hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, c
 {
     // scratch layout: see serve_scratch_bytes
     char *base = (char *)scratch;
-    auto *ucnt = (unsigned long long *)base;   // [0] pass 1, [1] pass 2
+    auto *ucnt = (unsigned long long *)base;   // uncertain after the first and second pass; nq
     int *unc = (int *)(base + SERVE_HEADER);
     int *ubest = (int *)((char *)unc + serve_up((size_t)nq * 4));
     int2 *sorted = (int2 *)((char *)ubest + serve_up((size_t)nq * 4));
     int *hist = (int *)((char *)sorted + serve_up((size_t)nq * 8));
     int *cursor = hist + (ANCHOR_MAX_SLOTS + 1);
-    const bool two = P.prec && P.anch;   // anchored second pass
+    const bool two = P.prec && P.anch;   // anchored passes
     const int nv = P.d <= 32 ? 1 : P.d <= 64 ? 2 : P.d <= 128 ? 4 : 8;
     const int grid2 = cap_grid((nq + 31) / 32, cfg.grid_cap);
     const unsigned long long *cnt_in = nullptr;
     const int *list = nullptr;
     if (P.prec) {
-        hipLaunchKernelGGL(k_serve_begin, dim3(1), dim3(1), 0, s, ucnt);
-        if (two) hipLaunchKernelGGL(k_fill0, dim3(cap_grid((P.kg + 255) / 256, 64)), dim3(256), 0, s, hist, (long long)P.kg);
+        hipLaunchKernelGGL(k_serve_begin, dim3(1), dim3(1), 0, s, ucnt, nq);
         const int grid = cap_grid((nq + 63) / 64, cfg.grid_cap);
-#define KP_SERVE(KS, ANCH, SRT, SCNT, UB, CNT)                                                                   \
-    if (cfg.depth == 1)                                                                                          \
-        hipLaunchKernelGGL((k_serve<KS, 1, ANCH>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, SRT, SCNT, unc, UB, \
-                           CNT);                                                                                 \
-    else                                                                                                         \
-        hipLaunchKernelGGL((k_serve<KS, 3, ANCH>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, SRT, SCNT, unc, UB, \
-                           CNT)
+#define KP_SERVE(KS, ANCH, SRT, SCNT, UB, CNT)                                                                  \
+    hipLaunchKernelGGL((k_serve<KS, 1, ANCH>), dim3(grid), dim3(256), 0, s, P, Q, nq, labels, SRT, SCNT, unc, UB, CNT)
 #define KP_SERVE_KS(ANCH, SRT, SCNT, UB, CNT)          \
     switch (P.ldb / 32) {                             \
     case 1: KP_SERVE(1, ANCH, SRT, SCNT, UB, CNT); break; \
@@ -3764,23 +3914,51 @@ hipError_t launch_serve(const ProbDev &P, hipStream_t s, const LaunchCfg &cfg, c
     case 8: KP_SERVE(8, ANCH, SRT, SCNT, UB, CNT); break; \
     default: break; /* excluded when the plan is made */ \
     }
-        // pass 1: every query, plain estimate
-        KP_SERVE_KS(false, (const int2 *)nullptr, (const unsigned long long *)nullptr, two ? ubest : nullptr, ucnt);
-        cnt_in = ucnt;
         if (two) {
-            // the uncertain queries sorted by provisional slot, then pass 2
-            // relative to each tile's anchor; its uncertain queries replace
-            // the list (pass 1's entries are in `sorted` by then)
-            const int gs = cap_grid((nq + 255) / 256, cfg.grid_cap);
-            hipLaunchKernelGGL(k_sv_hist, dim3(gs), dim3(256), 0, s, P, ubest, ucnt, nq, hist);
+            // every query anchored at its nearest chunk medoid, sorted by it
+            hipLaunchKernelGGL(k_fill0, dim3(cap_grid((P.kg + 255) / 256, 64)), dim3(256), 0, s, hist, (long long)P.kg);
+            switch (P.ldb / 32) {
+            case 1: hipLaunchKernelGGL(k_serve_pre<1>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            case 2: hipLaunchKernelGGL(k_serve_pre<2>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            case 3: hipLaunchKernelGGL(k_serve_pre<3>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            case 4: hipLaunchKernelGGL(k_serve_pre<4>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            case 6: hipLaunchKernelGGL(k_serve_pre<6>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            case 8: hipLaunchKernelGGL(k_serve_pre<8>, dim3(grid), dim3(256), 0, s, P, Q, nq, ubest); break;
+            default: break;
+            }
+            hipLaunchKernelGGL(k_sv_hist, dim3(SV_BLOCKS), dim3(1024), 0, s, P, ubest, ucnt + 2, nq, hist);
             hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, P.kg);
-            hipLaunchKernelGGL(k_sv_scatter, dim3(gs), dim3(256), 0, s, P, unc, ubest, ucnt, nq, cursor, sorted);
+            hipLaunchKernelGGL(k_sv_scatter, dim3(SV_BLOCKS), dim3(1024), 0, s, P, (const int *)nullptr, ubest,
+                               ucnt + 2, nq, cursor, sorted);
+            // pass A: every query relative to its anchor; the uncertain ones
+            // with their provisional best slot (overwriting the anchors,
+            // whose entries are in `sorted` by then)
+            KP_SERVE_KS(true, (const int2 *)sorted, (const unsigned long long *)(ucnt + 2), ubest, ucnt);
+            // pass B: those, sorted by that slot, relative to it
+            hipLaunchKernelGGL(k_fill0, dim3(cap_grid((P.kg + 255) / 256, 64)), dim3(256), 0, s, hist, (long long)P.kg);
+            hipLaunchKernelGGL(k_sv_hist, dim3(SV_BLOCKS), dim3(1024), 0, s, P, ubest, ucnt, nq, hist);
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, cursor, P.kg);
+            hipLaunchKernelGGL(k_sv_scatter, dim3(SV_BLOCKS), dim3(1024), 0, s, P, unc, ubest, ucnt, nq, cursor, sorted);
             KP_SERVE_KS(true, (const int2 *)sorted, (const unsigned long long *)ucnt, (int *)nullptr, ucnt + 1);
             cnt_in = ucnt + 1;
+        } else {
+            // no anchor tables: one pass with the plain estimate
+            KP_SERVE_KS(false, (const int2 *)nullptr, (const unsigned long long *)nullptr, (int *)nullptr, ucnt);
+            cnt_in = ucnt;
         }
 #undef KP_SERVE_KS
 #undef KP_SERVE
         list = unc;
+    }
+    if (list) {   // the queries the BF16 passes left: a wave each
+        const int gw = cap_grid((nq + 3) / 4, cfg.grid_cap);
+        switch (nv) {
+        case 1: hipLaunchKernelGGL(k_serve_fp32_list<1>, dim3(gw), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+        case 2: hipLaunchKernelGGL(k_serve_fp32_list<2>, dim3(gw), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+        case 4: hipLaunchKernelGGL(k_serve_fp32_list<4>, dim3(gw), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+        default: hipLaunchKernelGGL(k_serve_fp32_list<8>, dim3(gw), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;
+        }
+        return hipGetLastError();
     }
     switch (nv) {
     case 1: hipLaunchKernelGGL(k_serve_fp32<1>, dim3(grid2), dim3(256), 0, s, P, Q, nq, list, cnt_in, labels); break;

@@ -65,9 +65,9 @@ hipError_t launch_centroids_out(const ProbDev &P, hipStream_t s, float *c32, dou
 // distances Qt: kg^2 FP32 <= 1 GiB), and with them the anchored estimates of
 // the filtered iterations and of serving's second pass.
 constexpr size_t ANCHOR_MAX_SLOTS = 16384;
-// scratch: a SERVE_HEADER-byte header (the two passes' uncertain-query
-// counters), the list of uncertain queries (4 nq bytes); with anchors also
-// their provisional slots (4 nq), the list sorted by that slot (8 nq) and a
+// scratch: a SERVE_HEADER-byte header (the BF16 passes' uncertain-query
+// counters and nq), the list of uncertain queries (4 nq bytes); with anchors
+// also the anchors or provisional slots (4 nq), the list sorted by slot (8 nq) and a
 // slot histogram and its scan (2 x 4 (ANCHOR_MAX_SLOTS + 1)), each rounded up
 // to 256 bytes.
 constexpr size_t SERVE_HEADER = 256;
