@@ -1541,17 +1541,24 @@ struct Anchor {
     int a;
     float rt;
 };
-// One visit of a tile: a group and the four waves' 16-bit point masks.
+// One visit of a tile: a group, its first slot, size and rounded-down drift
+// sum (copied from the group tables when the list is loaded, so that a
+// chunk step reads its description in one LDS access), and the four waves'
+// 16-bit point masks.
 struct Visit {
-    int g;
+    int g, s0, ns;
+    float sgd;
     unsigned short m[4];
 };
 template <int KS>
 struct BlockLds {
     ChunkStage<KS> st[2];
-    Visit vis[GMAX_BF16];           // the tile's visits (filtered iterations)
-    int gst[GMAX_BF16], gsz[GMAX_BF16];
-    float gsd[GMAX_BF16];           // Sg rounded down
+    Visit vis[GMAX_BF16];           // the tile's visits (filtered), or every group in order (dense, serving)
+    // wide rows (two workgroups per CU, so LDS is not the limit): the group
+    // tables kept in LDS too, for the visit list's lookups of each tile
+    static constexpr int GT = KS >= 6 ? GMAX_BF16 : 1;
+    int gst[GT], gsz[GT];
+    float gsd[GT];
     float ar[32 * KS];              // the tile's anchor row (filtered iterations with anchors)
 };
 template <int KS>
@@ -1889,12 +1896,23 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
     float *sink = P.sink + 16 * (bid_ % SINK_SLOTS);
     const long long count = DENSE ? P.n : list_len(P, CTR_L1);
     const long long ntiles = (count + 63) / 64;
-    for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
-        L.gst[i] = P.gstart[i];
-        L.gsz[i] = P.gsize[i];
-        L.gsd[i] = P.Sgd[i];
+    if (DENSE) {
+        for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
+            Visit &d = L.vis[i];
+            d.g = i;
+            d.s0 = P.gstart[i];
+            d.ns = P.gsize[i];
+            d.sgd = P.Sgd[i];
+        }
+        __syncthreads();
+    } else if (KS >= 6) {
+        for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
+            L.gst[i] = P.gstart[i];
+            L.gsz[i] = P.gsize[i];
+            L.gsd[i] = P.Sgd[i];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     unsigned long long n_dist = 0, n_pairs = 0, n_visits = 0, n_moved = 0;
     // sorted entry of this lane's position in the tile after the one being
     // fetched, loaded one tile ahead
@@ -1961,8 +1979,8 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         };
         // a visited group's bound of this lane's point, offset form, rounded
         // down; lanes with nothing to write send the store to the sink slot
-        auto put_lb = [&](bool mine, int g, float l) {
-            const float lbv = dn_nonneg(root_lo(l) + L.gsd[g]);
+        auto put_lb = [&](bool mine, int g, float l, float sgd) {
+            const float lbv = dn_nonneg(root_lo(l) + sgd);
             if (lb16) {
                 uint16_t *dst = mine ? P.lbh + (size_t)pid * P.gs + g : (uint16_t *)sink;
                 *dst = lb16_enc(lbv, linv);
@@ -1973,14 +1991,14 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
         };
         // every lane holds the chunk's result for its point (groups of more
         // than one chunk); one unconditional store per chunk
-        auto fold1 = [&](int g, unsigned m, int slot0, bool first, float, const Key3 &kk) {
+        auto fold1 = [&](int g, unsigned m, int slot0, bool first, float sgd, const Key3 &kk) {
             const bool mine = (m >> pt) & 1u;
             const float l1 = key_value(kk.k1), l2 = key_value(kk.k2);
             const float gprev = first ? KP_INF : gmin;
             gmin = fminf(gprev, l1);
             runb_fold(r, mine, l1, kk.u1, slot0 + (int)(kk.k1 & 15u), l2, g, gprev, track_og);
             r.wq = 0;   // every lane folds every chunk; the stores are row 0's
-            put_lb(mine && quad == 0, g, gmin);
+            put_lb(mine && quad == 0, g, gmin, sgd);
         };
         // row q of lanes finishes chunk q of the n pending ones (every group
         // is one chunk, so l1 is the group's bound); one store per lane
@@ -1991,7 +2009,7 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             const bool mine = quad < n && ((mq.m >> pt) & 1u);
             const float l1 = key_value(kk.k1), l2 = key_value(kk.k2);
             runb_fold(r, mine, l1, kk.u1, mq.slot0 + (int)(kk.k1 & 15u), l2, mq.g, KP_INF, track_og);
-            put_lb(mine, mq.g, l1);
+            put_lb(mine, mq.g, l1, mq.sgd);
         };
         auto skip = [&]() { *(uint16_t *)sink = 0; };
         // every group is one chunk, and rows of 128 or more coordinates:
@@ -2015,9 +2033,9 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
             auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
                 g = k;
                 m = inm;
-                s0 = uni(L.gst[k]);
-                ns = uni(L.gsz[k]);
-                sgd = uni(L.gsd[k]);
+                s0 = uni(L.vis[k].s0);
+                ns = uni(L.vis[k].ns);
+                sgd = uni(L.vis[k].sgd);
             };
             n_visits += wv == 0 ? (unsigned long long)P.g : 0ull;
             visits(P.g, src);
@@ -2030,6 +2048,15 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
                 const int4 v = k == (int)threadIdx.x ? f_ent : tv[k];
                 Visit &d = L.vis[k];
                 d.g = min(max(v.x, 0), P.g - 1);
+                if constexpr (KS >= 6) {
+                    d.s0 = L.gst[d.g];
+                    d.ns = L.gsz[d.g];
+                    d.sgd = L.gsd[d.g];
+                } else {
+                    d.s0 = P.gstart[d.g];
+                    d.ns = P.gsize[d.g];
+                    d.sgd = P.Sgd[d.g];
+                }
                 d.m[0] = (unsigned short)((unsigned)v.y & 0xFFFFu);
                 d.m[1] = (unsigned short)((unsigned)v.y >> 16);
                 d.m[2] = (unsigned short)((unsigned)v.z & 0xFFFFu);
@@ -2063,9 +2090,9 @@ __device__ __forceinline__ void b_blk64(const ProbDev &P, const int bid_, const 
                 const Visit &v = L.vis[k];
                 g = uni(v.g);
                 m = uni((unsigned)v.m[wv]);
-                s0 = uni(L.gst[g]);
-                ns = uni(L.gsz[g]);
-                sgd = uni(L.gsd[g]);
+                s0 = uni(v.s0);
+                ns = uni(v.ns);
+                sgd = uni(v.sgd);
             };
             n_visits += wv == 0 ? (unsigned long long)nv : 0ull;
             visits(nv, src);
@@ -3023,10 +3050,12 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
     __shared__ BlockLds<KS> L;
     const int lane = lane_id(), pt = lane & 15, quad = lane >> 4, wv = threadIdx.x / WAVE;
     const Eta3 ek = mfma_eta3_coef(P.ldb);
-    for (int i = threadIdx.x; i < P.g; i += blockDim.x) {
-        L.gst[i] = P.gstart[i];
-        L.gsz[i] = P.gsize[i];
-        L.gsd[i] = 0.f;
+    for (int i = threadIdx.x; i < P.g; i += blockDim.x) {   // every group, in order
+        Visit &d = L.vis[i];
+        d.g = i;
+        d.s0 = P.gstart[i];
+        d.ns = P.gsize[i];
+        d.sgd = 0.f;
     }
     __syncthreads();
     ProbDev Pq = P;   // the query rows in place of the training points
@@ -3096,9 +3125,9 @@ __device__ __forceinline__ void b_serve(const ProbDev &P, const float *__restric
         auto src = [&](int k, int &g, unsigned &m, int &s0, int &ns, float &sgd) {
             g = k;
             m = inm;
-            s0 = uni(L.gst[k]);
-            ns = uni(L.gsz[k]);
-            sgd = uni(L.gsd[k]);
+            s0 = uni(L.vis[k].s0);
+            ns = uni(L.vis[k].ns);
+            sgd = uni(L.vis[k].sgd);
         };
         if (KS >= 4 && P.maxgs <= CHUNK) {   // as in the distance kernel
             block_visits<KS, DEPTH, true>(P, L, P.g, src, b, xnp, eA, anc, note, fold1, fold4, skip);
