@@ -61,3 +61,33 @@ def test_traffic_only_for_matching_source_and_tuning(tmp_path, monkeypatch):
     (tmp_path / "paper_1905_09345_amd" / "csrc" / "kp_kernels.hip").write_text("changed")
     assert bench.traffic_of("k", "W") is None   # the source has changed since
     bench.TUNING.clear()
+
+
+def test_batched_plain_lloyd_matches_per_problem_lloyd(monkeypatch):
+    """The batched torch comparator (problems of one (D, K) class padded and
+    stacked) computes the same Lloyd iterations as each problem alone:
+    padding rows take no part, and the labels and sums are per problem."""
+    import numpy as np
+    import torch
+    import bench
+    import datagen
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setattr(torch.cuda, "empty_cache", lambda *a, **k: None)
+    rng = np.random.default_rng(0)
+    Xs, Cs = [], []
+    for n, d, k in [(500, 16, 16), (300, 16, 16), (700, 32, 64), (200, 8, 16), (90, 8, 16)]:
+        X = datagen.gaussian_mixture(rng, n, d, k).astype(np.float32)
+        Xs.append(torch.from_numpy(X))
+        Cs.append(torch.from_numpy(X[:k].copy()))
+    out = []
+    bench.plain_fp32_lloyd_batched(torch, Xs, Cs, iters=2, warmup=1, rows=128, centroids_out=out)
+
+    def lloyd(X, C, T):
+        for _ in range(T):
+            lab = ((X[:, None, :].double() - C[None].double()) ** 2).sum(2).argmin(1)
+            s = torch.zeros_like(C).index_add_(0, lab, X)
+            c = torch.bincount(lab, minlength=C.shape[0]).float()
+            C = torch.where(c[:, None] > 0, s / c.clamp(min=1)[:, None], C)
+        return C
+    for X, C, Cb in zip(Xs, Cs, out):
+        assert torch.allclose(lloyd(X, C, 3), Cb, rtol=1e-5, atol=1e-5)
