@@ -69,13 +69,15 @@ def parse():
     return ap.parse_args()
 
 
-def plain_fp32_lloyd_batched(torch, Xs, Cs, iters, warmup=1, rows=1 << 16, centroids_out=None):
-    """Dense FP32 Lloyd with torch over many problems at once: the problems
-    of one (D, K) class are padded to the class's largest N and stacked, so
-    one batched GEMM, argmin and scatter-add serve the whole class per
-    iteration (padding rows take no part in the sums).  Returns seconds per
-    iteration of all problems; centroids_out (a list), when given, receives
-    every problem's centroids after the warmup and timed iterations."""
+def plain_fp32_lloyd_batched(torch, Xs, Cs, iters, warmup=1, rows=1 << 13, centroids_out=None):
+    """Dense FP32 Lloyd with torch over many problems at once.  Each problem
+    is cut into tiles of `rows` points (only its last tile is padded) and the
+    tiles of one (D, K) class are stacked, each with its own problem's
+    centroids gathered beside it, so a few batched GEMMs, one argmin and one
+    scatter-add serve the whole class per iteration; padding rows take no
+    part in the sums.  Returns seconds per iteration of all problems;
+    centroids_out (a list), when given, receives every problem's centroids
+    after the warmup and timed iterations."""
     torch.backends.cuda.matmul.allow_tf32 = False
     torch.set_float32_matmul_precision("highest")
     dev = Xs[0].device
@@ -84,29 +86,35 @@ def plain_fp32_lloyd_batched(torch, Xs, Cs, iters, warmup=1, rows=1 << 16, centr
         classes.setdefault((X.shape[1], C.shape[0]), []).append(i)
     state = []
     for (d, k), idx in classes.items():
-        nmax = max(Xs[i].shape[0] for i in idx)
-        b = len(idx)
-        Xp = torch.zeros((b, nmax, d), dtype=torch.float32, device=dev)
-        valid = torch.zeros((b, nmax), dtype=torch.bool, device=dev)
-        for j, i in enumerate(idx):
-            Xp[j, :Xs[i].shape[0]] = Xs[i]
-            valid[j, :Xs[i].shape[0]] = True
+        tiles = [(j, s) for j, i in enumerate(idx) for s in range(0, Xs[i].shape[0], rows)]
+        t = len(tiles)
+        Xt = torch.zeros((t, rows, d), dtype=torch.float32, device=dev)
+        valid = torch.zeros((t, rows), dtype=torch.bool, device=dev)
+        for u, (j, s) in enumerate(tiles):
+            part = Xs[idx[j]][s:s + rows]
+            Xt[u, :part.shape[0]] = part
+            valid[u, :part.shape[0]] = True
+        owner = torch.tensor([j for j, _ in tiles], dtype=torch.int64, device=dev)
         C = torch.stack([Cs[i] for i in idx]).contiguous()
-        state.append(dict(X=Xp, xn=(Xp * Xp).sum(2), valid=valid, C=C, b=b, n=nmax, d=d, k=k))
+        step = max(1, (1 << 28) // (rows * k))               # tiles per GEMM: at most 2^28 distances
+        state.append(dict(X=Xt, xn=(Xt * Xt).sum(2), valid=valid, owner=owner,
+                          flat_base=(owner * k).unsqueeze(1), Xv=Xt[valid], C=C,
+                          b=len(idx), t=t, d=d, k=k, step=step))
 
     def one():
         for st in state:
-            X, C, b, n, d, k = st["X"], st["C"], st["b"], st["n"], st["d"], st["k"]
+            X, C, b, t, d, k = st["X"], st["C"], st["b"], st["t"], st["d"], st["k"]
             cn = (C * C).sum(2)                                   # (b, k)
             Ct = C.transpose(1, 2).contiguous()                   # (b, d, k)
-            lab = torch.empty((b, n), dtype=torch.int64, device=dev)
-            for s in range(0, n, rows):
-                e = min(n, s + rows)
-                D = torch.baddbmm(cn.unsqueeze(1), X[:, s:e], Ct, beta=1.0, alpha=-2.0)
-                D.add_(st["xn"][:, s:e].unsqueeze(2))
-                lab[:, s:e] = D.argmin(2)
-            flat = (lab + torch.arange(b, device=dev).unsqueeze(1) * k)[st["valid"]]
-            sums = torch.zeros((b * k, d), dtype=torch.float32, device=dev).index_add_(0, flat, X[st["valid"]])
+            lab = torch.empty((t, X.shape[1]), dtype=torch.int64, device=dev)
+            for s in range(0, t, st["step"]):
+                e = min(t, s + st["step"])
+                own = st["owner"][s:e]
+                D = torch.baddbmm(cn[own].unsqueeze(1), X[s:e], Ct[own], beta=1.0, alpha=-2.0)
+                D.add_(st["xn"][s:e].unsqueeze(2))
+                lab[s:e] = D.argmin(2)
+            flat = (lab + st["flat_base"])[st["valid"]]
+            sums = torch.zeros((b * k, d), dtype=torch.float32, device=dev).index_add_(0, flat, st["Xv"])
             cnt = torch.bincount(flat, minlength=b * k).to(torch.float32).view(b, k)
             st["C"] = torch.where(cnt.unsqueeze(2) > 0, sums.view(b, k, d) / cnt.clamp(min=1).unsqueeze(2), C)
 
@@ -596,7 +604,7 @@ def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extr
         baseline = dict(value=ntot / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
                         ms_per_iteration_per_problem=sec_seq * 1e3, ms_per_iteration_batched=sec_bat * 1e3,
                         impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration: the faster of "
-                             "per-problem calls and per-(D, K)-class padded batched calls")
+                             "per-problem calls and per-(D, K)-class batched calls over 8192-point tiles")
         log("plain FP32 Lloyd: %.3f ms per iteration of all problems (%.3f one problem at a time, %.3f batched by class)"
             % (sec * 1e3, sec_seq * 1e3, sec_bat * 1e3))
     del Xd, Cd, spec
