@@ -309,7 +309,8 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
     if args.stats:
         for s in st:
             log("iter %(iter)3d dense=%(dense)d fail=%(point_filter_fail)d pairs=%(pairs)d dist=%(distances)d "
-                "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d" % s)
+                "rechecks=%(rechecks)d moved=%(moved)d maxdrift=%(max_drift).4g tilegroups=%(tile_groups)d "
+                "closed=%(closed)d rowtest=%(row_test)d" % s)
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
     # the dominant kernel stage, timed inside the timed region
@@ -352,8 +353,11 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
         plain_fp32_lloyd=baseline, speedup_vs_plain_fp32_lloyd=(value / baseline["value"]) if baseline else None,
         stage_ms_per_step={nm: round(a["ms"], 4) for nm, a in agg.items()},
         stage_ms_source="warmup runs with every stage timed" if warmup else "the timed runs",
-        filter={"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"]]
-                for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)})
+        filter={"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"], s["closed"],
+                                        s["row_test"]]
+                for s in st if s["iter"] in (1, 2, 3, 5, 10, P.iters)},
+        filter_fields=["point_filter_fail (L1)", "pairs", "rechecks", "moved", "closed (every group closed)",
+                       "row_test"])
 
 
 def main():
@@ -712,14 +716,19 @@ def roofline_of(stage, a, P, st):
                     unit="TFLOP/s", frac=ach / peak, traffic=None,
                     work_per_launch="2*N*K*D = %.4g flop" % flops, ms_per_launch=ms_per_launch)
     if stage == "bound_filter":
-        # every point's state read, an L1 entry written per point that fails
+        # every point's state read, an L1 entry written per point that fails;
+        # in iterations with the row test, the bound row of every point that
+        # fails ub < lbp (those in L1 and those the row test dropped)
         filt = [s for s in st if not s["dense"]]
         fails = sum(s["point_filter_fail"] for s in filt) / max(len(filt), 1)
-        byts = 16.0 * P.n + 16.0 * fails
+        bsz, gs = bound_layout(P)
+        rows = sum((s["point_filter_fail"] + s["closed"]) for s in filt if s.get("row_test")) / max(len(filt), 1)
+        byts = 16.0 * P.n + 16.0 * fails + bsz * gs * rows
         ach = byts / (ms_per_launch * 1e-3) / 1e9
         return dict(kernel="k_bound_filter", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=None,
-                    work_per_launch="16 B/point x N + 16 B per L1 entry = %.4g B" % byts,
+                    work_per_launch="16 B/point x N + 16 B per L1 entry + one bound row per point tested by rows "
+                                    "= %.4g B" % byts,
                     ms_per_launch=ms_per_launch)
     return dict(kernel=stage, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                 ms_per_launch=ms_per_launch)

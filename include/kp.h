@@ -131,13 +131,20 @@ typedef struct {
 typedef struct {
     int32_t iter;                  /* 1-based iteration number */
     int32_t dense;                 /* 1 if this iteration computed all distances */
-    int64_t point_filter_fail;     /* points whose upper bound reached the point-level lower bound */
+    int64_t point_filter_fail;     /* points whose upper bound reached the point-level lower bound
+                                      (and, with row_test, some group's bound): list L1 */
     int64_t pairs;                 /* (point, group) pairs that survived the group-level filter */
     int64_t distances;             /* point-centroid distances computed (padding excluded) */
     int64_t rechecks;              /* points re-decided in FP32 direct form */
     int64_t moved;                 /* points whose assignment changed */
     double max_drift;              /* largest centroid move of this iteration's update */
     int64_t tile_groups;           /* (64-point tile, open group) pairs visited by the distance kernel */
+    int64_t closed;                /* points with every group bound closed, their own group's
+                                      included: dropped from the point-filter failures by the
+                                      row test when it ran, else found by the group filter */
+    int32_t row_test;              /* 1 if the point-level filter tested whole bound rows in this
+                                      iteration (on after an iteration with closed >= n / 8) */
+    int32_t pad_;
 } kp_iter_stats;
 
 /* Accumulated GPU time of one stage (kp_stage_times). */

@@ -40,7 +40,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
     size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, nrel, Wu, Qt, Wa, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
+        cursor1, ctr, rowt, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
     bool anch;       // BF16 filtered tiles use estimates relative to an anchor centroid
@@ -124,6 +124,7 @@ Plan plan_problem(const kp_problem &p, bool lb16, bool det)
     o.hist1 = take((o.nk1max + 1) * 4);
     o.cursor1 = take((o.nk1max + 1) * 4);
     o.ctr = take(kp::NCTR * 8);
+    o.rowt = take(4);
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
     o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
@@ -552,6 +553,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.hist1 = (int *)(base + o.hist1);
         P.cursor1 = (int *)(base + o.cursor1);
         P.ctr = (unsigned long long *)(base + o.ctr);
+        P.rowt = (int *)(base + o.rowt);
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
         P.sink = (float *)(base + o.sink);
@@ -879,6 +881,9 @@ kp_status kp_stats(kp_ctx *ctx, int32_t problem, kp_iter_stats *out, int32_t cap
         std::memcpy(&md, &r[7], sizeof md);
         out[w].max_drift = md;
         out[w].tile_groups = r[8];
+        out[w].closed = r[9];
+        out[w].row_test = (int32_t)r[10];
+        out[w].pad_ = 0;
     }
     *n_out = w;
     return KP_OK;

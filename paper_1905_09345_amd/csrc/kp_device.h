@@ -33,7 +33,7 @@ namespace kp {
 constexpr int WAVE = 64;
 constexpr int CHUNK = 16;             // centroid slots per MFMA tile / group padding
 constexpr int STATS_CAP = 1024;       // per-iteration stats ring
-constexpr int NCTR = 8;               // per-iteration counters
+constexpr int NCTR = 9;               // per-iteration counters
 constexpr int HIST_LDS = 8192;        // largest slot count histogrammed in LDS
 constexpr int L1_HIST = 16384;        // largest key count of the L1 order histogrammed in LDS
 // Buckets of the nearest other group in the L1 order of a problem with n
@@ -54,7 +54,8 @@ constexpr int GMAX_BF16 = 1024;       // largest g of the BF16 mode (group table
 
 // counters (unsigned long long) per problem
 enum { CTR_L1 = 0, CTR_L3 = 1 /* rechecks */, CTR_MOVED = 2, CTR_PAIRS = 3, CTR_DIST = 4, CTR_DENSE = 5, CTR_VISITS = 6,
-       CTR_MV = 7 /* entries of the moved list */ };
+       CTR_MV = 7 /* entries of the moved list */,
+       CTR_CLOSED = 8 /* points with every group closed, their own included */ };
 
 struct __attribute__((aligned(16))) PointState {
     int a;        // slot of the assigned centroid
@@ -114,6 +115,8 @@ struct ProbDev {
     int *hist, *cursor;       // kg + 1: centroid update sort
     int *hist1, *cursor1;     // nk1 + 1: L1 sort
     unsigned long long *ctr;  // NCTR counters of the running iteration
+    int *rowt;                // 1: the bound filter tests whole bound rows this iteration (set by the
+                              // previous iteration's drift step from its count of closed points)
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
     float *sink;              // SINK_SLOTS x 16 floats, written and never read

@@ -279,8 +279,15 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
             rec[6] = (long long)P.ctr[CTR_MOVED];
             rec[7] = __double_as_longlong(red[0]);
             rec[8] = (long long)P.ctr[CTR_VISITS];
+            rec[9] = (long long)P.ctr[CTR_CLOSED];
+            rec[10] = *P.rowt;
             *P.iter = t;
         }
+        // the next iteration tests whole bound rows in the point-level filter
+        // when this one found at least an eighth of the points with every
+        // group closed (the rows' extra read then costs less than the later
+        // stages save on those points)
+        *P.rowt = (!first && 8ull * P.ctr[CTR_CLOSED] >= (unsigned long long)P.n) ? 1 : 0;
     }
 }
 __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
@@ -391,12 +398,76 @@ __global__ void kb_begin(const ProbDev *__restrict__ probs, const int *__restric
 // unless ub < lbp after both are brought to this iteration.  Positions come
 // from one atomic per workgroup step; within it, the order is that of the
 // points.
+//
+// lbp is brought forward by the largest drift of any centroid, which late in
+// a run exceeds the gap between a point's nearest and second-nearest
+// centroids for nearly every point; the group filter, which brings each
+// group's bound forward by that group's own drift, then finds many points
+// with every group closed (their own included).  After an iteration in which
+// at least an eighth of the points were such points, the next iteration's
+// filter also reads the bound row of each point that fails ub < lbp and keeps
+// it only if some group is open by the group filter's test.  A point dropped
+// this way keeps its assignment, state and bound row, exactly as the group
+// filter would have left them (the two-level test of Section 1, applied at
+// the point level).
 constexpr int BF_PER_THREAD = 16;
 static_assert(256 * BF_PER_THREAD == BF_CHUNK, "one bound-filter step per chunk");
 
-// Does point i fail the point-level filter?  (Its upper bound brought to this
-// iteration is not below its point-level lower bound.)  Returns the state's
-// slot, group field and that upper bound for the L1 entry.
+// Is some group open for a point with bound row r16 (FP16 codes, scale lsc)
+// or r32 (FP32), ub u brought to this iteration?  sgu: the groups'
+// cumulative drifts rounded up (an LDS copy when g fits).  The row is read in
+// segments of 64 groups, every load of a segment issued before the first
+// test (rows of codes are padded to whole segments; FP32 rows, padded to 4,
+// are read in groups of 4 up to the padding).
+__device__ __forceinline__ bool row_open(const uint16_t *__restrict__ r16, const float *__restrict__ r32,
+                                         const float *__restrict__ sgu, int g, float lsc, float u)
+{
+    if (r16) {
+#pragma unroll 1
+        for (int g0 = 0; g0 < g; g0 += 64) {
+            uint4 h[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) h[q] = *(const uint4 *)(r16 + g0 + 8 * q);
+            bool open = false;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const unsigned hw[4] = {h[q].x, h[q].y, h[q].z, h[q].w};
+                const float4 sa = *(const float4 *)(sgu + g0 + 8 * q), sb = *(const float4 *)(sgu + g0 + 8 * q + 4);
+                const float sv[8] = {sa.x, sa.y, sa.z, sa.w, sb.x, sb.y, sb.z, sb.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float v = lb16_dec((unsigned short)(hw[e >> 1] >> (16 * (e & 1))), lsc);
+                    open = open || (g0 + 8 * q + e < g && group_open(u, sv[e], v));
+                }
+            }
+            if (open) return true;
+        }
+        return false;
+    }
+    const int gp = (g + 3) & ~3;
+#pragma unroll 1
+    for (int g0 = 0; g0 < g; g0 += 32) {
+        float4 v4[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            v4[q] = g0 + 4 * q < gp ? *(const float4 *)(r32 + g0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        bool open = false;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float v[4] = {v4[q].x, v4[q].y, v4[q].z, v4[q].w};
+            const float4 s4 = g0 + 4 * q < gp ? *(const float4 *)(sgu + g0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) open = open || (g0 + 4 * q + e < g && group_open(u, sv[e], v[e]));
+        }
+        if (open) return true;
+    }
+    return false;
+}
+
+// Does point i fail the point-level test ub < lbp?  (Its upper bound brought
+// to this iteration is not below its point-level lower bound.)  Returns the
+// state's slot, group field and that upper bound for the L1 entry.
 __device__ __forceinline__ bool point_fails(const ProbDev &P, int64_t i, float sdu, int &a, int &gf, float &u)
 {
     const PointState s = P.st[i];
@@ -405,23 +476,65 @@ __device__ __forceinline__ bool point_fails(const ProbDev &P, int64_t i, float s
     u = ub_now(s.u, P.Scu[a]);
     return !(u < lb_now(s.p, sdu));
 }
+// The row test of the 16 points of a thread's step that failed ub < lbp
+// (bit r of fails): their bits are cleared where every group is closed.
+// Returns those points' count.  One point after another (the loop is not
+// unrolled: the scan's loads fill the registers).
+__device__ __forceinline__ int row_test16(const ProbDev &P, int64_t b0, unsigned &fails, const float (&ku)[BF_PER_THREAD],
+                                          const float *sgu)
+{
+    int closed = 0;
+    const bool c16 = P.prec && P.lb16;
+    const float lsc = c16 ? P.lbsc[0] : 1.f;
+#pragma unroll 1
+    for (int r = 0; r < BF_PER_THREAD; ++r) {
+        if (!((fails >> r) & 1u)) continue;
+        const size_t row = (size_t)(b0 + (int64_t)r * 256 + threadIdx.x) * P.gs;
+        if (!row_open(c16 ? P.lbh + row : nullptr, P.lb + row, sgu, P.g, lsc, ku[r])) {
+            fails &= ~(1u << r);
+            ++closed;
+        }
+    }
+    return closed;
+}
+// The groups' drifts for the row test: in LDS when they fit (padded with
+// zeros to a whole segment), else read from the problem's table.
+__device__ __forceinline__ const float *row_sgu(const ProbDev &P, bool rowt, float *lds)
+{
+    const bool fit = P.g <= GMAX_BF16;
+    if (rowt && fit)
+        for (int i = threadIdx.x; i < (P.g + 63) / 64 * 64; i += blockDim.x) lds[i] = i < P.g ? P.Sgu[i] : 0.f;
+    __syncthreads();
+    return fit ? lds : P.Sgu;
+}
+#define ROW_TEST(P, b0, fails, ku, sgu_l)                                                                    \
+    ((P).g <= GMAX_BF16 ? row_test16((P), (b0), (fails), (ku), (sgu_l)) : row_test16((P), (b0), (fails), (ku), (P).Sgu))
 
 // Deterministic mode, first pass: failures per chunk of BF_CHUNK points.
 __device__ __forceinline__ void b_bf_count(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int wcount[4];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    __shared__ float sgu_l[GMAX_BF16];
     const float sdu = P.Sdud[0];
+    const bool rowt = *P.rowt != 0;
+    row_sgu(P, rowt, sgu_l);
     for (int64_t b0 = (int64_t)bid_ * BF_CHUNK; b0 < P.n; b0 += (int64_t)nblk_ * BF_CHUNK) {
-        int mine = 0;
-#pragma unroll 4
+        unsigned fails = 0u;
+        int kgf[BF_PER_THREAD];
+        float ku[BF_PER_THREAD];
+#pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
-            int a, gf;
-            float u;
-            const bool keep = i < P.n && point_fails(P, i, sdu, a, gf, u);
-            mine += __popcll(__ballot(keep));
+            int a;
+            kgf[r] = 0;
+            ku[r] = 0.f;
+            if (i < P.n && point_fails(P, i, sdu, a, kgf[r], ku[r])) fails |= 1u << r;
         }
+        if (rowt) ROW_TEST(P, b0, fails, ku, sgu_l);
+        int mine = 0;
+#pragma unroll
+        for (int r = 0; r < BF_PER_THREAD; ++r) mine += __popcll(__ballot((fails >> r) & 1u));
         if (lane == 0) wcount[wv] = mine;
         __syncthreads();
         if (tid == 0) P.dcnt[b0 / BF_CHUNK] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
@@ -435,21 +548,30 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
     __shared__ int wcount[4];
     __shared__ unsigned long long base_s;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    __shared__ float sgu_l[GMAX_BF16];
     const float sdu = P.Sdud[0];
+    const bool rowt = *P.rowt != 0;
+    row_sgu(P, rowt, sgu_l);
     const int64_t chunk = 256 * BF_PER_THREAD;
+    unsigned long long n_closed = 0;
     for (int64_t b0 = (int64_t)bid_ * chunk; b0 < P.n; b0 += (int64_t)nblk_ * chunk) {
         unsigned long long masks[BF_PER_THREAD];
         int ka[BF_PER_THREAD], kgf[BF_PER_THREAD];   // the kept points' slot and group field
         float ku[BF_PER_THREAD];                     // and upper bound brought to this iteration
         int mine = 0;
+        unsigned fails = 0u;
 #pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
             ka[r] = 0;
             kgf[r] = 0;
             ku[r] = 0.f;
-            const bool keep = i < P.n && point_fails(P, i, sdu, ka[r], kgf[r], ku[r]);
-            masks[r] = __ballot(keep);
+            if (i < P.n && point_fails(P, i, sdu, ka[r], kgf[r], ku[r])) fails |= 1u << r;
+        }
+        if (rowt) n_closed += (unsigned long long)ROW_TEST(P, b0, fails, ku, sgu_l);
+#pragma unroll
+        for (int r = 0; r < BF_PER_THREAD; ++r) {
+            masks[r] = __ballot((fails >> r) & 1u);
             mine += __popcll(masks[r]);
         }
         if (lane == 0) wcount[wv] = mine;
@@ -474,6 +596,7 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
         }
         __syncthreads();
     }
+    if (n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
 }
 __global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
 {
@@ -1254,13 +1377,14 @@ __device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, c
     const long long count = list_len(P, CTR_L1);
     const long long ntiles = (count + WAVE - 1) / WAVE;
     const int half = lane >> 5, col = lane & 31;
-    unsigned long long n_pairs = 0, n_visits = 0;
+    unsigned long long n_pairs = 0, n_visits = 0, n_closed = 0;
     for (long long tl = (long long)bid_ * GT_WAVES + wv; tl < ntiles; tl += (long long)nblk_ * GT_WAVES) {
         const long long idx = tl * WAVE + lane;
         const bool act = idx < count;
         const int pid = act ? clamp_pid(P, P.L1s[idx]) : 0;
         float ubt = KP_INF, minnc = KP_INF;
         int ga = -1;
+        bool anyb = false;   // some group open by its bound (own group included)
         if (act) {
             const PointState s = P.st[pid];
             const int a = clamp_slot(P, s.a);
@@ -1290,7 +1414,9 @@ __device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, c
                 const int g = g0 + j;
                 const float sgu = P.Sgu[g];
                 const float v = act ? sm[lane * GT_LD + j] : 0.f;
-                const bool cand = act && (g == ga || group_open(ubt, sgu, v));
+                const bool byb = act && group_open(ubt, sgu, v);
+                const bool cand = byb || (act && g == ga);
+                anyb = anyb || byb;
                 const unsigned long long m = __ballot(cand);
                 if (m) {
                     if (lane == 0) lst[cnt] = make_int4(g, (int)(unsigned)m, (int)(unsigned)(m >> 32), 0);
@@ -1305,6 +1431,7 @@ __device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, c
         }
         if (lane == 0) P.tcnt[tl] = cnt;
         n_visits += (unsigned long long)cnt;
+        n_closed += (unsigned long long)__popcll(__ballot(act && !anyb));
         if (act) {
             P.ps4[idx] = make_float4(ubt, f_dn(minnc), 0.f, 0.f);
             P.psf[idx] = 1;
@@ -1312,6 +1439,7 @@ __device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, c
     }
     if (lane == 0 && n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
     if (lane == 0 && n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
+    if (lane == 0 && n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
 }
 __global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
 {
@@ -1350,6 +1478,7 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
     const float lsc = P.lbsc[0];
     constexpr bool lb16 = LB16;
     int rb = 0;   // mask buffer, alternating over every round of the launch
+    unsigned long long n_closed = 0;
     for (long long tl = bid_; tl < ntiles; tl += nblk_) {   // uniform per workgroup
         const long long pos = tl * 64 + 16 * wv + pt;
         const bool in = pos < count;
@@ -1366,6 +1495,7 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
         int4 *vis = P.tlist + (size_t)tl * P.g;
         float cm = KP_INF;
         int nv = 0;
+        bool anyb = false;   // some group of this lane's 16 open by its bound (own group included)
         for (int g0 = 0; g0 < P.g; g0 += WAVE, rb ^= 1) {
             const int gq = g0 + 16 * quad;
             float v[16], sg[16];
@@ -1407,7 +1537,9 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
             for (int j = 0; j < 16; ++j) {
                 const int g = gq + j;
                 const bool cand = in && g < P.g;
-                const bool open = cand && (g == ga || group_open(ubt, sg[j], v[j]));
+                const bool byb = cand && group_open(ubt, sg[j], v[j]);
+                const bool open = byb || (cand && g == ga);
+                anyb = anyb || byb;
                 bits |= open ? 1u << j : 0u;
                 cm = (cand && !open) ? fminf(cm, v[j] - sg[j]) : cm;   // rounded down once below
             }
@@ -1435,7 +1567,11 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
         cm = fminf(cm, __shfl_xor(cm, 32));
         if (in && quad == 0) P.minnc[pos] = f_dn(cm);
         if (wv == 0 && lane == 0) P.tcnt[tl] = nv;
+        // points of this wave with every group closed by its bound
+        const unsigned long long ob = __ballot(anyb), ib = __ballot(in);
+        n_closed += (unsigned long long)__popcll(ib & ~(ob | ob >> 16 | ob >> 32 | ob >> 48) & 0xFFFFull);
     }
+    if (lane == 0 && n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
 }
 template <bool LB16>
 __global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter<LB16>(P, (int)blockIdx.x, (int)gridDim.x); }

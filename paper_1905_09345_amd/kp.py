@@ -44,7 +44,8 @@ STAGES = ("begin", "bound_filter", "l1_sort", "assign_dense", "group_filter", "a
 class kp_iter_stats(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("dense", ctypes.c_int32), ("point_filter_fail", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("distances", ctypes.c_int64), ("rechecks", ctypes.c_int64),
-                ("moved", ctypes.c_int64), ("max_drift", ctypes.c_double), ("tile_groups", ctypes.c_int64)]
+                ("moved", ctypes.c_int64), ("max_drift", ctypes.c_double), ("tile_groups", ctypes.c_int64),
+                ("closed", ctypes.c_int64), ("row_test", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class kp_stage_time(ctypes.Structure):
@@ -158,7 +159,7 @@ def kp_stats(ctx, problem, cap=1024):
     _check(lib().kp_stats(ctypes.c_void_p(ctx), int(problem), buf, int(cap), ctypes.byref(n)), "kp_stats")
     return [dict(iter=s.iter, dense=s.dense, point_filter_fail=s.point_filter_fail, pairs=s.pairs,
                  distances=s.distances, rechecks=s.rechecks, moved=s.moved, max_drift=s.max_drift,
-                 tile_groups=s.tile_groups)
+                 tile_groups=s.tile_groups, closed=s.closed, row_test=s.row_test)
             for s in buf[:n.value]]
 
 

@@ -33,7 +33,8 @@ def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_tuning) == 32 and kp.kp_tuning.bound_codes.offset == 20
     assert kp.kp_tuning.timing_stages.offset == 24 and kp.kp_tuning.deterministic.offset == 28
     assert ctypes.sizeof(kp.kp_stage_time) == 40
-    assert ctypes.sizeof(kp.kp_iter_stats) == 64 and kp.kp_iter_stats.point_filter_fail.offset == 8
+    assert ctypes.sizeof(kp.kp_iter_stats) == 80 and kp.kp_iter_stats.point_filter_fail.offset == 8
+    assert kp.kp_iter_stats.closed.offset == 64 and kp.kp_iter_stats.row_test.offset == 72
 
 
 def _prob(**kw):

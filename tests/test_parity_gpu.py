@@ -54,6 +54,28 @@ def test_c5_shape_bf16():
     assert r["stats"][-1]["pairs"] < P.n * P.g
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_row_test_in_point_filter(prec):
+    """Late in a run many points have every group closed, their own included.
+    After an iteration where at least an eighth of the points were such
+    points, the point-level filter reads whole bound rows and leaves them out
+    of L1.  The run stays step-locked with the oracle, the gate follows that
+    rule in every iteration, and it switches on."""
+    rng = np.random.default_rng(21)
+    X = datagen.gaussian_mixture(rng, 20_011, 24, 40)
+    C0 = datagen.kmeanspp(rng, X, 60, sample=4000)
+    _print_case("row-test", prec=prec)
+    r = run_steplocked(X, C0, 8, prec, 25)
+    st = r["stats"]
+    n = X.shape[0]
+    assert st[0]["row_test"] == 0 and st[0]["closed"] == 0
+    for prev, cur in zip(st, st[1:]):
+        assert cur["row_test"] == int(8 * prev["closed"] >= n), (prev, cur)
+        assert cur["point_filter_fail"] + (cur["closed"] if cur["row_test"] else 0) <= n
+    on = [s for s in st if s["row_test"]]
+    assert on and sum(s["closed"] for s in on) > 0, [(s["iter"], s["closed"]) for s in st]
+
+
 @pytest.mark.parametrize("d", [16, 32, 64])
 def test_bf16_small_dims(d):
     rng = np.random.default_rng(d)
