@@ -40,7 +40,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
     size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, nrel, Wu, Qt, Wa, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
-        cursor1, ctr, rowt, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
+        cursor1, ctr, rowt, rclosed, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
     bool anch;       // BF16 filtered tiles use estimates relative to an anchor centroid
@@ -125,6 +125,7 @@ Plan plan_problem(const kp_problem &p, bool lb16, bool det)
     o.cursor1 = take((o.nk1max + 1) * 4);
     o.ctr = take(kp::NCTR * 8);
     o.rowt = take(4);
+    o.rclosed = take((n + 63) / 64 * 8);
     o.stats = take((size_t)kp::STATS_CAP * 16 * 8);
     o.iter = take(4);
     o.sink = take(bf ? (size_t)kp::SINK_SLOTS * 64 : 0);
@@ -554,6 +555,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.cursor1 = (int *)(base + o.cursor1);
         P.ctr = (unsigned long long *)(base + o.ctr);
         P.rowt = (int *)(base + o.rowt);
+        P.rclosed = (unsigned *)(base + o.rclosed);
         P.stats = (long long *)(base + o.stats);
         P.iter = (int *)(base + o.iter);
         P.sink = (float *)(base + o.sink);

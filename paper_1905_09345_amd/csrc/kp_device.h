@@ -115,8 +115,9 @@ struct ProbDev {
     int *hist, *cursor;       // kg + 1: centroid update sort
     int *hist1, *cursor1;     // nk1 + 1: L1 sort
     unsigned long long *ctr;  // NCTR counters of the running iteration
-    int *rowt;                // 1: the bound filter tests whole bound rows this iteration (set by the
-                              // previous iteration's drift step from its count of closed points)
+    int *rowt;                // 1: the point-level filter tests whole bound rows this iteration (set by
+                              // the previous iteration's drift step from its count of closed points)
+    unsigned *rclosed;        // with rowt: bit i of word i / 32 set for point i when every group is closed
     long long *stats;         // STATS_CAP x 16
     int *iter;                // completed iterations
     float *sink;              // SINK_SLOTS x 16 floats, written and never read

@@ -287,7 +287,7 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
         // when this one found at least an eighth of the points with every
         // group closed (the rows' extra read then costs less than the later
         // stages save on those points)
-        *P.rowt = (!first && 8ull * P.ctr[CTR_CLOSED] >= (unsigned long long)P.n) ? 1 : 0;
+        *P.rowt = (!first && P.g <= GMAX_BF16 && 8ull * P.ctr[CTR_CLOSED] >= (unsigned long long)P.n) ? 1 : 0;
     }
 }
 __global__ __launch_bounds__(1024) void k_drift(ProbDev P, int first)
@@ -413,58 +413,6 @@ __global__ void kb_begin(const ProbDev *__restrict__ probs, const int *__restric
 constexpr int BF_PER_THREAD = 16;
 static_assert(256 * BF_PER_THREAD == BF_CHUNK, "one bound-filter step per chunk");
 
-// Is some group open for a point with bound row r16 (FP16 codes, scale lsc)
-// or r32 (FP32), ub u brought to this iteration?  sgu: the groups'
-// cumulative drifts rounded up (an LDS copy when g fits).  The row is read in
-// segments of 64 groups, every load of a segment issued before the first
-// test (rows of codes are padded to whole segments; FP32 rows, padded to 4,
-// are read in groups of 4 up to the padding).
-__device__ __forceinline__ bool row_open(const uint16_t *__restrict__ r16, const float *__restrict__ r32,
-                                         const float *__restrict__ sgu, int g, float lsc, float u)
-{
-    if (r16) {
-#pragma unroll 1
-        for (int g0 = 0; g0 < g; g0 += 64) {
-            uint4 h[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) h[q] = *(const uint4 *)(r16 + g0 + 8 * q);
-            bool open = false;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const unsigned hw[4] = {h[q].x, h[q].y, h[q].z, h[q].w};
-                const float4 sa = *(const float4 *)(sgu + g0 + 8 * q), sb = *(const float4 *)(sgu + g0 + 8 * q + 4);
-                const float sv[8] = {sa.x, sa.y, sa.z, sa.w, sb.x, sb.y, sb.z, sb.w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float v = lb16_dec((unsigned short)(hw[e >> 1] >> (16 * (e & 1))), lsc);
-                    open = open || (g0 + 8 * q + e < g && group_open(u, sv[e], v));
-                }
-            }
-            if (open) return true;
-        }
-        return false;
-    }
-    const int gp = (g + 3) & ~3;
-#pragma unroll 1
-    for (int g0 = 0; g0 < g; g0 += 32) {
-        float4 v4[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            v4[q] = g0 + 4 * q < gp ? *(const float4 *)(r32 + g0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool open = false;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float v[4] = {v4[q].x, v4[q].y, v4[q].z, v4[q].w};
-            const float4 s4 = g0 + 4 * q < gp ? *(const float4 *)(sgu + g0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) open = open || (g0 + 4 * q + e < g && group_open(u, sv[e], v[e]));
-        }
-        if (open) return true;
-    }
-    return false;
-}
-
 // Does point i fail the point-level test ub < lbp?  (Its upper bound brought
 // to this iteration is not below its point-level lower bound.)  Returns the
 // state's slot, group field and that upper bound for the L1 entry.
@@ -476,65 +424,156 @@ __device__ __forceinline__ bool point_fails(const ProbDev &P, int64_t i, float s
     u = ub_now(s.u, P.Scu[a]);
     return !(u < lb_now(s.p, sdu));
 }
-// The row test of the 16 points of a thread's step that failed ub < lbp
-// (bit r of fails): their bits are cleared where every group is closed.
-// Returns those points' count.  One point after another (the loop is not
-// unrolled: the scan's loads fill the registers).
-__device__ __forceinline__ int row_test16(const ProbDev &P, int64_t b0, unsigned &fails, const float (&ku)[BF_PER_THREAD],
-                                          const float *sgu)
+// Bits of x at multiples of np (np a power of two, at most 8) moved to
+// positions 0, 1, ...: one halving per factor of two.
+__device__ __forceinline__ unsigned long long gather_stride(unsigned long long x, int lnp)
 {
-    int closed = 0;
-    const bool c16 = P.prec && P.lb16;
-    const float lsc = c16 ? P.lbsc[0] : 1.f;
-#pragma unroll 1
-    for (int r = 0; r < BF_PER_THREAD; ++r) {
-        if (!((fails >> r) & 1u)) continue;
-        const size_t row = (size_t)(b0 + (int64_t)r * 256 + threadIdx.x) * P.gs;
-        if (!row_open(c16 ? P.lbh + row : nullptr, P.lb + row, sgu, P.g, lsc, ku[r])) {
-            fails &= ~(1u << r);
-            ++closed;
+    for (int s = 0; s < lnp; ++s) {
+        x &= 0x5555555555555555ull;
+        x = (x | (x >> 1)) & 0x3333333333333333ull;
+        x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+        x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+        x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+        x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    }
+    return x;
+}
+// Row test of a wave's 64 consecutive points p0 .. p0 + 63 (lane l: point
+// p0 + l with ub u brought to this iteration); fm: the points that failed
+// ub < lbp.  Returns the points of fm with every group closed.  np (<= 8)
+// lanes read one point's row side by side, 16 bytes each (8 FP16 codes or 4
+// FP32 bounds), so each load instruction covers 64 / np points' segments of
+// np pieces; the np loads of a segment are all issued before the first test,
+// and ballots merge the lanes' results per point.  sgu: the groups'
+// cumulative drifts rounded up, in LDS.  Rows are padded to whole pieces.
+template <bool C16>
+__device__ __forceinline__ unsigned long long row_closed64(const ProbDev &P, int64_t p0, unsigned long long fm, float u,
+                                                           const float *__restrict__ sgu)
+{
+    constexpr int PER = C16 ? 8 : 4;   // groups per 16-byte piece
+    constexpr int ESZ = C16 ? 2 : 4;
+    const int lane = lane_id(), g = P.g;
+    const int need = (g + PER - 1) / PER;
+    const int lnp = need <= 1 ? 0 : need <= 2 ? 1 : need <= 4 ? 2 : 3;
+    const int np = 1 << lnp, ppl = 64 >> lnp;   // lanes per point, points per load
+    const int q = lane >> lnp, pc = lane & (np - 1);
+    const unsigned long long stride = lnp == 0 ? ~0ull : lnp == 1 ? 0x5555555555555555ull
+                                    : lnp == 2 ? 0x1111111111111111ull : 0x0101010101010101ull;
+    const float lsc = C16 ? P.lbsc[0] : 1.f;
+    const char *rows = C16 ? (const char *)P.lbh : (const char *)P.lb;
+    const size_t pitch = (size_t)P.gs * ESZ;
+    unsigned long long open = 0ull;   // points with some group open
+    for (int g0 = 0; g0 < g && (fm & ~open) != 0ull; g0 += np * PER) {
+        const int gp = g0 + pc * PER;   // this lane's first group
+        const bool gin = gp < g;
+        float sv[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) sv[e] = (gin && gp + e < g) ? sgu[gp + e] : 0.f;
+        const unsigned long long todo = fm & ~open;
+        uint4 h[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int j = b * ppl + q;
+            const bool act = b < np && gin && ((todo >> (j & 63)) & 1ull);
+            h[b] = act ? *(const uint4 *)(rows + (size_t)(p0 + j) * pitch + (size_t)gp * ESZ) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            if (b >= np) break;
+            const float uj = __shfl(u, (b * ppl + q) & 63);
+            const unsigned w[4] = {h[b].x, h[b].y, h[b].z, h[b].w};
+            bool o = false;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const float v = C16 ? lb16_dec((unsigned short)(w[e >> 1] >> (16 * (e & 1))), lsc) : __uint_as_float(w[e & 3]);
+                o = o || (gp + e < g && group_open(uj, sv[e], v));
+            }
+            unsigned long long m = __ballot(o);
+            for (int s = 1; s < np; s <<= 1) m |= m >> s;   // bit q np: any lane of point q
+            open |= gather_stride(m & stride, lnp) << (b * ppl);
         }
     }
-    return closed;
+    return fm & ~open;
 }
-// The groups' drifts for the row test: in LDS when they fit (padded with
-// zeros to a whole segment), else read from the problem's table.
-__device__ __forceinline__ const float *row_sgu(const ProbDev &P, bool rowt, float *lds)
+// Add the workgroup's count of points with every group closed (each wave's
+// in its lane 0) to the iteration's counter: one atomic per workgroup.  Every
+// thread of the workgroup calls it.
+__device__ __forceinline__ void block_add_closed(const ProbDev &P, unsigned long long mine)
 {
-    const bool fit = P.g <= GMAX_BF16;
-    if (rowt && fit)
-        for (int i = threadIdx.x; i < (P.g + 63) / 64 * 64; i += blockDim.x) lds[i] = i < P.g ? P.Sgu[i] : 0.f;
+    __shared__ unsigned long long part[8];
+    const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    if (lane_id() == 0) part[wv] = mine;
     __syncthreads();
-    return fit ? lds : P.Sgu;
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < nw; ++w) t += part[w];
+        if (t) atomicAdd(&P.ctr[CTR_CLOSED], t);
+    }
 }
-#define ROW_TEST(P, b0, fails, ku, sgu_l)                                                                    \
-    ((P).g <= GMAX_BF16 ? row_test16((P), (b0), (fails), (ku), (sgu_l)) : row_test16((P), (b0), (fails), (ku), (P).Sgu))
+
+// Row pre-pass (only with the row test on): one wave per 64 consecutive
+// points.  Each lane tests its point's ub < lbp, the wave runs the row test
+// on the points that fail it, and the mask of the points with every group
+// closed is stored as two words of rclosed, which the bound filter then
+// reads.  The groups' drifts are copied to LDS (g <= GMAX_BF16 whenever the
+// row test is on).
+__device__ __forceinline__ void b_row_pre(const ProbDev &P, const int bid_, const int nblk_)
+{
+    __shared__ float sgu_l[GMAX_BF16];
+    if (*P.rowt == 0) return;   // uniform: the gate of this iteration
+    for (int i = threadIdx.x; i < (P.g + 63) / 64 * 64; i += blockDim.x) sgu_l[i] = i < P.g ? P.Sgu[i] : 0.f;
+    __syncthreads();
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    const bool c16 = P.prec && P.lb16;
+    const float sdu = P.Sdud[0];
+    const int64_t nw = (P.n + 63) / 64;
+    unsigned long long n_closed = 0;
+    for (int64_t w = (int64_t)bid_ * 4 + wv; w < nw; w += (int64_t)nblk_ * 4) {
+        const int64_t p0 = w * 64, i = p0 + lane;
+        int a = 0, gf = 0;
+        float u = 0.f;
+        const bool f = i < P.n && point_fails(P, i, sdu, a, gf, u);
+        const unsigned long long fm = __ballot(f);
+        const unsigned long long cm = fm == 0ull ? 0ull
+                                      : (c16 ? row_closed64<true>(P, p0, fm, u, sgu_l)
+                                             : row_closed64<false>(P, p0, fm, u, sgu_l));
+        if (lane < 2) P.rclosed[2 * w + lane] = (unsigned)(cm >> (32 * lane));
+        n_closed += (unsigned long long)__popcll(cm);
+    }
+    block_add_closed(P, n_closed);
+}
+__global__ __launch_bounds__(256) void k_row_pre(ProbDev P) { b_row_pre(P, (int)blockIdx.x, (int)gridDim.x); }
+__global__ __launch_bounds__(256) void kb_row_pre(const ProbDev *__restrict__ probs, const int *__restrict__ tab, int count)
+{
+    const int pi = batch_problem(tab, count);
+    const ProbDev P = probs[pi];
+    b_row_pre(P, (int)blockIdx.x - tab[pi], tab[pi + 1] - tab[pi]);
+}
+// Does point i go to L1: it fails ub < lbp and, with the row test on, the
+// row pre-pass found some group open.
+__device__ __forceinline__ bool point_kept(const ProbDev &P, int64_t i, float sdu, bool rowt, int &a, int &gf, float &u)
+{
+    if (!point_fails(P, i, sdu, a, gf, u)) return false;
+    return !rowt || !((P.rclosed[i >> 5] >> (i & 31)) & 1u);
+}
 
 // Deterministic mode, first pass: failures per chunk of BF_CHUNK points.
 __device__ __forceinline__ void b_bf_count(const ProbDev &P, const int bid_, const int nblk_)
 {
     __shared__ int wcount[4];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
-    __shared__ float sgu_l[GMAX_BF16];
     const float sdu = P.Sdud[0];
     const bool rowt = *P.rowt != 0;
-    row_sgu(P, rowt, sgu_l);
     for (int64_t b0 = (int64_t)bid_ * BF_CHUNK; b0 < P.n; b0 += (int64_t)nblk_ * BF_CHUNK) {
-        unsigned fails = 0u;
-        int kgf[BF_PER_THREAD];
-        float ku[BF_PER_THREAD];
-#pragma unroll
+        int mine = 0;
+#pragma unroll 4
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
-            int a;
-            kgf[r] = 0;
-            ku[r] = 0.f;
-            if (i < P.n && point_fails(P, i, sdu, a, kgf[r], ku[r])) fails |= 1u << r;
+            int a, gf;
+            float u;
+            const bool keep = i < P.n && point_kept(P, i, sdu, rowt, a, gf, u);
+            mine += __popcll(__ballot(keep));
         }
-        if (rowt) ROW_TEST(P, b0, fails, ku, sgu_l);
-        int mine = 0;
-#pragma unroll
-        for (int r = 0; r < BF_PER_THREAD; ++r) mine += __popcll(__ballot((fails >> r) & 1u));
         if (lane == 0) wcount[wv] = mine;
         __syncthreads();
         if (tid == 0) P.dcnt[b0 / BF_CHUNK] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
@@ -548,30 +587,22 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
     __shared__ int wcount[4];
     __shared__ unsigned long long base_s;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
-    __shared__ float sgu_l[GMAX_BF16];
     const float sdu = P.Sdud[0];
     const bool rowt = *P.rowt != 0;
-    row_sgu(P, rowt, sgu_l);
     const int64_t chunk = 256 * BF_PER_THREAD;
-    unsigned long long n_closed = 0;
     for (int64_t b0 = (int64_t)bid_ * chunk; b0 < P.n; b0 += (int64_t)nblk_ * chunk) {
         unsigned long long masks[BF_PER_THREAD];
         int ka[BF_PER_THREAD], kgf[BF_PER_THREAD];   // the kept points' slot and group field
         float ku[BF_PER_THREAD];                     // and upper bound brought to this iteration
         int mine = 0;
-        unsigned fails = 0u;
 #pragma unroll
         for (int r = 0; r < BF_PER_THREAD; ++r) {
             const int64_t i = b0 + (int64_t)r * 256 + tid;
             ka[r] = 0;
             kgf[r] = 0;
             ku[r] = 0.f;
-            if (i < P.n && point_fails(P, i, sdu, ka[r], kgf[r], ku[r])) fails |= 1u << r;
-        }
-        if (rowt) n_closed += (unsigned long long)ROW_TEST(P, b0, fails, ku, sgu_l);
-#pragma unroll
-        for (int r = 0; r < BF_PER_THREAD; ++r) {
-            masks[r] = __ballot((fails >> r) & 1u);
+            const bool keep = i < P.n && point_kept(P, i, sdu, rowt, ka[r], kgf[r], ku[r]);
+            masks[r] = __ballot(keep);
             mine += __popcll(masks[r]);
         }
         if (lane == 0) wcount[wv] = mine;
@@ -596,7 +627,6 @@ __device__ __forceinline__ void b_bound_filter(const ProbDev &P, const int bid_,
         }
         __syncthreads();
     }
-    if (n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
 }
 __global__ __launch_bounds__(256) void k_bound_filter(ProbDev P)
 {
@@ -1439,7 +1469,7 @@ __device__ __forceinline__ void b_group_test(const ProbDev &P, const int bid_, c
     }
     if (lane == 0 && n_pairs) atomicAdd(&P.ctr[CTR_PAIRS], n_pairs);
     if (lane == 0 && n_visits) atomicAdd(&P.ctr[CTR_VISITS], n_visits);
-    if (lane == 0 && n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
+    block_add_closed(P, n_closed);
 }
 __global__ __launch_bounds__(WAVE * GT_WAVES) void k_group_test(ProbDev P)
 {
@@ -1571,7 +1601,7 @@ __device__ __forceinline__ void b_gfilter(const ProbDev &P, const int bid_, cons
         const unsigned long long ob = __ballot(anyb), ib = __ballot(in);
         n_closed += (unsigned long long)__popcll(ib & ~(ob | ob >> 16 | ob >> 32 | ob >> 48) & 0xFFFFull);
     }
-    if (lane == 0 && n_closed) atomicAdd(&P.ctr[CTR_CLOSED], n_closed);
+    block_add_closed(P, n_closed);
 }
 template <bool LB16>
 __global__ __launch_bounds__(256) void k_gfilter(ProbDev P) { b_gfilter<LB16>(P, (int)blockIdx.x, (int)gridDim.x); }
@@ -3777,6 +3807,9 @@ hipError_t launch_stage(const ProbDev &P, hipStream_t s, Stage st, bool dense, c
         break;
     case ST_FILTER: {
         const int grid = cap_grid((P.n + BF_CHUNK - 1) / BF_CHUNK, cfg.grid_cap);
+        if (P.g <= GMAX_BF16)   // returns at once unless the row test is on
+            hipLaunchKernelGGL(k_row_pre, dim3(cap_grid((P.n + 255) / 256, std::min(cfg.grid_cap, 2048))), dim3(256), 0,
+                               s, P);
         if (P.det) {
             hipLaunchKernelGGL(k_bf_count, dim3(grid), dim3(256), 0, s, P);
             hipLaunchKernelGGL(k_bf_scan, dim3(1), dim3(1024), 0, s, P, (int)((P.n + BF_CHUNK - 1) / BF_CHUNK));
@@ -3869,6 +3902,7 @@ static int tab_blocks(int id, const ProbDev &P, const LaunchCfg &cfg, int cap)
     switch (id) {
     case TB_BEGIN: return cap_grid(((long long)P.nk1 + 256) / 256, 1024);
     case TB_FILTER: return cap_grid((n + 4095) / 4096, cap);
+    case TB_ROWPRE: return P.g <= GMAX_BF16 ? cap_grid((n + 255) / 256, std::min(cap, 2048)) : 0;
     case TB_SORT: return cap_grid((n + 16383) / 16384, 1024);
     case TB_ONE: return 1;
     case TB_CENT: return cap_grid((P.kg + 3) / 4, 4096);
@@ -3948,7 +3982,10 @@ hipError_t launch_stage_batch(const Batch &B, hipStream_t s, Stage st, bool dens
     const int wthreads = 64 * cfg.waves;
     switch (st) {
     case ST_BEGIN: KB_LAUNCH(TB_BEGIN, kb_begin, 256, dense ? 1 : 0); break;
-    case ST_FILTER: KB_LAUNCH(TB_FILTER, kb_bound_filter, 256); break;
+    case ST_FILTER:
+        KB_LAUNCH(TB_ROWPRE, kb_row_pre, 256);   // returns at once unless the problem's row test is on
+        KB_LAUNCH(TB_FILTER, kb_bound_filter, 256);
+        break;
     case ST_SORT:
         KB_LAUNCH(TB_SORT, kb_key_hist, 256);
         KB_LAUNCH(TB_ONE, kb_scan, 1024, 1);

@@ -33,7 +33,7 @@ hipError_t launch_iteration(const ProbDev &P, hipStream_t s, bool dense, const L
 // gives each problem a contiguous range of blocks; a problem outside the
 // class gets none.
 enum TabId {
-    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_GF, TB_HIST, TB_SCATTER, TB_ATAB,
+    TB_BEGIN = 0, TB_FILTER, TB_SORT, TB_ONE, TB_CENT, TB_GT, TB_GF, TB_HIST, TB_SCATTER, TB_ATAB, TB_ROWPRE,
     TB_DENSE_F32,                     // + DMAX class (5)
     TB_TILE_F32 = TB_DENSE_F32 + 5,   // + DMAX class (5)
     TB_BLK64 = TB_TILE_F32 + 5,       // + KS class (6)
