@@ -62,6 +62,8 @@ def parse():
                     help="workgroups per CU of the grid-stride launches (0: library default)")
     ap.add_argument("--bound-codes", type=int, default=0, choices=[0, 1, 2],
                     help="BF16 mode: 1 = FP32 group bounds, 2 = FP16 codes (0: library default)")
+    ap.add_argument("--no-group-autotune", action="store_true",
+                    help="skip the extra run at the group counts kp_autotune_groups picks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip kp_autotune (untimed, before the contexts are made) and use the defaults")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -320,6 +322,11 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
         if nm in agg and nm != dom:
             r = roofline_of(nm, agg[nm], P, st)
             others[nm] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    groups = None
+    if not args.no_group_autotune:
+        groups = autotuned_groups(args, torch, KMeans, kp_tuning, spec, tun, P.iters, min(steps, 2))
+        if "ms_per_step" in groups:
+            log("with autotuned groups: %.3f ms/step" % groups["ms_per_step"])
     ref, km = check_run(KMeans, kp_tuning, spec, tun, P.iters)
     serve = None
     if extras:
@@ -351,6 +358,7 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
                 else "fp32 direct + fp64 centroids", "tuning": dict(TUNING)},
         roofline=roofline, stage_rooflines=others, serving=serve, cpu_baseline=cpu, precision=precision,
         plain_fp32_lloyd=baseline, speedup_vs_plain_fp32_lloyd=(value / baseline["value"]) if baseline else None,
+        autotuned_groups=groups,
         stage_ms_per_step={nm: round(a["ms"], 4) for nm, a in agg.items()},
         stage_ms_source="warmup runs with every stage timed" if warmup else "the timed runs",
         filter={"iter_%d" % s["iter"]: [s["point_filter_fail"], s["pairs"], s["rechecks"], s["moved"], s["closed"],
@@ -402,7 +410,8 @@ def main():
             r = measure_single(args, torch, datagen, KMeans, kp_tuning, c, args.secondary_steps, 1, extras=False)
         secondary["C%d" % c] = {k: r[k] for k in ("value", "ms_per_step", "steps", "dtype", "config", "roofline",
                                                   "stage_rooflines", "precision", "plain_fp32_lloyd",
-                                                  "speedup_vs_plain_fp32_lloyd", "cpu_baseline") if k in r}
+                                                  "speedup_vs_plain_fp32_lloyd", "autotuned_groups",
+                                                  "cpu_baseline") if k in r}
         secondary["C%d" % c]["unit"] = "point-iterations/s"
         torch.cuda.empty_cache()
     if secondary:
@@ -541,6 +550,30 @@ def run_steps(torch, KMeans, kp_tuning, spec, tun, T, steps, warmup):
 TUNING = {}
 
 
+def autotuned_groups(args, torch, KMeans, kp_tuning, spec, tun, T, steps):
+    """The same workload with the group counts kp_autotune_groups picks (per
+    (D, K) class; the configured g is one of the candidates).  The method's
+    result does not depend on g, so this is the configured run's work at the
+    group counts the library would choose.  Returns the picked g per class,
+    the time per step of `steps` timed runs and the autotuner's own time."""
+    t0 = time.perf_counter()
+    gs = KMeans.autotune_groups(spec, iters=3, tuning=tun)
+    tune_s = time.perf_counter() - t0
+    picks = {}
+    for sp, g in zip(spec, gs):
+        picks.setdefault("d%d_k%d" % (sp[0].shape[1], sp[1].shape[0]), g)
+    log("group autotune (%.1f s): %s" % (tune_s, picks))
+    res = dict(g=picks, autotune_seconds=tune_s, candidates="per (D, K) class: the configured g, ceil(K/16), ceil(K/10)")
+    if all(int(sp[2]) == g for sp, g in zip(spec, gs)):
+        res["same_as_configured"] = True   # nothing to measure apart
+        return res
+    spec2 = [(sp[0], sp[1], g) + tuple(sp[3:]) for sp, g in zip(spec, gs)]
+    el, _, _, _, _ = run_steps(torch, KMeans, kp_tuning, spec2, tun, T, steps, 1)
+    ntot = sum(sp[0].shape[0] for sp in spec)
+    res.update(value=ntot * T * steps / el, ms_per_step=el / steps * 1e3, steps=steps)
+    return res
+
+
 def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extras=True):
     """The batched workload: many independent problems in one context, every
     stage launched once for all of them, one graph replay per iteration."""
@@ -558,6 +591,11 @@ def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extr
     value = ntot * T * steps / el
     for nm, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
         log("stage %-14s %8.3f ms/step over %5.1f launches" % (nm, a["ms"], a["launches"]))
+    groups = None
+    if not args.no_group_autotune:
+        groups = autotuned_groups(args, torch, KMeans, kp_tuning, spec, tun, T, min(steps, 2))
+        if "ms_per_step" in groups:
+            log("with autotuned groups: %.3f ms/step" % groups["ms_per_step"])
     # statistics and the oracle check come from one more (untimed) run
     t = kp_tuning(**{f: getattr(tun, f) for f, _ in kp_tuning._fields_})
     t.timing = 0
@@ -629,6 +667,7 @@ def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extr
                 "iterations": T, "precision": "bf16 MFMA + fp32 recheck + fp64 centroids", "tuning": dict(TUNING)},
         roofline=roofline, stage_rooflines=others, cpu_baseline=cpu, precision=precision,
         plain_fp32_lloyd=baseline, speedup_vs_plain_fp32_lloyd=(value / baseline["value"]) if baseline else None,
+        autotuned_groups=groups,
         stage_ms_per_step={nm: round(a["ms"], 4) for nm, a in agg.items()})
 
 

@@ -278,6 +278,27 @@ kp_status kp_destroy(kp_ctx *ctx);
 kp_status kp_autotune(const kp_problem *problems_host, int32_t count, void *workspace_dev,
                       size_t workspace_bytes, void *stream, int32_t iters, kp_tuning *best_host);
 
+/* Autotuner of the group counts.  The result of the method does not depend
+ * on g (the filters of Section 1 only skip distances that cannot change an
+ * assignment), so g is a speed parameter like the degree of parallelism of
+ * Section 1.  For each class of problems with the same (d, k, precision), in
+ * the order of first appearance, runs `iters` iterations (>= 2) of that
+ * class's problems from their initial centroids under each candidate:
+ * every problem's own g, ceil(k / 16) (the fewest groups that each fit one
+ * 16-slot tile of the BF16 distance kernels) and ceil(k / 10), each clipped
+ * to 1 .. k (and <= 1024 for BF16) -- with launch shapes `tuning_host` (NULL:
+ * defaults; timing and use_graph are overridden to 0 and 1), and writes each
+ * problem's fastest g to g_host[i] (count entries, caller-owned host
+ * memory).  A candidate whose class needs more than workspace_bytes of
+ * workspace is skipped; every problem's own g must fit.  The time of the
+ * first (dense) iteration is excluded, as in kp_autotune.  Synchronises
+ * `stream`; leaves no ctx behind; the workspace contents are undefined
+ * afterwards.  KP_ERR_INVALID for invalid problems or tuning, NULL g_host,
+ * iters < 2 or a workspace too small for the problems as given. */
+kp_status kp_autotune_groups(const kp_problem *problems_host, int32_t count, void *workspace_dev,
+                             size_t workspace_bytes, void *stream, int32_t iters, const kp_tuning *tuning_host,
+                             int32_t *g_host);
+
 /* ------------------------------------------------------------ diagnostics
  * Two read-only views of what the filtered iteration computes, for tests
  * that check the precision argument directly rather than through the final

@@ -1100,6 +1100,87 @@ kp_status kp_autotune(const kp_problem *problems, int32_t count, void *workspace
     return KP_OK;
 }
 
+kp_status kp_autotune_groups(const kp_problem *problems, int32_t count, void *workspace, size_t ws_bytes, void *stream,
+                             int32_t iters, const kp_tuning *tuning, int32_t *g_out)
+{
+    if (!g_out || iters < 2) {
+        set_error("NULL g_host or iters=%d < 2", iters);
+        return KP_ERR_INVALID;
+    }
+    if (!validate(problems, count, tuning)) return KP_ERR_INVALID;
+    if (kp_workspace_bytes(problems, count, tuning) > ws_bytes) {
+        set_error("workspace of %zu bytes is smaller than the problems need", ws_bytes);
+        return KP_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    kp_ctx *ctx = nullptr;   // for KP_HIP
+    KP_HIP(hipEventCreate(&e0));
+    std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> h0(e0, hipEventDestroy);
+    KP_HIP(hipEventCreate(&e1));
+    std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> h1(e1, hipEventDestroy);
+    kp_tuning t = tuning ? *tuning : kp_tuning{};
+    t.timing = 0;
+    t.use_graph = 1;
+    // classes of equal (d, k, precision), in order of first appearance
+    std::vector<std::vector<int>> classes;
+    for (int i = 0; i < count; ++i) {
+        bool placed = false;
+        for (auto &c : classes) {
+            const kp_problem &r = problems[c[0]];
+            if (r.d == problems[i].d && r.k == problems[i].k && r.precision == problems[i].precision) {
+                c.push_back(i);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) classes.push_back({i});
+    }
+    for (const auto &cls : classes) {
+        const kp_problem &r = problems[cls[0]];
+        const int gmax = r.precision == KP_PREC_BF16_RECHECK ? std::min(r.k, 1024) : r.k;
+        // candidate 0: every problem's own g; then the two rules
+        std::vector<int> cand = {0};
+        for (int div : {16, 10}) {
+            const int g = std::max(1, std::min(gmax, (r.k + div - 1) / div));
+            bool dup = true;   // the same run as candidate 0 when every problem has g already
+            for (int i : cls) dup = dup && problems[i].g == g;
+            for (size_t j = 1; j < cand.size(); ++j) dup = dup || cand[j] == g;
+            if (!dup) cand.push_back(g);
+        }
+        float best_ms = -1.f;
+        int best = 0;
+        for (int c : cand) {
+            std::vector<kp_problem> sub;
+            for (int i : cls) {
+                sub.push_back(problems[i]);
+                if (c > 0) sub.back().g = c;
+            }
+            if (kp_workspace_bytes(sub.data(), (int32_t)sub.size(), &t) > ws_bytes) continue;
+            kp_ctx *cx = nullptr;
+            kp_status st = kp_init(&cx, sub.data(), (int32_t)sub.size(), workspace, ws_bytes, stream, &t);
+            if (st != KP_OK) return st;
+            st = kp_iterate(cx, 1);   // the dense iteration and the graph capture, untimed
+            if (st == KP_OK && hipEventRecord(e0, s) != hipSuccess) st = KP_ERR_HIP;
+            if (st == KP_OK) st = kp_iterate(cx, iters - 1);
+            if (st == KP_OK && hipEventRecord(e1, s) != hipSuccess) st = KP_ERR_HIP;
+            float ms = 0.f;
+            if (st == KP_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = KP_ERR_HIP;
+            const kp_status sd = kp_destroy(cx);
+            if (st != KP_OK) return st;
+            if (sd != KP_OK) return sd;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        for (int i : cls) g_out[i] = best > 0 ? best : problems[i].g;
+    }
+    g_last_error.clear();
+    return KP_OK;
+}
+
 kp_status kp_destroy(kp_ctx *ctx)
 {
     if (!ctx) return KP_OK;

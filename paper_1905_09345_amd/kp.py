@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": KP_PREC_FP32, "bf16": KP_PREC_BF16_RECHECK, "bf16_recheck"
 
 # Every function kp.h declares; the CPU tests check that the library exports each.
 EXPORTS = ("kp_workspace_bytes", "kp_init", "kp_iterate", "kp_assign", "kp_centroids", "kp_stats",
-           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_predict_scratch_bytes", "kp_predict", "kp_predict_noalloc",
+           "kp_stage_times", "kp_iterations", "kp_destroy", "kp_autotune", "kp_autotune_groups", "kp_predict_scratch_bytes", "kp_predict", "kp_predict_noalloc",
            "kp_probe_estimates", "kp_bounds", "kp_strerror", "kp_last_error")
 
 
@@ -89,6 +89,9 @@ def lib():
         L.kp_destroy.restype = ctypes.c_int
         L.kp_autotune.argtypes = [P(kp_problem), ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_int32, P(kp_tuning)]
         L.kp_autotune.restype = ctypes.c_int
+        L.kp_autotune_groups.argtypes = [P(kp_problem), ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.c_int32,
+                                         P(kp_tuning), P(ctypes.c_int32)]
+        L.kp_autotune_groups.restype = ctypes.c_int
         L.kp_predict_scratch_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
         L.kp_predict_scratch_bytes.restype = ctypes.c_size_t
         L.kp_predict.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t]
@@ -187,6 +190,16 @@ def kp_autotune(problems, workspace_ptr, workspace_bytes, stream=0, iters=4):
     return best
 
 
+def kp_autotune_groups(problems, workspace_ptr, workspace_bytes, stream=0, iters=4, tuning=None):
+    """Returns the fastest g of each problem (see kp.h)."""
+    arr, n = _probs(problems)
+    out = (ctypes.c_int32 * max(n, 1))()
+    tp = ctypes.byref(tuning) if tuning is not None else None
+    _check(lib().kp_autotune_groups(arr, n, ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream),
+                                    int(iters), tp, out), "kp_autotune_groups")
+    return [int(v) for v in out[:n]]
+
+
 KP_PREDICT_NOALLOC_MAX_QUERIES = 1 << 22
 
 
@@ -275,6 +288,26 @@ class KMeans:
         best = kp_autotune(descs, ws.data_ptr(), nbytes, stream, iters)
         del ws
         return best
+
+    @staticmethod
+    def autotune_groups(problems, iters=4, tuning=None):
+        """Group count per problem from kp_autotune_groups (same problem tuples
+        as the constructor; each problem's own g is one of the candidates)."""
+        import torch
+        descs, keep = [], []
+        for pr in problems:
+            X, C0, g = pr[0], pr[1], int(pr[2])
+            prec = PRECISIONS[pr[3]] if len(pr) > 3 else KP_PREC_FP32
+            seed = int(pr[4]) if len(pr) > 4 else 0
+            keep += [X, C0]
+            descs.append(kp_problem(n=X.shape[0], d=X.shape[1], k=C0.shape[0], g=g, precision=prec,
+                                    points_dev=X.data_ptr(), init_centroids_dev=C0.data_ptr(), seed=seed))
+        nbytes = kp_workspace_bytes(descs, tuning)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=problems[0][0].device)
+        stream = torch.cuda.current_stream(problems[0][0].device).cuda_stream
+        gs = kp_autotune_groups(descs, ws.data_ptr(), nbytes, stream, iters, tuning)
+        del ws
+        return gs
 
     def iterate(self, iters=1):
         kp_iterate(self.ctx, iters)

@@ -134,6 +134,17 @@ def test_strerror():
     assert kp.kp_strerror(99) == "unknown status"
 
 
+def test_autotune_groups_argument_errors():
+    lib = kp.lib()
+    arr, n = kp._probs([_prob()])
+    gs = (ctypes.c_int32 * 1)()
+    assert lib.kp_autotune_groups(arr, n, None, 0, None, 4, None, None) == kp.KP_ERR_INVALID       # no output
+    assert lib.kp_autotune_groups(arr, n, None, 0, None, 1, None, gs) == kp.KP_ERR_INVALID         # iters < 2
+    assert lib.kp_autotune_groups(arr, 0, None, 0, None, 4, None, gs) == kp.KP_ERR_INVALID         # no problems
+    assert lib.kp_autotune_groups(arr, n, None, 16, None, 4, None, gs) == kp.KP_ERR_INVALID        # workspace too small
+    assert b"smaller" in lib.kp_last_error()
+
+
 def test_autotune_argument_errors():
     lib = kp.lib()
     arr, n = kp._probs([_prob()])

@@ -80,6 +80,32 @@ def test_autotune_then_run():
     run_steplocked_batch(probs, 5, tuning=best)
 
 
+def test_autotune_groups_then_run():
+    """kp_autotune_groups gives every problem of a (d, k, precision) class the
+    same g, one of its candidates (the problem's own g, ceil(k/16), ceil(k/10));
+    the batch then runs with those group counts and matches the oracle."""
+    import torch
+    from paper_1905_09345_amd import KMeans
+    from paper_1905_09345_amd.kp import kp_tuning
+    specs = [(11, 6_000, 32, 64, "bf16"), (12, 9_000, 32, 64, "bf16"), (13, 12_000, 64, 256, "bf16"),
+             (14, 5_000, 16, 16, "bf16"), (15, 7_000, 32, 48, "fp32"), (16, 4_000, 32, 48, "fp32")]
+    probs = [_problem(*sp) for sp in specs]
+    probs[1] = probs[1][:2] + (3,) + probs[1][3:]   # an own g that differs within its class
+    dev = [(torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda(), g, prec) for X, C0, g, prec in probs]
+    print("CASE autotune-groups", flush=True)
+    tun = kp_tuning(bound_codes=2, blocks_per_cu=16, chunk_depth=1)
+    gs = KMeans.autotune_groups(dev, iters=3, tuning=tun)
+    assert len(gs) == len(probs)
+    for (X, C0, g, prec), gt, sp in zip(probs, gs, specs):
+        k = C0.shape[0]
+        assert gt in (g, max(1, math.ceil(k / 16)), math.ceil(k / 10)), (sp, g, gt)
+    for a, b in ((0, 1), (4, 5)):   # one g per class, unless each kept its own
+        own = gs[a] == probs[a][2] and gs[b] == probs[b][2]
+        assert gs[a] == gs[b] or own
+    tuned = [(X, C0, gt, prec) for (X, C0, _, prec), gt in zip(probs, gs)]
+    run_steplocked_batch(tuned, 5, tuning=tun)
+
+
 def test_batch_whole_call_graph():
     """A batch iterated with use_graph = 2: the calls' iterations run as one
     graph each (the last call replays the previous one's); the final step is
