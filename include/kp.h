@@ -125,6 +125,16 @@ typedef struct {
                                       bit for bit.  0 (default): incremental
                                       sums over the moved points with FP64
                                       atomic adds, whose order varies */
+    int32_t local_filter;          /* FP32 problems: 1 = the per-centroid local
+                                      filter inside each open group (a member
+                                      is skipped when its group's bound, raised
+                                      by how much less than the group's largest
+                                      drift it moved, exceeds ub for every
+                                      point of the 64-point tile that visits
+                                      the group).  0 (default): every member of
+                                      an open group is computed, which keeps
+                                      the group bounds exact and, on the
+                                      workloads measured, is faster overall */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */

@@ -39,7 +39,7 @@ inline size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of one problem's arrays inside the workspace.
 struct Plan {
     size_t xn, st, lb, c32, cb, cbl, cn, c64, sums, delta, cnt, perm, sgrp, gstart, gsize;
-    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, nrel, Wu, Qt, Wa, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
+    size_t Sc, Sg, Sd, Scu, Scd, Sgu, Sgd, slk, nrel, Wu, Qt, Wa, Sdud, L1, L1s, L1x, L3, minnc, tlist, tcnt, ps4, psf, mvp, mvo, mvn, srtp, srtk, hist, cursor, hist1,
         cursor1, ctr, rowt, rclosed, stats, iter, sink, lbsc, dcnt, doff, hist2, spart, pfirst, plast;
     size_t bytes;
     int kgmax, ldc, ldb, gs;
@@ -94,6 +94,7 @@ Plan plan_problem(const kp_problem &p, bool lb16, bool det)
     o.Scd = take(kgm * 4);
     o.Sgu = take((size_t)g * 4);
     o.Sgd = take((size_t)g * 4);
+    o.slk = take(kgm * 4);
     // BF16 mode: relative norms and per-chunk bounds of the chunk rows; with
     // anchors, the slot-to-slot table of squared distances and the
     // per-(anchor, chunk) bounds (kgmax <= ANCHOR_MAX_SLOTS keeps them <= 1 GiB)
@@ -199,6 +200,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
         }
         if (t->deterministic < 0 || t->deterministic > 1) {
             set_error("deterministic=%d outside 0..1", t->deterministic);
+            return false;
+        }
+        if (t->local_filter < 0 || t->local_filter > 1) {
+            set_error("local_filter=%d outside 0..1", t->local_filter);
             return false;
         }
     }
@@ -528,6 +533,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.Scd = (float *)(base + o.Scd);
         P.Sgu = (float *)(base + o.Sgu);
         P.Sgd = (float *)(base + o.Sgd);
+        P.slk = (float *)(base + o.slk);
         P.nch = G.kg / kp::CHUNK;
         P.nrel = (float *)(base + o.nrel);
         P.Wu = (float2 *)(base + o.Wu);
@@ -560,6 +566,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         P.iter = (int *)(base + o.iter);
         P.sink = (float *)(base + o.sink);
         P.det = det ? 1 : 0;
+        P.lf = (tuning && tuning->local_filter == 1 && p.precision == KP_PREC_FP32) ? 1 : 0;
         P.nb_l1 = bits_for(P.nk1 - 1);
         P.nb_slot = bits_for(P.kg - 1);
         P.dcnt = (int *)(base + o.dcnt);

@@ -92,6 +92,8 @@ struct ProbDev {
     double *Sc, *Sg, *Sd;     // cumulative drifts (kg, g, 1), FP64
     float *Scu, *Scd;         // FP32 copies of Sc rounded up / down
     float *Sgu, *Sgd;         // FP32 copies of Sg rounded up / down
+    float *slk;               // per slot: its group's largest drift in the last update minus its own
+                              // drift, rounded down (0 before the first update and for padding)
     int nch;                  // 16-slot chunks: kg / CHUNK (every group is padded to whole chunks)
     float *nrel;              // per slot j: ||fl(c_j - c_f)|| rounded up, f the first slot of j's chunk (0 for f)
     float2 *Wu;               // per chunk: (W, c W^2) of the estimate without an anchor, W >= ||c_f||
@@ -123,6 +125,7 @@ struct ProbDev {
     float *sink;              // SINK_SLOTS x 16 floats, written and never read
     // deterministic mode (kp_tuning.deterministic): fixed-order lists and sums
     int det;                  // 1: the list of point-filter failures and the centroid sums in a fixed order
+    int lf;                   // FP32 problems: 1 = the per-centroid local filter in the tile kernel
     int nb_l1, nb_slot;       // bits of the largest L1 key (nk1 - 1) and slot (kg - 1)
     int *dcnt, *doff;         // per chunk of BF_CHUNK points: failures, their first position in L1
     int *hist2;               // (key, block) counts of the stable counting sorts, then their cursors

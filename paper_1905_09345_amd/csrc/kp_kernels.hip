@@ -232,6 +232,8 @@ __device__ __forceinline__ void b_drift(const ProbDev &P, const int bid_, const 
         double m = 0.0;
         const int s0 = P.gstart[g], ns = P.gsize[g];
         for (int r = 0; r < ns; ++r) m = fmax(m, P.delta[s0 + r]);
+        // per member: how much less than the group's largest drift it moved
+        for (int r = 0; r < ns; ++r) P.slk[s0 + r] = first ? 0.f : d2f_dn(fmax(m - P.delta[s0 + r], 0.0));
         const double sg = first ? 0.0 : (P.Sg[g] + m) * up;
         P.Sg[g] = sg;
         P.Sgu[g] = d2f_up(sg);
@@ -864,10 +866,12 @@ __device__ __forceinline__ bool before(const ProbDev &P, float v, int sa, float 
 // nearest other group, kept for the order of the next iteration's L1).
 struct Run {
     float bd, sec, bm2, ov;
+    float lk;   // smallest lower bound (a distance) of the centroids the local filter skipped
     int bs, bg, og;
 };
 __device__ __forceinline__ void run_init(Run &r)
 {
+    r.lk = KP_INF;
     r.bd = KP_INF;
     r.sec = KP_INF;
     r.bm2 = KP_INF;
@@ -934,7 +938,7 @@ __device__ __forceinline__ bool finish_f32(const ProbDev &P, int pid, bool dense
 {
     float *lbrow = P.lb + (size_t)pid * P.gs;
     if (r.bg >= 0) lbrow[r.bg] = store_lb(dist_lo(r.bm2, eps2), P.Sgd[r.bg]);
-    float lbp = fminf(dist_lo(r.sec, eps2), minnc);
+    float lbp = fminf(fminf(dist_lo(r.sec, eps2), minnc), r.lk);
     if (!dense && a_sep && r.bs != a) {
         const float va = fminf(lbe_a, dist_lo(d2a, eps2));
         lbrow[ga] = store_lb(va, P.Sgd[ga]);
@@ -1620,13 +1624,13 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
 {
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // the tile and its visits are uniform
     const double eps2 = eps2_direct(P.d);
     const float sdd = P.Sdud[1];
     const long long count = list_len(P, CTR_L1);
     const long long ntiles = (count + WAVE - 1) / WAVE;
     unsigned long long n_dist = 0, n_moved = 0;
-    for (long long tl = (long long)bid_ * wpb + threadIdx.x / WAVE; tl < ntiles;
-         tl += (long long)nblk_ * wpb) {
+    for (long long tl = (long long)bid_ * wpb + wv; tl < ntiles; tl += (long long)nblk_ * wpb) {
         const long long idx = tl * WAVE + lane;
         const bool in = idx < count;
         const int flags = in ? P.psf[idx] : 0;
@@ -1635,6 +1639,7 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
         const int pid = in ? clamp_pid(P, P.L1s[idx]) : 0;
         const float4 q = in ? P.ps4[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
         const float d2a = q.w, lbe_a = q.z, minnc = q.y;
+        const float ubt = q.x;   // ub brought to this iteration
         const int a = act ? clamp_slot(P, P.st[pid].a) : 0;
         const int ga = P.slot_group[a];
         float x[DMAX];
@@ -1646,17 +1651,64 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
             r.bd = d2a;
             r.bs = a;
         }
+        float *lbrow = P.lb + (size_t)pid * P.gs;
         const int cnt = min(max(P.tcnt[tl], 0), P.g);
         const int4 *lst = P.tlist + (size_t)tl * P.g;
-        for (int k = 0; k < cnt; ++k) {
+        // each visit's bound of this lane's point is loaded one visit ahead
+        auto vis_of = [&](int k, unsigned long long &m) {
             int4 e = lst[k];
             e.x = min(max(e.x, 0), P.g - 1);
-            const unsigned long long m = (unsigned long long)(unsigned)e.y | ((unsigned long long)(unsigned)e.z << 32);
-            const Best3 gb = direct_group<DMAX>(P, e.x, x);
-            n_dist += (unsigned long long)__popcll(m) * (unsigned long long)P.gsize[e.x];
-            if ((m >> lane) & 1ull) {
-                P.lb[(size_t)pid * P.gs + e.x] = store_lb(dist_lo(gb.m1, eps2), P.Sgd[e.x]);
-                run_fold(P, r, gb, e.x);
+            m = (unsigned long long)(unsigned)e.y | ((unsigned long long)(unsigned)e.z << 32);
+            return e.x;
+        };
+        const bool lf = P.lf != 0;
+        unsigned long long mn = 0ull;
+        int gn = cnt > 0 ? vis_of(0, mn) : 0;
+        float vn = (lf && cnt > 0 && ((mn >> lane) & 1ull)) ? lbrow[gn] : 0.f;
+        for (int k = 0; k < cnt; ++k) {
+            const int g = gn;
+            const unsigned long long m = mn;
+            const float vrow = vn;
+            if (k + 1 < cnt) {
+                gn = vis_of(k + 1, mn);
+                vn = (lf && ((mn >> lane) & 1ull)) ? lbrow[gn] : 0.f;
+            }
+            const bool mine = (m >> lane) & 1ull;
+            // Local filter (kp_tuning.local_filter): member j of g lies at
+            // least lb(x, g) brought forward plus slk[j] from x (the bound
+            // moved by g's largest drift, the member by its own); it is
+            // skipped when that exceeds ub for every point of the wave that
+            // visits g, and is never a visiting point's own centroid.  Skipped
+            // members enter the group's bound and lbp with that lower bound,
+            // never the search for the nearest.
+            const float lbn = (mine && lf) ? lb_now(vrow, P.Sgu[g]) : 0.f;
+            Best3 gb = {KP_INF, -1, KP_INF};
+            float lk = KP_INF;
+            const int s0 = P.gstart[g], ns = P.gsize[g];
+            int ncomp = 0;
+            for (int rr = 0; rr < ns; ++rr) {
+                const int j = s0 + rr;
+                const float L = lf ? f_dn(lbn + P.slk[j]) : 0.f;
+                if (lf && __ballot(mine && !(j != a && L > ubt)) == 0ull) {
+                    lk = fminf(lk, L);
+                    continue;
+                }
+                ++ncomp;
+                const float v = direct_d2<DMAX>(x, P.c32 + (size_t)j * P.ldc, P.ldc);
+                if (v < gb.m1) {
+                    gb.m2 = gb.m1;
+                    gb.m1 = v;
+                    gb.s1 = j;
+                } else {
+                    gb.m2 = fminf(gb.m2, v);
+                }
+            }
+            n_dist += (unsigned long long)__popcll(m) * (unsigned long long)ncomp;
+            if (mine) {
+                gb.m2 = fminf(gb.m2, lk < KP_INF ? f_dn(lk * lk) : KP_INF);   // squared, rounded down
+                lbrow[g] = store_lb(fminf(dist_lo(gb.m1, eps2), lk), P.Sgd[g]);
+                run_fold(P, r, gb, g);
+                r.lk = fminf(r.lk, lk);
             }
         }
         bool moved = false;

@@ -92,7 +92,8 @@ static void check_abi()
     } badt[] = {{&kp_tuning::waves_per_block, 5},  {&kp_tuning::waves_per_block, -1}, {&kp_tuning::blocks_per_cu, 65},
                 {&kp_tuning::chunk_depth, 2},      {&kp_tuning::bound_codes, 3},      {&kp_tuning::use_graph, 3},
                 {&kp_tuning::timing, 2},           {&kp_tuning::timing_stages, -1},   {&kp_tuning::timing_stages, 1 << 9},
-                {&kp_tuning::deterministic, 2},    {&kp_tuning::deterministic, -1}};
+                {&kp_tuning::deterministic, 2},    {&kp_tuning::deterministic, -1},   {&kp_tuning::local_filter, 2},
+                {&kp_tuning::local_filter, -1}};
     for (const Field &b : badt) {
         kp_tuning t;
         std::memset(&t, 0, sizeof t);

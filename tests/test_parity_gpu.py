@@ -76,6 +76,34 @@ def test_row_test_in_point_filter(prec):
     assert on and sum(s["closed"] for s in on) > 0, [(s["iter"], s["closed"]) for s in st]
 
 
+@pytest.mark.parametrize("case", ["c1", "c2", "groups1", "groups30", "ties"])
+def test_fp32_local_filter(case):
+    """The FP32 form with the per-centroid local filter on: step-locked with
+    the oracle, and it computes fewer distances than the surviving pairs'
+    groups hold."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    t = kp_tuning(local_filter=1)
+    if case in ("c1", "c2"):
+        P = datagen.make_config(int(case[1]), n=None if case == "c1" else 60_007)
+        X, C0, g, iters = P.X, P.C0, P.g, (P.iters if case == "c1" else 12)
+    elif case == "ties":
+        gr = np.arange(-4, 5, dtype=np.float32)
+        X = np.concatenate([np.stack(np.meshgrid(gr, gr, gr), axis=-1).reshape(-1, 3)] * 3).astype(np.float32)
+        C0 = np.array([[0.5, 0, 0], [-0.5, 0, 0], [0, 0.5, 0], [0, -0.5, 0], [2, 2, 2], [2, 2, 2],
+                       [100, 100, 100], [-3, -3, 3]], np.float32)
+        g, iters = 3, 5
+    else:
+        rng = np.random.default_rng(7)
+        X = datagen.gaussian_mixture(rng, 5_000, 24, 30)
+        C0 = datagen.kmeanspp(rng, X, 30)
+        g, iters = (1 if case == "groups1" else 30), 8
+    _print_case("fp32-local-filter", case=case)
+    r = run_steplocked(X, C0, g, "fp32", iters, tuning=t)
+    if case in ("c1", "c2"):
+        st = [s for s in r["stats"] if not s["dense"]]
+        assert sum(s["distances"] for s in st) < sum(s["pairs"] for s in st) * (C0.shape[0] / g)
+
+
 @pytest.mark.parametrize("d", [16, 32, 64])
 def test_bf16_small_dims(d):
     rng = np.random.default_rng(d)
