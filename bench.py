@@ -338,7 +338,9 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
     torch.cuda.empty_cache()
     baseline = None
     if not args.no_baseline:
-        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=3)
+        # small problems are launch-bound: time more iterations after more warmup
+        small = P.n * P.k < 1 << 26
+        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=30 if small else 3, warmup=5 if small else 1)
         baseline = dict(value=P.n / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
                         impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration")
         log("plain FP32 Lloyd: %.3f ms/iteration" % (sec * 1e3))
