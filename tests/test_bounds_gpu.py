@@ -92,13 +92,17 @@ def test_bounds_c5_shape():
     _run(P.X, P.C0, P.g, "bf16", 6, 1024)
 
 
+@pytest.mark.parametrize("lf", [0, 1])
 @pytest.mark.parametrize("g", [1, 3, 40])
-def test_bounds_fp32(g):
+def test_bounds_fp32(g, lf):
+    """FP32 form, with and without the local filter (whose skipped members
+    enter the group bounds and lbp with a lower bound instead of a distance)."""
+    from paper_1905_09345_amd.kp import kp_tuning
     rng = np.random.default_rng(g)
     X = datagen.gaussian_mixture(rng, 20_000, 24, 40)
     C0 = datagen.kmeanspp(rng, X, 40)
-    print("CASE bounds-fp32", g, flush=True)
-    _run(X, C0, g, "fp32", 10, 2048)
+    print("CASE bounds-fp32", g, lf, flush=True)
+    _run(X, C0, g, "fp32", 14, 2048, tuning=kp_tuning(local_filter=lf))
 
 
 def test_bounds_full_c3_sampled():
