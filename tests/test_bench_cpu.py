@@ -91,3 +91,20 @@ def test_batched_plain_lloyd_matches_per_problem_lloyd(monkeypatch):
         return C
     for X, C, Cb in zip(Xs, Cs, out):
         assert torch.allclose(lloyd(X, C, 3), Cb, rtol=1e-5, atol=1e-5)
+
+
+def test_fp32_filtered_roofline_counts_direct_form_work():
+    """The FP32 form's filtered stage is priced at 3d operations per distance
+    computed against the FP32 vector peak, with its HBM bytes beside it."""
+    import types
+    import bench
+    P = types.SimpleNamespace(precision="fp32", d=32, g=26, k=256, n=10 ** 6, meta={"name": "w"})
+    st = [dict(dense=1, point_filter_fail=0, pairs=0, distances=0),
+          dict(dense=0, point_filter_fail=1000, pairs=3000, distances=20000),
+          dict(dense=0, point_filter_fail=3000, pairs=5000, distances=40000)]
+    r = bench.roofline_of("assign", dict(ms=2.0, launches=2), P, st)   # 1 ms per launch
+    ops = 3 * 32 * 30000
+    assert r["bound"] == "alu" and abs(r["achieved"] - ops / 1e-3 / 1e12) < 1e-12
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-15
+    byts = 2000 * (4 * 32 + 48) + 4000 * 8
+    assert abs(r["hbm"]["achieved"] - byts / 1e-3 / 1e9) < 1e-9
