@@ -773,16 +773,31 @@ __global__ __launch_bounds__(256) void kb_l1_scatter(const ProbDev *__restrict__
 template <int DMAX>
 __device__ __forceinline__ float direct_d2(const float (&x)[DMAX], const float *__restrict__ c, int ldc)
 {
+    // Blocks of up to 32 coordinates: every load of a block is issued before
+    // the first product (addresses past ldc are clamped into the row and their
+    // terms are exact zeros), so a row costs one memory latency per block.
+    constexpr int B = DMAX < 32 ? DMAX : 32;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
-    for (int i = 0; i < DMAX; i += 4) {
-        if (i < ldc) {
-            const float4 cv = *(const float4 *)(c + i);
-            const float t0 = x[i] - cv.x, t1 = x[i + 1] - cv.y, t2 = x[i + 2] - cv.z, t3 = x[i + 3] - cv.w;
-            a0 = fmaf(t0, t0, a0);
-            a1 = fmaf(t1, t1, a1);
-            a2 = fmaf(t2, t2, a2);
-            a3 = fmaf(t3, t3, a3);
+    for (int i0 = 0; i0 < DMAX; i0 += B) {
+        if (i0 < ldc) {
+            float4 cv[B / 4];
+#pragma unroll
+            for (int q = 0; q < B / 4; ++q) {
+                const int i = i0 + 4 * q;
+                cv[q] = *(const float4 *)(c + (i < ldc ? i : i0));
+            }
+#pragma unroll
+            for (int q = 0; q < B / 4; ++q) {
+                const int i = i0 + 4 * q;
+                const bool in = i < ldc;
+                const float t0 = in ? x[i] - cv[q].x : 0.f, t1 = in ? x[i + 1] - cv[q].y : 0.f;
+                const float t2 = in ? x[i + 2] - cv[q].z : 0.f, t3 = in ? x[i + 3] - cv[q].w : 0.f;
+                a0 = fmaf(t0, t0, a0);
+                a1 = fmaf(t1, t1, a1);
+                a2 = fmaf(t2, t2, a2);
+                a3 = fmaf(t3, t3, a3);
+            }
         }
     }
     return (a0 + a1) + (a2 + a3);
