@@ -621,7 +621,8 @@ def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extr
         ms = timed[dom]["ms"] / max(timed[dom]["launches"], 1e-9)   # timed inside the timed region
         ach = byts / (ms * 1e-3) / 1e9
         roofline = dict(kernel="kb_blk64 (filtered iteration, all problems)", bound="hbm", achieved=ach,
-                        peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                        traffic=traffic_of("kb_blk64_filtered", datagen.CONFIGS[4]["name"]),
                         work_per_launch="%.4g B" % byts, ms_per_launch=ms)
     else:
         roofline = dict(kernel=dom, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None,
