@@ -753,7 +753,8 @@ def roofline_of(stage, a, P, st):
         ach = ops / (ms_per_launch * 1e-3) / 1e12
         peak = 78.6
         return dict(kernel="k_group_test + k_tile_f32 (filtered iteration, FP32 direct form)", bound="alu",
-                    achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None,
+                    achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                    traffic=traffic_of("fp32_filtered", wl),
                     work_per_launch="3*d per distance computed = %.4g FP32 operations" % ops,
                     ms_per_launch=ms_per_launch,
                     hbm=dict(achieved=byts / (ms_per_launch * 1e-3) / 1e9, unit="GB/s",
