@@ -744,12 +744,12 @@ def roofline_of(stage, a, P, st):
         # FP32 form: the group test and the direct-form tile kernel.  Work:
         # 3d FP32 operations (subtract, multiply, add) per distance computed,
         # against the vector FMA peak without packed instructions; the HBM
-        # bytes (row, state and entries per L1 entry, a bound per open pair)
-        # are given beside it.
+        # bytes (point row, bound row, state and entries per L1 entry, a bound
+        # per open pair) are given beside it.
         filt = [s for s in st if not s["dense"]]
         ops = sum(3.0 * P.d * s["distances"] for s in filt) / max(len(filt), 1)
-        byts = sum(s["point_filter_fail"] * (4 * P.d + 16 + 4 + 16 + 12) + s["pairs"] * 8 for s in filt) / max(
-            len(filt), 1)
+        byts = sum(s["point_filter_fail"] * (4 * P.d + 4 * P.g + 16 + 4 + 16 + 12) + s["pairs"] * 8
+                   for s in filt) / max(len(filt), 1)
         ach = ops / (ms_per_launch * 1e-3) / 1e12
         peak = 78.6
         return dict(kernel="k_group_test + k_tile_f32 (filtered iteration, FP32 direct form)", bound="alu",
@@ -759,7 +759,7 @@ def roofline_of(stage, a, P, st):
                     ms_per_launch=ms_per_launch,
                     hbm=dict(achieved=byts / (ms_per_launch * 1e-3) / 1e9, unit="GB/s",
                              frac=byts / (ms_per_launch * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                             work_per_launch="%.4g B (per L1 entry 4d+48 B, per open pair 8 B)" % byts))
+                             work_per_launch="%.4g B (per L1 entry 4d+4g+48 B, per open pair 8 B)" % byts))
     if stage == "assign_dense":
         flops = 2.0 * P.n * P.k * P.d
         ach = flops / (ms_per_launch * 1e-3) / 1e12

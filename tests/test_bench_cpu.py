@@ -106,5 +106,5 @@ def test_fp32_filtered_roofline_counts_direct_form_work():
     ops = 3 * 32 * 30000
     assert r["bound"] == "alu" and abs(r["achieved"] - ops / 1e-3 / 1e12) < 1e-12
     assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-15
-    byts = 2000 * (4 * 32 + 48) + 4000 * 8
+    byts = 2000 * (4 * 32 + 4 * 26 + 48) + 4000 * 8
     assert abs(r["hbm"]["achieved"] - byts / 1e-3 / 1e9) < 1e-9
