@@ -139,6 +139,27 @@ def plain_fp32_lloyd_batched(torch, Xs, Cs, iters, warmup=1, rows=1 << 13, centr
     return sec
 
 
+def plain_fp32_kernels(torch, KMeans, kp_tuning, spec, iters, warmup=1):
+    """Plain FP32 Lloyd with this library's hand-written kernels
+    (kp_tuning.plain: the FP32 direct-form dense pass and a full centroid
+    recompute in every iteration, no filtering) on the same problems; returns
+    seconds per iteration, or None where the FP32 form does not apply
+    (d > 128)."""
+    if any(sp[0].shape[1] > 128 for sp in spec):
+        return None
+    fp = [(sp[0], sp[1], sp[2], "fp32") for sp in spec]
+    km = KMeans(fp, tuning=kp_tuning(plain=1))
+    try:
+        km.iterate(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        km.iterate(iters)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / iters
+    finally:
+        km.close()
+
+
 def plain_fp32_lloyd(torch, Xd, C0d, iters, warmup=1, chunk=1 << 19):
     """Dense FP32 Lloyd with torch on the same GPU; returns seconds per iteration."""
     torch.backends.cuda.matmul.allow_tf32 = False
@@ -340,10 +361,18 @@ def measure_single(args, torch, datagen, KMeans, kp_tuning, config, steps, warmu
     if not args.no_baseline:
         # small problems are launch-bound: time more iterations after more warmup
         small = P.n * P.k < 1 << 26
-        sec = plain_fp32_lloyd(torch, Xd, C0d, iters=30 if small else 3, warmup=5 if small else 1)
+        sec_t = plain_fp32_lloyd(torch, Xd, C0d, iters=30 if small else 3, warmup=5 if small else 1)
+        sec_k = plain_fp32_kernels(torch, KMeans, kp_tuning, spec, iters=30 if small else 3,
+                                   warmup=5 if small else 1)
+        sec = min(sec_t, sec_k) if sec_k else sec_t
         baseline = dict(value=P.n / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
-                        impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration")
-        log("plain FP32 Lloyd: %.3f ms/iteration" % (sec * 1e3))
+                        ms_per_iteration_torch=sec_t * 1e3,
+                        ms_per_iteration_hand_written=sec_k * 1e3 if sec_k else None,
+                        impl="the faster of torch FP32 GEMM (TF32 off) + argmin + index_add and this library's "
+                             "FP32 direct-form kernels (kp_tuning.plain; d <= 128), every iteration dense, "
+                             "full centroid recompute")
+        log("plain FP32 Lloyd: %.3f ms/iteration (torch %.3f, hand-written %s)" % (
+            sec * 1e3, sec_t * 1e3, "%.3f" % (sec_k * 1e3) if sec_k else "n/a (d > 128)"))
     del Xd, C0d
     torch.cuda.empty_cache()
     cpu, precision = (None, None) if args.no_cpu else cpu_baseline(P, args.cpu_seconds if extras else
@@ -645,13 +674,17 @@ def measure_batched(args, torch, datagen, KMeans, kp_tuning, steps, warmup, extr
         # problems of each (D, K) class padded and batched
         sec_seq = sum(plain_fp32_lloyd(torch, Xd[i], Cd[i], iters=2, warmup=1) for i in range(len(probs)))
         sec_bat = plain_fp32_lloyd_batched(torch, Xd, Cd, iters=3, warmup=1)
-        sec = min(sec_seq, sec_bat)
+        sec_k = plain_fp32_kernels(torch, KMeans, kp_tuning, spec, iters=3, warmup=1)
+        sec = min(x for x in (sec_seq, sec_bat, sec_k) if x)
         baseline = dict(value=ntot / sec, unit="point-iterations/s", ms_per_iteration=sec * 1e3,
                         ms_per_iteration_per_problem=sec_seq * 1e3, ms_per_iteration_batched=sec_bat * 1e3,
-                        impl="torch FP32 GEMM (TF32 off) + argmin + index_add, dense every iteration: the faster of "
-                             "per-problem calls and per-(D, K)-class batched calls over 8192-point tiles")
-        log("plain FP32 Lloyd: %.3f ms per iteration of all problems (%.3f one problem at a time, %.3f batched by class)"
-            % (sec * 1e3, sec_seq * 1e3, sec_bat * 1e3))
+                        ms_per_iteration_hand_written=sec_k * 1e3 if sec_k else None,
+                        impl="the fastest of torch FP32 GEMM (TF32 off) + argmin + index_add per problem, the same "
+                             "batched per (D, K) class over 8192-point tiles, and this library's FP32 direct-form "
+                             "kernels on the whole batch (kp_tuning.plain); every iteration dense, full centroid "
+                             "recompute")
+        log("plain FP32 Lloyd: %.3f ms per iteration of all problems (%.3f one problem at a time, %.3f batched by class, "
+            "%s hand-written)" % (sec * 1e3, sec_seq * 1e3, sec_bat * 1e3, "%.3f" % (sec_k * 1e3) if sec_k else "n/a"))
     del Xd, Cd, spec
     torch.cuda.empty_cache()
     cpu = precision = None

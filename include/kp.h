@@ -135,6 +135,14 @@ typedef struct {
                                       an open group is computed, which keeps
                                       the group bounds exact and, on the
                                       workloads measured, is faster overall */
+    int32_t plain;                 /* 1: plain Lloyd, the comparator of the
+                                      filtered method: every iteration
+                                      computes every distance (the dense pass
+                                      of the first iteration, with plain
+                                      launches) and recomputes the centroid
+                                      sums from all points; no filter skips
+                                      anything.  0 (default): the filtered
+                                      iterations of Section 1 */
 } kp_tuning;
 
 /* Per-iteration counters of one problem (kp_stats). */

@@ -206,6 +206,10 @@ bool validate(const kp_problem *ps, int32_t count, const kp_tuning *t)
             set_error("local_filter=%d outside 0..1", t->local_filter);
             return false;
         }
+        if (t->plain < 0 || t->plain > 1) {
+            set_error("plain=%d outside 0..1", t->plain);
+            return false;
+        }
     }
     for (int i = 0; i < count; ++i) {
         const kp_problem &p = ps[i];
@@ -363,6 +367,7 @@ struct kp_ctx {
     kp::Batch batch;                           // count > 1: batched launches
     kp::LaunchCfg cfg{4, 4096, 1, false};
     int use_graph = 1;
+    int plain = 0;   // plain Lloyd: a dense pass in every iteration
     int iters = 0;
     bool poisoned = false;
     hipGraph_t graph = nullptr;
@@ -476,6 +481,7 @@ kp_status kp_init(kp_ctx **out, const kp_problem *problems, int32_t count, void 
         ctx->cfg.lb16 = tuning->bound_codes == 2;
         if (tuning->use_graph) ctx->use_graph = tuning->use_graph > 0 ? tuning->use_graph : 0;
         ctx->timing = tuning->timing;
+        ctx->plain = tuning->plain;
         if (tuning->timing_stages) ctx->timed_stages = (unsigned)tuning->timing_stages;
     }
     KP_HIP(hipGetDevice(&ctx->device));
@@ -786,6 +792,24 @@ kp_status kp_iterate(kp_ctx *ctx, int32_t iters)
     }
     KP_HIP(hipEventRecord(ctx->ev_in, ctx->user));
     KP_HIP(hipStreamWaitEvent(ctx->own, ctx->ev_in, 0));
+    if (ctx->plain) {
+        // plain Lloyd: each iteration is the dense pass, whose update adds
+        // every point to sums started from zero (cleared here on the ctx's
+        // stream; this path is never captured into a graph)
+        for (int i = 0; i < iters; ++i) {
+            if (ctx->iters > 0)
+                for (int p = 0; p < ctx->count; ++p) {
+                    const kp::ProbDev &P = ctx->P[p];
+                    KP_HIP(hipMemsetAsync(P.sums, 0, (size_t)P.kg * P.d * sizeof(double), ctx->own));
+                    KP_HIP(hipMemsetAsync(P.cnt, 0, (size_t)P.kg * sizeof(int), ctx->own));
+                }
+            KP_HIP(launch_all(ctx, true));
+            ++ctx->iters;
+        }
+        KP_HIP(hipEventRecord(ctx->ev_out, ctx->own));
+        KP_HIP(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+        return KP_OK;
+    }
     if (ctx->use_graph == 2) {
         const bool dense_first = ctx->iters == 0;
         if (!ctx->rexec || ctx->run_iters != iters || ctx->run_dense != dense_first)

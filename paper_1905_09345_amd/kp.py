@@ -33,7 +33,7 @@ class kp_tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32), ("chunk_depth", ctypes.c_int32),
                 ("bound_codes", ctypes.c_int32), ("timing_stages", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("local_filter", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("local_filter", ctypes.c_int32), ("plain", ctypes.c_int32)]
 
 
 # stage indices of kp_tuning.timing_stages

@@ -93,7 +93,7 @@ static void check_abi()
                 {&kp_tuning::chunk_depth, 2},      {&kp_tuning::bound_codes, 3},      {&kp_tuning::use_graph, 3},
                 {&kp_tuning::timing, 2},           {&kp_tuning::timing_stages, -1},   {&kp_tuning::timing_stages, 1 << 9},
                 {&kp_tuning::deterministic, 2},    {&kp_tuning::deterministic, -1},   {&kp_tuning::local_filter, 2},
-                {&kp_tuning::local_filter, -1}};
+                {&kp_tuning::local_filter, -1},    {&kp_tuning::plain, 2}};
     for (const Field &b : badt) {
         kp_tuning t;
         std::memset(&t, 0, sizeof t);

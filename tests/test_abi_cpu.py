@@ -30,9 +30,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(kp.kp_problem) == 48
     assert kp.kp_problem.points_dev.offset == 24 and kp.kp_problem.seed.offset == 40
-    assert ctypes.sizeof(kp.kp_tuning) == 36 and kp.kp_tuning.bound_codes.offset == 20
+    assert ctypes.sizeof(kp.kp_tuning) == 40 and kp.kp_tuning.bound_codes.offset == 20
     assert kp.kp_tuning.timing_stages.offset == 24 and kp.kp_tuning.deterministic.offset == 28
-    assert kp.kp_tuning.local_filter.offset == 32
+    assert kp.kp_tuning.local_filter.offset == 32 and kp.kp_tuning.plain.offset == 36
     assert ctypes.sizeof(kp.kp_stage_time) == 40
     assert ctypes.sizeof(kp.kp_iter_stats) == 80 and kp.kp_iter_stats.point_filter_fail.offset == 8
     assert kp.kp_iter_stats.closed.offset == 64 and kp.kp_iter_stats.row_test.offset == 72

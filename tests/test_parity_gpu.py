@@ -76,6 +76,31 @@ def test_row_test_in_point_filter(prec):
     assert on and sum(s["closed"] for s in on) > 0, [(s["iter"], s["closed"]) for s in st]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_plain_lloyd_mode(prec):
+    """kp_tuning.plain (the comparator): every iteration is a dense pass over
+    sums recomputed from all points; step-locked with the oracle."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    rng = np.random.default_rng(33)
+    X = datagen.gaussian_mixture(rng, 12_007, 24, 40)
+    C0 = datagen.kmeanspp(rng, X, 48, sample=4000)
+    _print_case("plain", prec=prec)
+    r = run_steplocked(X, C0, 5, prec, 8, tuning=kp_tuning(plain=1))
+    assert all(s["dense"] == 1 for s in r["stats"]) and len(r["stats"]) == 8
+
+
+def test_plain_lloyd_mode_batch():
+    from paper_1905_09345_amd.kp import kp_tuning
+    from parity import run_steplocked_batch
+    probs = []
+    for i, (n, d, k) in enumerate([(3_001, 16, 16), (5_003, 32, 64), (2_011, 8, 12)]):
+        rng = np.random.default_rng(70 + i)
+        X = datagen.gaussian_mixture(rng, n, d, k)
+        probs.append((X, datagen.kmeanspp(rng, X, k, sample=2000), int(np.ceil(k / 10)), "fp32"))
+    _print_case("plain-batch")
+    run_steplocked_batch(probs, 5, tuning=kp_tuning(plain=1))
+
+
 @pytest.mark.parametrize("case", ["c1", "c2", "groups1", "groups30", "ties"])
 def test_fp32_local_filter(case):
     """The FP32 form with the per-centroid local filter on: step-locked with
