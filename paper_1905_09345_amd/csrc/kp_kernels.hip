@@ -774,8 +774,11 @@ template <int DMAX>
 __device__ __forceinline__ float direct_d2(const float (&x)[DMAX], const float *__restrict__ c, int ldc)
 {
     // Blocks of up to 32 coordinates: every load of a block is issued before
-    // the first product (addresses past ldc are clamped into the row and their
-    // terms are exact zeros), so a row costs one memory latency per block.
+    // the first product, so a row costs one memory latency per block.  Pieces
+    // past ldc read the row's last piece (a clamped address) and are weighted
+    // by 0, making their terms exact zeros.  The loaded values are used with
+    // no condition: a use under a branch would let the compiler move each
+    // load into its own branch and wait for it there.
     constexpr int B = DMAX < 32 ? DMAX : 32;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
@@ -783,16 +786,13 @@ __device__ __forceinline__ float direct_d2(const float (&x)[DMAX], const float *
         if (i0 < ldc) {
             float4 cv[B / 4];
 #pragma unroll
-            for (int q = 0; q < B / 4; ++q) {
-                const int i = i0 + 4 * q;
-                cv[q] = *(const float4 *)(c + (i < ldc ? i : i0));
-            }
+            for (int q = 0; q < B / 4; ++q) cv[q] = *(const float4 *)(c + min(i0 + 4 * q, ldc - 4));
 #pragma unroll
             for (int q = 0; q < B / 4; ++q) {
                 const int i = i0 + 4 * q;
-                const bool in = i < ldc;
-                const float t0 = in ? x[i] - cv[q].x : 0.f, t1 = in ? x[i + 1] - cv[q].y : 0.f;
-                const float t2 = in ? x[i + 2] - cv[q].z : 0.f, t3 = in ? x[i + 3] - cv[q].w : 0.f;
+                const float w = i < ldc ? 1.f : 0.f;
+                const float t0 = (x[i] - cv[q].x) * w, t1 = (x[i + 1] - cv[q].y) * w;
+                const float t2 = (x[i + 2] - cv[q].z) * w, t3 = (x[i + 3] - cv[q].w) * w;
                 a0 = fmaf(t0, t0, a0);
                 a1 = fmaf(t1, t1, a1);
                 a2 = fmaf(t2, t2, a2);
