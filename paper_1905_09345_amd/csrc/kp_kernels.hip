@@ -1634,9 +1634,42 @@ __global__ __launch_bounds__(256) void kb_gfilter(const ProbDev *__restrict__ pr
 }
 
 // ================================================== distance kernels (phase 2)
+constexpr int TF_STAGE = 1024;   // floats of centroid rows staged per wave (4 KB)
+
+// Wave-local hand-off through LDS: the compiler keeps the accesses on either
+// side in order, and a wave's LDS operations complete in issue order.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copies n4 (1 <= n4 <= TF_STAGE / 4) 16-byte pieces from src into this
+// wave's LDS region dst, all lanes taking part.  Every load is issued before
+// the first store; lanes past n4 repeat the last piece (same address, same
+// value), so there is no branch between the loads.
+__device__ __forceinline__ void stage_rows(float *dst, const float *__restrict__ src, int n4, int lane)
+{
+    static_assert(TF_STAGE == 16 * WAVE, "four pieces per lane");
+    const float4 *s4 = (const float4 *)src;
+    float4 *d4 = (float4 *)dst;
+    const int i0 = min(lane, n4 - 1), i1 = min(lane + WAVE, n4 - 1), i2 = min(lane + 2 * WAVE, n4 - 1),
+              i3 = min(lane + 3 * WAVE, n4 - 1);
+    const float4 v0 = s4[i0], v1 = s4[i1], v2 = s4[i2], v3 = s4[i3];
+    wave_lds_sync();   // the previous rows have been read
+    d4[i0] = v0;
+    d4[i1] = v1;
+    d4[i2] = v2;
+    d4[i3] = v3;
+    wave_lds_sync();
+}
+
 template <int DMAX>
 __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, const int nblk_)
 {
+    static_assert(DMAX <= TF_STAGE / 8, "a staged batch holds at least eight rows");
+    __shared__ __align__(16) float crows[4][TF_STAGE];   // launches have at most four waves
     const int lane = lane_id();
     const int wpb = blockDim.x / WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // the tile and its visits are uniform
@@ -1644,6 +1677,8 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
     const float sdd = P.Sdud[1];
     const long long count = list_len(P, CTR_L1);
     const long long ntiles = (count + WAVE - 1) / WAVE;
+    float *cw = crows[wv];
+    const int mrow = TF_STAGE / P.ldc;   // rows per staged batch (ldc <= DMAX)
     unsigned long long n_dist = 0, n_moved = 0;
     for (long long tl = (long long)bid_ * wpb + wv; tl < ntiles; tl += (long long)nblk_ * wpb) {
         const long long idx = tl * WAVE + lane;
@@ -1680,13 +1715,17 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
         unsigned long long mn = 0ull;
         int gn = cnt > 0 ? vis_of(0, mn) : 0;
         float vn = (lf && cnt > 0 && ((mn >> lane) & 1ull)) ? lbrow[gn] : 0.f;
+        int s0n = P.gstart[gn], nsn = P.gsize[gn];   // the next visit's members, also loaded ahead
         for (int k = 0; k < cnt; ++k) {
             const int g = gn;
             const unsigned long long m = mn;
             const float vrow = vn;
+            const int s0 = s0n, ns = nsn;
             if (k + 1 < cnt) {
                 gn = vis_of(k + 1, mn);
                 vn = (lf && ((mn >> lane) & 1ull)) ? lbrow[gn] : 0.f;
+                s0n = P.gstart[gn];
+                nsn = P.gsize[gn];
             }
             const bool mine = (m >> lane) & 1ull;
             // Local filter (kp_tuning.local_filter): member j of g lies at
@@ -1699,23 +1738,28 @@ __device__ __forceinline__ void b_tile_f32(const ProbDev &P, const int bid_, con
             const float lbn = (mine && lf) ? lb_now(vrow, P.Sgu[g]) : 0.f;
             Best3 gb = {KP_INF, -1, KP_INF};
             float lk = KP_INF;
-            const int s0 = P.gstart[g], ns = P.gsize[g];
             int ncomp = 0;
-            for (int rr = 0; rr < ns; ++rr) {
-                const int j = s0 + rr;
-                const float L = lf ? f_dn(lbn + P.slk[j]) : 0.f;
-                if (lf && __ballot(mine && !(j != a && L > ubt)) == 0ull) {
-                    lk = fminf(lk, L);
-                    continue;
-                }
-                ++ncomp;
-                const float v = direct_d2<DMAX>(x, P.c32 + (size_t)j * P.ldc, P.ldc);
-                if (v < gb.m1) {
-                    gb.m2 = gb.m1;
-                    gb.m1 = v;
-                    gb.s1 = j;
-                } else {
-                    gb.m2 = fminf(gb.m2, v);
+            // the group's rows are contiguous: staged in LDS a batch at a time
+            // (one memory latency per batch), then read from there
+            for (int b0 = 0; b0 < ns; b0 += mrow) {
+                const int mb = min(mrow, ns - b0);
+                stage_rows(cw, P.c32 + (size_t)(s0 + b0) * P.ldc, mb * P.ldc / 4, lane);
+                for (int rr = 0; rr < mb; ++rr) {
+                    const int j = s0 + b0 + rr;
+                    const float L = lf ? f_dn(lbn + P.slk[j]) : 0.f;
+                    if (lf && __ballot(mine && !(j != a && L > ubt)) == 0ull) {
+                        lk = fminf(lk, L);
+                        continue;
+                    }
+                    ++ncomp;
+                    const float v = direct_d2<DMAX>(x, cw + rr * P.ldc, P.ldc);
+                    if (v < gb.m1) {
+                        gb.m2 = gb.m1;
+                        gb.m1 = v;
+                        gb.s1 = j;
+                    } else {
+                        gb.m2 = fminf(gb.m2, v);
+                    }
                 }
             }
             n_dist += (unsigned long long)__popcll(m) * (unsigned long long)ncomp;
