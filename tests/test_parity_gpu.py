@@ -129,6 +129,34 @@ def test_fp32_local_filter(case):
         assert sum(s["distances"] for s in st) < sum(s["pairs"] for s in st) * (C0.shape[0] / g)
 
 
+@pytest.mark.parametrize("case", ["d100_g2", "d24_g1_k100", "d100_g2_local_filter", "batch"])
+def test_fp32_groups_over_one_staged_batch(case):
+    """The FP32 tile kernel copies a visited group's member rows into LDS in
+    batches of 1024 floats (10 rows at d = 100, 42 at d = 24).  Groups larger
+    than one batch, a partial last batch, the local filter's skips across
+    batches and the batched launch stay step-locked with the oracle."""
+    from paper_1905_09345_amd.kp import kp_tuning
+    from parity import run_steplocked_batch
+    shapes = {"d100_g2": (6_007, 100, 64, 2), "d24_g1_k100": (8_009, 24, 100, 1),
+              "d100_g2_local_filter": (6_007, 100, 64, 2)}
+    tuning = kp_tuning(local_filter=1) if case.endswith("local_filter") else None
+    _print_case("fp32-staged", case=case)
+    if case == "batch":
+        probs = []
+        for i, (n, d, k, g) in enumerate([(4_001, 100, 64, 2), (3_001, 24, 100, 1), (2_003, 8, 40, 1)]):
+            rng = np.random.default_rng(90 + i)
+            X = datagen.gaussian_mixture(rng, n, d, k)
+            probs.append((X, datagen.kmeanspp(rng, X, k, sample=2000), g, "fp32"))
+        run_steplocked_batch(probs, 6)
+        return
+    n, d, k, g = shapes[case]
+    rng = np.random.default_rng(n + d)
+    X = datagen.gaussian_mixture(rng, n, d, k)
+    C0 = datagen.kmeanspp(rng, X, k, sample=4000)
+    r = run_steplocked(X, C0, g, "fp32", 8, tuning=tuning)
+    assert sum(s["distances"] for s in r["stats"] if not s["dense"]) > 0
+
+
 @pytest.mark.parametrize("d", [16, 32, 64])
 def test_bf16_small_dims(d):
     rng = np.random.default_rng(d)
